@@ -1,0 +1,196 @@
+"""FP64 CPU oracle for the client-side splat ray-tracing path (arXiv 2006.14726).
+
+TEST INFRASTRUCTURE ONLY: the tests, ``__graft_entry__.smoke()`` and the
+benchmark's CPU-baseline leg are the only users.  The product path never
+imports this package; it shares no code with the GPU library.
+
+Everything is computed in double precision by ``oracle.c`` (plain C, OpenMP
+over pixels), brute force: every ray against every sphere, hits sorted by
+(t0, id), composited in order.  This module only marshals arrays:
+
+* ``unproject``  Sec. 3.1, Eq. 1 (p = o + d t_i), footprint radius, compaction
+* ``render``     Sec. 3.1 / Fig. 2: spheres traced from a new camera,
+                 composited front to back with an alpha stop
+* ``grad``       analytic gradient of a per-pixel loss through ``render``
+* ``half_bits``  double -> binary16 with round-to-nearest-even
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+MODE_CONSTANT = 0
+MODE_SOFT = 1
+
+FLAG_GRAZE = 1
+FLAG_KNIFE = 2
+FLAG_MULTI_KNIFE = 4
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c with gcc into oracle/liboracle.so (no fast-math, no FMA contraction)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99",
+                               "-ffp-contract=off", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class _Cam(ctypes.Structure):
+    _fields_ = [("eye", ctypes.c_double * 3), ("forward", ctypes.c_double * 3),
+                ("right", ctypes.c_double * 3), ("up", ctypes.c_double * 3),
+                ("tan_half_fov_y", ctypes.c_double), ("width", ctypes.c_int32),
+                ("height", ctypes.c_int32)]
+
+
+def _cam(c) -> _Cam:
+    out = _Cam()
+    out.eye[:] = [float(v) for v in c.eye]
+    out.forward[:] = [float(v) for v in c.forward]
+    out.right[:] = [float(v) for v in c.right]
+    out.up[:] = [float(v) for v in c.up]
+    out.tan_half_fov_y = float(c.tan_half_fov_y)
+    out.width, out.height = int(c.width), int(c.height)
+    return out
+
+
+_lib = None
+_P = ctypes.c_void_p
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build(force=False)
+        lib = ctypes.CDLL(_LIB_PATH)
+        lib.orc_half_bits.argtypes = [ctypes.c_double]
+        lib.orc_half_bits.restype = ctypes.c_uint16
+        lib.orc_unproject.argtypes = [ctypes.POINTER(_Cam), _P, _P, ctypes.c_double, _P, _P, _P, _P]
+        lib.orc_unproject.restype = ctypes.c_int64
+        lib.orc_render.argtypes = [_P, ctypes.c_int64, ctypes.POINTER(_Cam), ctypes.c_double, ctypes.c_double,
+                                   ctypes.c_int, _P, ctypes.c_int64, _P, _P, _P, _P, _P, _P]
+        lib.orc_render.restype = ctypes.c_int
+        lib.orc_grad.argtypes = [_P, ctypes.c_int64, ctypes.POINTER(_Cam), ctypes.c_double, ctypes.c_double,
+                                 ctypes.c_int, _P, _P]
+        lib.orc_grad.restype = ctypes.c_int
+        lib.orc_sphere_test.argtypes = [_P, _P, _P, ctypes.c_double, ctypes.c_double, _P]
+        lib.orc_sphere_test.restype = ctypes.c_int
+        lib.orc_pixels_near.argtypes = [ctypes.POINTER(_Cam), _P, ctypes.c_double, _P, ctypes.c_int64]
+        lib.orc_pixels_near.restype = ctypes.c_int64
+        _lib = lib
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+def half_bits(values) -> np.ndarray:
+    """binary16 bit patterns of float64 values, round-to-nearest-even."""
+    v = np.asarray(values, dtype=np.float64).ravel()
+    lib = _load()
+    return np.array([lib.orc_half_bits(float(x)) for x in v], dtype=np.uint16)
+
+
+def unproject(cam, rgba: np.ndarray, depth: np.ndarray, radius_scale: float, half: bool):
+    """Eq. 1 unprojection of a premultiplied RGBA + depth image.
+
+    Returns (centre_radius float32 [N][4], colour [N][4] float16 or float32
+    straight RGBA, src_index uint32 [N]).
+    """
+    H, W = int(cam.height), int(cam.width)
+    rgba = np.ascontiguousarray(rgba, dtype=np.float32).reshape(H, W, 4)
+    depth = np.ascontiguousarray(depth, dtype=np.float32).reshape(H, W)
+    cap = H * W
+    cr = np.zeros((cap, 4), dtype=np.float32)
+    col32 = None if half else np.zeros((cap, 4), dtype=np.float32)
+    col16 = np.zeros((cap, 4), dtype=np.uint16) if half else None
+    idx = np.zeros(cap, dtype=np.uint32)
+    c = _cam(cam)
+    n = _load().orc_unproject(ctypes.byref(c), rgba.ctypes.data, depth.ctypes.data, float(radius_scale),
+                              cr.ctypes.data, _ptr(col32), _ptr(col16), idx.ctypes.data)
+    col = col16.view(np.float16) if half else col32
+    return cr[:n].copy(), col[:n].copy(), idx[:n].copy()
+
+
+def sphere_table(centre_radius: np.ndarray, colour: np.ndarray) -> np.ndarray:
+    """Exact widening of the stored sphere values to the oracle's [N][8] float64 table."""
+    cr = np.asarray(centre_radius).reshape(-1, 4).astype(np.float64)
+    col = np.asarray(colour).reshape(-1, 4).astype(np.float64)
+    return np.ascontiguousarray(np.concatenate([cr, col], axis=1))
+
+
+def render_table(table: np.ndarray, cam, alpha_stop: float = 0.99, t_max: float = np.inf,
+                 mode: int = MODE_CONSTANT, pixels=None):
+    """Brute-force render from an [N][8] float64 sphere table (cx cy cz r kr kg kb a)."""
+    table = np.ascontiguousarray(table, dtype=np.float64).reshape(-1, 8)
+    if pixels is None:
+        pix = None
+        npix = int(cam.width) * int(cam.height)
+    else:
+        pix = np.ascontiguousarray(pixels, dtype=np.int64).ravel()
+        npix = pix.size
+    out = np.zeros((npix, 4), dtype=np.float64)
+    alt = np.zeros((npix, 4), dtype=np.float64)
+    n = np.zeros(npix, dtype=np.int32)
+    nalt = np.zeros(npix, dtype=np.int32)
+    flags = np.zeros(npix, dtype=np.int32)
+    sig = np.zeros(npix, dtype=np.uint64)
+    c = _cam(cam)
+    rc = _load().orc_render(table.ctypes.data, table.shape[0], ctypes.byref(c), float(alpha_stop), float(t_max),
+                            int(mode), _ptr(pix), npix, out.ctypes.data, n.ctypes.data, flags.ctypes.data,
+                            alt.ctypes.data, nalt.ctypes.data, sig.ctypes.data)
+    if rc != 0:
+        raise RuntimeError(f"orc_render failed ({rc})")
+    return {"rgba": out, "n": n, "flags": flags, "alt_rgba": alt, "alt_n": nalt, "sig": sig}
+
+
+def render(centre_radius, colour, cam, alpha_stop: float = 0.99, t_max: float = np.inf,
+           mode: int = MODE_CONSTANT, pixels=None):
+    """Brute-force FP64 render of stored spheres (float32 centre/radius, float16/32 colour)."""
+    return render_table(sphere_table(centre_radius, colour), cam, alpha_stop, t_max, mode, pixels)
+
+
+def grad_table(table: np.ndarray, cam, grad_rgba: np.ndarray, alpha_stop: float = 0.99,
+               t_max: float = np.inf, mode: int = MODE_SOFT) -> np.ndarray:
+    """dL/d(cx cy cz r kr kg kb a) [N][8] for L = sum(grad_rgba * I)."""
+    table = np.ascontiguousarray(table, dtype=np.float64).reshape(-1, 8)
+    g = np.ascontiguousarray(grad_rgba, dtype=np.float64).reshape(-1, 4)
+    assert g.shape[0] == int(cam.width) * int(cam.height)
+    out = np.zeros_like(table)
+    c = _cam(cam)
+    rc = _load().orc_grad(table.ctypes.data, table.shape[0], ctypes.byref(c), float(alpha_stop), float(t_max),
+                          int(mode), g.ctypes.data, out.ctypes.data)
+    if rc != 0:
+        raise RuntimeError(f"orc_grad failed ({rc})")
+    return out
+
+
+def sphere_test(o, d, c, r: float, t_max: float = np.inf):
+    """One ray against one sphere: (hit, t0, q, disc, v[3], b)."""
+    o = np.ascontiguousarray(o, dtype=np.float64)
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    c = np.ascontiguousarray(c, dtype=np.float64)
+    out = np.zeros(7, dtype=np.float64)
+    hit = _load().orc_sphere_test(o.ctypes.data, d.ctypes.data, c.ctypes.data, float(r), float(t_max),
+                                  out.ctypes.data)
+    return bool(hit), out[0], out[1], out[2], out[3:6].copy(), out[6]
+
+
+def pixels_near(cam, centre, radius: float) -> np.ndarray:
+    """Row-major ids of pixels whose ray passes within `radius` of `centre` (in front of the eye)."""
+    c = _cam(cam)
+    ctr = np.ascontiguousarray(centre, dtype=np.float64)
+    cap = int(cam.width) * int(cam.height)
+    out = np.zeros(cap, dtype=np.int64)
+    n = _load().orc_pixels_near(ctypes.byref(c), ctr.ctypes.data, float(radius), out.ctypes.data, cap)
+    return out[:n].copy()

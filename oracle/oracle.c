@@ -1,0 +1,487 @@
+/*
+ * FP64 CPU oracle for the client-side splat ray-tracing path of
+ * "Augmenting Image Warping-Based Remote Volume Rendering with Ray Tracing"
+ * (Zellmann, arXiv 2006.14726).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path links, loads or
+ * calls this file; only the tests, the smoke check and the benchmark's CPU
+ * baseline do.  It shares no code with the GPU library.
+ *
+ * It is deliberately plain and slow: every ray is tested against every
+ * sphere, the hits are sorted, and they are composited one by one in double
+ * precision.  Functions:
+ *
+ *   orc_unproject   Sec. 3.1, Eq. 1: p = o + d t_i per pixel, a footprint
+ *                   radius, compaction of pixels without a sample.
+ *   orc_render      Sec. 3.1 / Fig. 2: the samples as coloured
+ *                   semi-transparent spheres, traced from a new camera,
+ *                   composited front to back, stopping at a given alpha.
+ *   orc_grad        gradient of a per-pixel loss through orc_render.
+ *   orc_pixels_near lists the pixels whose ray passes near a point.
+ *   orc_sphere_test one ray against one sphere (exposed for closed-form pins).
+ *   orc_half_bits   double -> IEEE binary16, round to nearest even.
+ *
+ * Readings of the paper (it specifies none of these):
+ *   - camera: pinhole, ray through pixel centre (x+1/2, y+1/2), row 0 at top,
+ *     d = normalize(F + sx R + sy U), sx = ((2x+1)/W - 1) tan(fov/2) W/H,
+ *     sy = (1 - (2y+1)/H) tan(fov/2);
+ *   - a source pixel holds a sample iff its depth t is finite, t > 0, A > 0;
+ *     radius = s * 2 t tan(fov/2) / H_src (s times the pixel footprint at t);
+ *     colour stored straight: k = clamp(C/A, 0, 1), alpha a = A;
+ *   - hit: with oc = c - o, b = oc.d, v = oc - b d, q = v.v, disc = r^2 - q,
+ *     sphere hit iff disc >= 0 and t0 = b - sqrt(disc) lies in (0, t_max);
+ *   - order: ascending (t0, sphere id);
+ *   - compositing, per hit: C += T alpha k, A += T alpha, T *= (1 - alpha),
+ *     n += 1; stop after a hit iff A >= alpha_stop; background 0;
+ *   - alpha = a (mode 0, constant, the paper's constant sample colour) or
+ *     alpha = a (1 - q/r^2)^2 (mode 1, soft, differentiable in r and c).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef struct {
+    double eye[3], forward[3], right[3], up[3];
+    double tan_half_fov_y;
+    int32_t width, height;
+} orc_camera;
+
+/* Pixel-centre ray of a pinhole camera. */
+static void orc_ray(const orc_camera *c, int64_t x, int64_t y, double d[3])
+{
+    double aspect = (double)c->width / (double)c->height;
+    double sx = ((2.0 * (double)x + 1.0) / c->width - 1.0) * c->tan_half_fov_y * aspect;
+    double sy = (1.0 - (2.0 * (double)y + 1.0) / c->height) * c->tan_half_fov_y;
+    double v[3];
+    for (int k = 0; k < 3; ++k) v[k] = c->forward[k] + sx * c->right[k] + sy * c->up[k];
+    double len = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    for (int k = 0; k < 3; ++k) d[k] = v[k] / len;
+}
+
+/* IEEE binary16 bits of v, rounded to nearest even (rint in the default mode). */
+uint16_t orc_half_bits(double v)
+{
+    uint16_t sign = signbit(v) ? 0x8000u : 0u;
+    double a = fabs(v);
+    if (isnan(v)) return 0x7e00u;
+    if (a == 0.0) return sign;
+    if (a >= 65520.0) return (uint16_t)(sign | 0x7c00u); /* rounds to infinity */
+    int e;
+    frexp(a, &e);          /* a = m 2^e, m in [0.5, 1) */
+    int E = e - 1;         /* a in [2^E, 2^(E+1)) */
+    if (E < -14) {         /* subnormal range: multiples of 2^-24 */
+        double q = rint(ldexp(a, 24));
+        return (uint16_t)(sign | (uint16_t)q); /* q == 1024 is the smallest normal */
+    }
+    double q = rint(ldexp(a, 10 - E)); /* in [1024, 2048] */
+    if (q == 2048.0) { q = 1024.0; E += 1; }
+    if (E > 15) return (uint16_t)(sign | 0x7c00u);
+    return (uint16_t)(sign | (uint16_t)((E + 15) << 10) | (uint16_t)(q - 1024.0));
+}
+
+/*
+ * Eq. 1 unprojection with stable compaction.  rgba: premultiplied float
+ * [H][W][4]; depth: float [H][W].  Outputs sample j (j < returned count):
+ * centre_radius[4j..4j+3] = (float)p, (float)r; colour straight RGBA rounded
+ * once from double, either as float (col_f32) or binary16 bits (col_f16);
+ * src_index[j] = row-major source pixel index.  Pixels are visited in
+ * row-major order, so samples keep the pixel order.
+ */
+int64_t orc_unproject(const orc_camera *cam, const float *rgba, const float *depth, double radius_scale,
+                      float *centre_radius, float *col_f32, uint16_t *col_f16, uint32_t *src_index)
+{
+    const int64_t W = cam->width, H = cam->height;
+    int64_t n = 0;
+    for (int64_t y = 0; y < H; ++y) {
+        for (int64_t x = 0; x < W; ++x) {
+            int64_t i = y * W + x;
+            double t = depth[i];
+            double A = rgba[4 * i + 3];
+            if (!(isfinite(t) && t > 0.0 && A > 0.0)) continue;
+            double d[3];
+            orc_ray(cam, x, y, d);
+            for (int k = 0; k < 3; ++k) centre_radius[4 * n + k] = (float)(cam->eye[k] + d[k] * t);
+            double footprint = 2.0 * t * cam->tan_half_fov_y / (double)H;
+            centre_radius[4 * n + 3] = (float)(radius_scale * footprint);
+            double col[4];
+            for (int k = 0; k < 3; ++k) {
+                double kc = (double)rgba[4 * i + k] / A;
+                col[k] = kc < 0.0 ? 0.0 : (kc > 1.0 ? 1.0 : kc);
+            }
+            col[3] = A;
+            for (int k = 0; k < 4; ++k) {
+                if (col_f32) col_f32[4 * n + k] = (float)col[k];
+                if (col_f16) col_f16[4 * n + k] = orc_half_bits(col[k]);
+            }
+            if (src_index) src_index[n] = (uint32_t)i;
+            ++n;
+        }
+    }
+    return n;
+}
+
+/* One ray-sphere candidate. */
+typedef struct {
+    double t0;   /* entry distance */
+    double q;    /* squared distance from ray to centre */
+    double v[3]; /* offset from the closest ray point to the centre */
+    int64_t id;
+} orc_hit;
+
+static int orc_hit_cmp(const void *pa, const void *pb)
+{
+    const orc_hit *a = (const orc_hit *)pa, *b = (const orc_hit *)pb;
+    if (a->t0 < b->t0) return -1;
+    if (a->t0 > b->t0) return 1;
+    return (a->id > b->id) - (a->id < b->id);
+}
+
+/* Sphere table: [N][8] doubles = cx, cy, cz, r, k_r, k_g, k_b, a. */
+#define SPH(j, f) (sph[8 * (j) + (f)])
+
+static double orc_alpha(const double *sph, const orc_hit *h, int mode)
+{
+    double a = SPH(h->id, 7);
+    if (mode == 0) return a;
+    double r = SPH(h->id, 3);
+    double u = h->q / (r * r);
+    return a * (1.0 - u) * (1.0 - u);
+}
+
+/* Test every sphere; returns the number of hits (sorted) and flags grazing candidates. */
+typedef struct {
+    orc_hit *hits;
+    int64_t nhits, cap_hits;
+    double *graze_t; /* approximate position along the ray of grazing spheres */
+    double *graze_r;
+    int64_t ngraze, cap_graze;
+    orc_hit *scratch; /* same capacity as hits */
+    double *Ti, *al;  /* same capacity as hits */
+    int oom;
+} orc_ray_hits;
+
+static void orc_rh_init(orc_ray_hits *rh)
+{
+    memset(rh, 0, sizeof(*rh));
+}
+
+static void orc_rh_free(orc_ray_hits *rh)
+{
+    free(rh->hits);
+    free(rh->graze_t);
+    free(rh->graze_r);
+    free(rh->scratch);
+    free(rh->Ti);
+    free(rh->al);
+    memset(rh, 0, sizeof(*rh));
+}
+
+static int orc_rh_grow_hits(orc_ray_hits *rh)
+{
+    int64_t cap = rh->cap_hits ? 2 * rh->cap_hits : 256;
+    orc_hit *h = (orc_hit *)realloc(rh->hits, sizeof(orc_hit) * (size_t)cap);
+    orc_hit *s = h ? (orc_hit *)realloc(rh->scratch, sizeof(orc_hit) * (size_t)cap) : NULL;
+    if (h) rh->hits = h;
+    if (s) rh->scratch = s;
+    double *t = s ? (double *)realloc(rh->Ti, sizeof(double) * (size_t)cap) : NULL;
+    if (t) rh->Ti = t;
+    double *a = t ? (double *)realloc(rh->al, sizeof(double) * (size_t)cap) : NULL;
+    if (a) rh->al = a;
+    if (!a) { rh->oom = 1; return 1; }
+    rh->cap_hits = cap;
+    return 0;
+}
+
+static int orc_rh_grow_graze(orc_ray_hits *rh)
+{
+    int64_t cap = rh->cap_graze ? 2 * rh->cap_graze : 64;
+    double *t = (double *)realloc(rh->graze_t, sizeof(double) * (size_t)cap);
+    double *r = t ? (double *)realloc(rh->graze_r, sizeof(double) * (size_t)cap) : NULL;
+    if (t) rh->graze_t = t;
+    if (r) rh->graze_r = r;
+    if (!r) { rh->oom = 1; return 1; }
+    rh->cap_graze = cap;
+    return 0;
+}
+
+/*
+ * Ray-sphere test in the numerically robust form (the perpendicular offset v
+ * is formed before squaring, instead of b^2 - |oc|^2 + r^2, which cancels).
+ * out[0] = t0, out[1] = q, out[2] = disc, out[3..5] = v, out[6] = b.
+ * Returns 1 iff disc >= 0 and 0 < t0 < t_max.
+ */
+int orc_sphere_test(const double o[3], const double d[3], const double c[3], double r, double t_max,
+                    double out[7])
+{
+    double oc[3] = {c[0] - o[0], c[1] - o[1], c[2] - o[2]};
+    double b = oc[0] * d[0] + oc[1] * d[1] + oc[2] * d[2];
+    double v[3] = {oc[0] - b * d[0], oc[1] - b * d[1], oc[2] - b * d[2]};
+    double q = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+    double disc = r * r - q;
+    double t0 = disc >= 0.0 ? b - sqrt(disc) : NAN;
+    out[0] = t0;
+    out[1] = q;
+    out[2] = disc;
+    out[3] = v[0];
+    out[4] = v[1];
+    out[5] = v[2];
+    out[6] = b;
+    return disc >= 0.0 && t0 > 0.0 && t0 < t_max;
+}
+
+static void orc_collect(const double *sph, int64_t nsph, const double o[3], const double d[3], double t_max,
+                        orc_ray_hits *rh)
+{
+    rh->nhits = 0;
+    rh->ngraze = 0;
+    for (int64_t j = 0; j < nsph; ++j) {
+        double res[7];
+        double r = SPH(j, 3);
+        int hit = orc_sphere_test(o, d, &SPH(j, 0), r, t_max, res);
+        if (fabs(res[2]) <= 1e-6 * r * r) {
+            if (rh->ngraze == rh->cap_graze && orc_rh_grow_graze(rh)) return;
+            rh->graze_t[rh->ngraze] = res[6];
+            rh->graze_r[rh->ngraze] = r;
+            rh->ngraze++;
+        }
+        if (!hit) continue;
+        if (rh->nhits == rh->cap_hits && orc_rh_grow_hits(rh)) return;
+        orc_hit *h = &rh->hits[rh->nhits++];
+        h->t0 = res[0];
+        h->q = res[1];
+        h->v[0] = res[3];
+        h->v[1] = res[4];
+        h->v[2] = res[5];
+        h->id = j;
+    }
+    qsort(rh->hits, (size_t)rh->nhits, sizeof(orc_hit), orc_hit_cmp);
+}
+
+/*
+ * Composite a sorted hit list.  force_at >= 0 flips the decision taken at
+ * knife-edge number force_at (0 = the first one met): a stop decision with
+ * |A - alpha_stop| <= 1e-5 is reversed, a pair of consecutive hits with
+ * 0 < |dt| <= 1e-12 t is swapped.  Returns the number of knife-edges met.
+ */
+static int orc_composite(const double *sph, const orc_hit *hits_in, int64_t nh, int mode, double alpha_stop,
+                         int force_at, orc_hit *scratch, double out[4], int64_t *out_n, double *t_last)
+{
+    memcpy(scratch, hits_in, sizeof(orc_hit) * (size_t)nh);
+    double C[3] = {0, 0, 0}, A = 0.0, T = 1.0;
+    int64_t n = 0;
+    int knives = 0;
+    *t_last = -INFINITY;
+    for (int64_t i = 0; i < nh; ++i) {
+        if (i + 1 < nh) {
+            double dt = scratch[i + 1].t0 - scratch[i].t0;
+            if (dt != 0.0 && fabs(dt) <= 1e-12 * fabs(scratch[i].t0)) {
+                if (knives == force_at) {
+                    orc_hit tmp = scratch[i];
+                    scratch[i] = scratch[i + 1];
+                    scratch[i + 1] = tmp;
+                }
+                knives++;
+            }
+        }
+        const orc_hit *h = &scratch[i];
+        double al = orc_alpha(sph, h, mode);
+        for (int k = 0; k < 3; ++k) C[k] += T * al * SPH(h->id, 4 + k);
+        A += T * al;
+        T *= (1.0 - al);
+        n++;
+        *t_last = h->t0;
+        int stop = A >= alpha_stop;
+        if (fabs(A - alpha_stop) <= 1e-5) {
+            if (knives == force_at) stop = !stop;
+            knives++;
+        }
+        if (stop) break;
+    }
+    out[0] = C[0];
+    out[1] = C[1];
+    out[2] = C[2];
+    out[3] = A;
+    *out_n = n;
+    return knives;
+}
+
+/*
+ * Brute-force render of the pixels listed in `pix` (row-major ids; NULL means
+ * all W*H pixels in order).  Per output pixel: out_rgba[4], out_n, flags:
+ *   bit 0: a grazing sphere (|disc| <= 1e-6 r^2) lies before the end of the
+ *          composited range (exempt from the comparison);
+ *   bit 1: exactly one knife-edge; alt_rgba / alt_n hold the other branch;
+ *   bit 2: more than one knife-edge (exempt).
+ * out_sig (nullable) receives a hash of the ordered composited sphere ids.
+ * Returns 0, 1 on bad arguments, 2 when out of memory.
+ */
+int orc_render(const double *sph, int64_t nsph, const orc_camera *cam, double alpha_stop, double t_max, int mode,
+               const int64_t *pix, int64_t npix, double *out_rgba, int32_t *out_n, int32_t *flags,
+               double *alt_rgba, int32_t *alt_n, uint64_t *out_sig)
+{
+    if (!sph && nsph > 0) return 1;
+    if (!cam || !out_rgba || !out_n || !flags || !alt_rgba || !alt_n) return 1;
+    const int64_t W = cam->width;
+    if (!pix) npix = (int64_t)cam->width * cam->height;
+    int err = 0;
+#pragma omp parallel
+    {
+        orc_ray_hits rh;
+        orc_rh_init(&rh);
+        orc_rh_grow_hits(&rh);
+        orc_rh_grow_graze(&rh);
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t p = 0; p < npix; ++p) {
+            if (rh.oom) continue;
+            int64_t id = pix ? pix[p] : p;
+            double d[3];
+            orc_ray(cam, id % W, id / W, d);
+            orc_collect(sph, nsph, cam->eye, d, t_max, &rh);
+            if (rh.oom) continue;
+            double rgba[4], t_last;
+            int64_t n;
+            int knives = orc_composite(sph, rh.hits, rh.nhits, mode, alpha_stop, -1, rh.scratch, rgba, &n, &t_last);
+            int32_t f = 0;
+            int stopped = n < rh.nhits || (n > 0 && rgba[3] >= alpha_stop);
+            for (int64_t g = 0; g < rh.ngraze; ++g) {
+                double tb = rh.graze_t[g], rr = rh.graze_r[g];
+                if (tb + rr <= 0.0 || tb - 1e-3 * rr >= t_max) continue; /* outside (0, t_max) */
+                if (!stopped || tb - 1e-3 * rr <= t_last) f |= 1;
+            }
+            double alt[4] = {rgba[0], rgba[1], rgba[2], rgba[3]};
+            int64_t nalt = n;
+            if (knives == 1) {
+                double t2;
+                int k2 = orc_composite(sph, rh.hits, rh.nhits, mode, alpha_stop, 0, rh.scratch, alt, &nalt, &t2);
+                f |= (k2 == 1) ? 2 : 4;
+            } else if (knives > 1) {
+                f |= 4;
+            }
+            for (int k = 0; k < 4; ++k) {
+                out_rgba[4 * p + k] = rgba[k];
+                alt_rgba[4 * p + k] = alt[k];
+            }
+            out_n[p] = (int32_t)n;
+            alt_n[p] = (int32_t)nalt;
+            flags[p] = f;
+            if (out_sig) {
+                /* FNV-1a over the composited ids, in order */
+                uint64_t hsh = 1469598103934665603ull;
+                for (int64_t i = 0; i < n; ++i) {
+                    hsh ^= (uint64_t)rh.hits[i].id;
+                    hsh *= 1099511628211ull;
+                }
+                out_sig[p] = hsh ^ (uint64_t)n;
+            }
+        }
+        if (rh.oom) {
+#pragma omp atomic write
+            err = 2;
+        }
+        orc_rh_free(&rh);
+    }
+    return err;
+}
+
+/*
+ * Gradient of L = sum_p sum_ch g[p][ch] * I[p][ch] (a linearised loss: pass
+ * g = dL/dI of the real loss) with respect to every sphere parameter.
+ * out_grad [N][8] (zeroed here) = dL/d(cx, cy, cz, r, k_r, k_g, k_b, a).
+ *
+ * Per pixel with ordered composited hits i = 1..n (T_1 = 1,
+ * T_{i+1} = T_i (1 - alpha_i)), w_i = k_i . g_C + g_A:
+ *   dL/dk_i     = T_i alpha_i g_C
+ *   dL/dalpha_i = T_i (w_i - R_i),  R_n = 0,
+ *                 R_{i-1} = alpha_i w_i + (1 - alpha_i) R_i
+ * (R_i is the remainder behind hit i composited from full transmittance).
+ * Chain rule through alpha = a (1-u)^2, u = q / r^2, q = |v|^2 (soft mode):
+ *   dalpha/da = (1-u)^2, dalpha/dr = 4 a (1-u) q / r^3,
+ *   dalpha/dc = -4 a (1-u) v / r^2;
+ * constant mode: dalpha/da = 1, no radius or centre gradient.  The order of
+ * the hits is piecewise constant and carries no gradient.
+ */
+int orc_grad(const double *sph, int64_t nsph, const orc_camera *cam, double alpha_stop, double t_max, int mode,
+             const double *grad_rgba, double *out_grad)
+{
+    if (!cam || !grad_rgba || !out_grad || (!sph && nsph > 0)) return 1;
+    const int64_t W = cam->width, P = (int64_t)cam->width * cam->height;
+    memset(out_grad, 0, sizeof(double) * 8 * (size_t)nsph);
+    int err = 0;
+#pragma omp parallel
+    {
+        orc_ray_hits rh;
+        orc_rh_init(&rh);
+        orc_rh_grow_hits(&rh);
+        orc_rh_grow_graze(&rh);
+        double *acc = (double *)calloc(8 * (size_t)(nsph > 0 ? nsph : 1), sizeof(double));
+        if (!acc) rh.oom = 1;
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t p = 0; p < P; ++p) {
+            if (rh.oom) continue;
+            const double *g = grad_rgba + 4 * p;
+            double d[3];
+            orc_ray(cam, p % W, p / W, d);
+            orc_collect(sph, nsph, cam->eye, d, t_max, &rh);
+            if (rh.oom) continue;
+            double rgba[4], t_last;
+            int64_t n;
+            orc_composite(sph, rh.hits, rh.nhits, mode, alpha_stop, -1, rh.scratch, rgba, &n, &t_last);
+            double T = 1.0;
+            for (int64_t i = 0; i < n; ++i) {
+                rh.Ti[i] = T;
+                rh.al[i] = orc_alpha(sph, &rh.hits[i], mode);
+                T *= (1.0 - rh.al[i]);
+            }
+            double R = 0.0;
+            for (int64_t i = n - 1; i >= 0; --i) {
+                const orc_hit *h = &rh.hits[i];
+                int64_t j = h->id;
+                double al = rh.al[i], Ti = rh.Ti[i];
+                double w = SPH(j, 4) * g[0] + SPH(j, 5) * g[1] + SPH(j, 6) * g[2] + g[3];
+                double dal = Ti * (w - R);
+                for (int k = 0; k < 3; ++k) acc[8 * j + 4 + k] += Ti * al * g[k];
+                if (mode == 0) {
+                    acc[8 * j + 7] += dal;
+                } else {
+                    double a = SPH(j, 7), r = SPH(j, 3);
+                    double u = h->q / (r * r);
+                    acc[8 * j + 7] += dal * (1.0 - u) * (1.0 - u);
+                    acc[8 * j + 3] += dal * 4.0 * a * (1.0 - u) * h->q / (r * r * r);
+                    for (int k = 0; k < 3; ++k) acc[8 * j + k] += dal * (-4.0 * a * (1.0 - u) * h->v[k] / (r * r));
+                }
+                R = al * w + (1.0 - al) * R;
+            }
+        }
+        if (rh.oom) {
+#pragma omp atomic write
+            err = 2;
+        } else {
+#pragma omp critical
+            for (size_t k = 0; k < 8 * (size_t)nsph; ++k) out_grad[k] += acc[k];
+        }
+        free(acc);
+        orc_rh_free(&rh);
+    }
+    return err;
+}
+
+/* Row-major ids of the pixels whose ray passes within `radius` of `centre`, in front of the eye. */
+int64_t orc_pixels_near(const orc_camera *cam, const double centre[3], double radius, int64_t *out, int64_t cap)
+{
+    const int64_t W = cam->width, P = (int64_t)cam->width * cam->height;
+    int64_t n = 0;
+    for (int64_t p = 0; p < P; ++p) {
+        double d[3];
+        orc_ray(cam, p % W, p / W, d);
+        double oc[3] = {centre[0] - cam->eye[0], centre[1] - cam->eye[1], centre[2] - cam->eye[2]};
+        double b = oc[0] * d[0] + oc[1] * d[1] + oc[2] * d[2];
+        double v[3] = {oc[0] - b * d[0], oc[1] - b * d[1], oc[2] - b * d[2]};
+        double q = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+        if (q <= radius * radius && b + radius > 0.0) {
+            if (n < cap) out[n] = p;
+            n++;
+        }
+    }
+    return n;
+}
