@@ -1,0 +1,224 @@
+/*
+ * splat.h -- C ABI of the MI355X (gfx950) splat ray tracer.
+ *
+ * The client side of image-warping remote volume rendering with ray tracing
+ * (Zellmann, arXiv 2006.14726, Sec. 3.1 and Fig. 2): the samples of a 2.5D
+ * RGBA + depth image become coloured semi-transparent spheres, a linear BVH
+ * is built over them, and the view from a new camera is ray traced through
+ * them with front-to-back compositing.
+ *
+ * Conventions shared by every entry point
+ *   - Every pointer named "device" is device memory on the current HIP
+ *     device; the caller allocates and owns it.  The library allocates
+ *     nothing and keeps no per-call state.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Every call only
+ *     enqueues work on it; none synchronises.  The sphere count stays in
+ *     device memory, so the calls can be captured in a HIP graph.
+ *   - Return value 0 on success, else one of the SPLAT_E* codes; all argument
+ *     checks happen on the host before anything is enqueued, and
+ *     splat_last_error() gives a thread-local message for the last failure.
+ */
+#ifndef SPLAT_H
+#define SPLAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SPLAT_OK 0
+#define SPLAT_EINVAL 1        /* null pointer, bad size, non-orthonormal camera, bad option */
+#define SPLAT_ENOSPC 2        /* capacity or workspace too small */
+#define SPLAT_ENODEV 3        /* no gfx950 device, or HIP initialisation failed */
+#define SPLAT_EHIP 4          /* a HIP launch or runtime call failed */
+#define SPLAT_EUNSUPPORTED 5  /* unknown dtype, mode or tile shape */
+
+#define SPLAT_F32 0           /* sphere colour stored as float4 */
+#define SPLAT_F16 1           /* sphere colour stored as IEEE half4 */
+
+#define SPLAT_ALPHA_CONSTANT 0 /* alpha = a: the paper's constant sample colour */
+#define SPLAT_ALPHA_SOFT 1     /* alpha = a (1 - q/r^2)^2, q = squared ray-centre distance */
+
+#define SPLAT_OP_UNPROJECT 0
+#define SPLAT_OP_BUILD 1
+#define SPLAT_OP_TRACE 2
+#define SPLAT_OP_BACKWARD 3
+#define SPLAT_OP_BATCHED 4
+
+/*
+ * Pinhole camera, all in double.  forward/right/up must be orthonormal
+ * (checked to 1e-9).  Pixel (x, y), row 0 at the top, looks along
+ * normalize(forward + sx right + sy up) with
+ *   sx = ((2x+1)/width - 1) tan_half_fov_y width/height,
+ *   sy = (1 - (2y+1)/height) tan_half_fov_y.
+ * The paper ships the camera with the buffers (Sec. 3.2).
+ */
+typedef struct splat_camera {
+    double eye[3];
+    double forward[3];
+    double right[3];
+    double up[3];
+    double tan_half_fov_y;
+    int32_t width;
+    int32_t height;
+} splat_camera;
+
+/*
+ * Sphere set (Sec. 3.1: samples reinterpreted as semi-transparent spheres),
+ * structure of arrays, `capacity` slots, the first *count used.
+ *   centre_radius  device float4[capacity]: x, y, z, r (object space)
+ *   rgba           device half4 or float4 [capacity]: straight colour k, alpha a
+ *   rgba_dtype     SPLAT_F16 or SPLAT_F32
+ *   src_index      device uint32[capacity]: source pixel of each sphere (may be NULL)
+ *   count          device uint32 scalar: N
+ * Sphere ids are slot indices; they break ties between equal hit distances.
+ */
+typedef struct splat_spheres {
+    float *centre_radius;
+    void *rgba;
+    int32_t rgba_dtype;
+    int32_t reserved;
+    uint32_t *src_index;
+    uint32_t *count;
+    uint32_t capacity;
+} splat_spheres;
+
+/*
+ * Linear BVH (Sec. 3.1, the LBVH of the paper) over at most `capacity`
+ * spheres, in one device allocation of splat_bvh_bytes(capacity) bytes,
+ * 256-byte aligned.  Opaque layout; valid after splat_build_bvh.
+ */
+typedef struct splat_bvh {
+    void *mem;
+    uint32_t capacity;
+} splat_bvh;
+
+/*
+ * Trace options.
+ *   alpha_stop  stop a ray once its accumulated alpha reaches this value
+ *               (0.99 by default; 0 = the paper's first-hit query; > 1 never)
+ *   t_max       hits must satisfy 0 < t0 < t_max (INFINITY for none)
+ *   mode        SPLAT_ALPHA_CONSTANT or SPLAT_ALPHA_SOFT
+ *   kbuf        hits gathered per traversal pass: 1, 2, 4, 8 or 16 (0 = 8);
+ *               the result does not depend on it
+ *   tile_w/h    pixels per 64-lane wavefront: 8x8, 16x4 or 32x2 (0 = 8x8);
+ *               the result does not depend on it
+ */
+typedef struct splat_trace_opts {
+    float alpha_stop;
+    int32_t mode;
+    double t_max;
+    int32_t kbuf;
+    int32_t tile_w;
+    int32_t tile_h;
+    int32_t reserved;
+} splat_trace_opts;
+
+/* Per-sphere gradients, device float arrays indexed by sphere id; accumulated into (+=). */
+typedef struct splat_grads {
+    float *d_rgb;     /* [capacity][3] */
+    float *d_alpha;   /* [capacity] */
+    float *d_radius;  /* [capacity] */
+    float *d_centre;  /* [capacity][3] */
+} splat_grads;
+
+/*
+ * One job of a batched trace: one target view of one frame's sphere set.
+ * All pointers are device pointers, as for splat_trace.
+ */
+typedef struct splat_batch_job {
+    const void *bvh_mem;           /* splat_bvh.mem of the frame */
+    const float *centre_radius;    /* spheres of the frame */
+    const void *rgba;
+    int32_t rgba_dtype;
+    uint32_t bvh_capacity;         /* splat_bvh.capacity of the frame */
+    splat_camera camera;           /* target view */
+    float *out_rgba;               /* float4 [height][width] */
+    uint32_t *out_hits;            /* uint32 [height][width] or NULL */
+} splat_batch_job;
+
+/* Bytes of workspace that `op` (SPLAT_OP_*) needs for the given capacity and image size. */
+size_t splat_workspace_bytes(int32_t op, uint32_t capacity, int32_t width, int32_t height);
+
+/* Bytes of the BVH allocation for `capacity` spheres. */
+size_t splat_bvh_bytes(uint32_t capacity);
+
+/*
+ * Unprojection (Sec. 3.1, Eq. 1).  For every source pixel whose depth t is
+ * finite and positive and whose alpha A is positive: centre p = o + d t in
+ * double (d the unit pixel-centre ray of `src`), radius
+ * r = radius_scale * 2 t tan_half_fov_y / height (the pixel footprint at t),
+ * colour k = clamp(C/A, 0, 1), a = A; each rounded once to float (half for
+ * SPLAT_F16 colours).  Pixels without a sample are compacted away; the
+ * spheres keep row-major pixel order (src_index ascending).
+ *   rgba_premul  device float [height][width][4], premultiplied
+ *   depth        device float [height][width], ray parameter along the unit ray
+ *   out          out->capacity >= width*height (SPLAT_ENOSPC otherwise)
+ *   ws           device, >= splat_workspace_bytes(SPLAT_OP_UNPROJECT, 0, width, height)
+ */
+int splat_unproject(const splat_camera *src, const float *rgba_premul, const float *depth, float radius_scale,
+                    const splat_spheres *out, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * LBVH build (Sec. 3.1): scene bounds, 30-bit Morton codes of the centres,
+ * stable LDS radix sort of (code, id), Karras radix-tree hierarchy, and a
+ * bottom-up refit of boxes rounded outward to float.  refit_only != 0 keeps
+ * the hierarchy of the previous build over the same centres and recomputes
+ * the boxes and the per-leaf data (radius or colour changes).
+ *   ws  device, >= splat_workspace_bytes(SPLAT_OP_BUILD, bvh->capacity, 0, 0)
+ *   sph->capacity <= bvh->capacity (SPLAT_ENOSPC otherwise)
+ */
+int splat_build_bvh(const splat_spheres *sph, const splat_bvh *bvh, int32_t refit_only, void *ws, size_t ws_bytes,
+                    void *stream);
+
+/*
+ * Trace and composite (Sec. 3.1, Fig. 2).  For every pixel of `cam`: all
+ * spheres hit by its ray (disc >= 0, 0 < t0 < t_max) in ascending
+ * (t0, sphere id), composited front to back, C += T alpha k, A += T alpha,
+ * T *= 1 - alpha, stopping after the hit at which A >= alpha_stop.  Ray,
+ * sphere test and ordering are double precision; compositing is float.
+ *   out_rgba  device float4 [height][width] (C, A), background 0
+ *   out_hits  device uint32 [height][width] composited hit count, or NULL
+ */
+int splat_trace(const splat_bvh *bvh, const splat_spheres *sph, const splat_camera *cam, const splat_trace_opts *opts,
+                float *out_rgba, uint32_t *out_hits, void *stream);
+
+/*
+ * Backward of splat_trace: given dL/d(out_rgba), accumulates dL/dk, dL/da,
+ * dL/dr and dL/dc of every sphere into `grads` (+=; zero them first).  The
+ * ordered hits are recomputed by a second traversal, not stored.  Radius
+ * and centre gradients are zero in SPLAT_ALPHA_CONSTANT mode.
+ *   out_rgba   device float4 [height][width]: the forward output of the same call
+ *   grad_rgba  device float4 [height][width]
+ */
+int splat_trace_backward(const splat_bvh *bvh, const splat_spheres *sph, const splat_camera *cam,
+                         const splat_trace_opts *opts, const float *out_rgba, const float *grad_rgba,
+                         const splat_grads *grads, void *stream);
+
+/*
+ * Batched trace: every job of `jobs` (device array of n_jobs splat_batch_job)
+ * in ONE persistent launch; waves take tiles from an atomic work counter.
+ * Each job's output equals splat_trace's bit for bit.
+ *   ws          device, >= splat_workspace_bytes(SPLAT_OP_BATCHED, n_jobs, 0, 0)
+ *   total_tiles sum over jobs of ceil(w / tile_w) * ceil(h / tile_h)
+ *   max_waves   resident waves to launch (0 = one per SIMD slot of the device)
+ * The host passes per-job tile offsets through `tile_offsets` (device
+ * uint32[n_jobs + 1], exclusive prefix of tiles per job).
+ */
+int splat_trace_batched(const splat_batch_job *jobs, const uint32_t *tile_offsets, int32_t n_jobs,
+                        uint32_t total_tiles, const splat_trace_opts *opts, int32_t max_waves, void *ws,
+                        size_t ws_bytes, void *stream);
+
+/* Thread-local text for the last non-zero status. */
+const char *splat_last_error(void);
+
+/* ABI version (major * 100 + minor). */
+int splat_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPLAT_H */

@@ -1,0 +1,256 @@
+// C ABI of the splat library: argument checks on the host, then launches.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+
+#include "common.h"
+#include "kernels.h"
+
+using namespace splat;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+// Device check, cached per device id: gfx950 only.
+int check_device()
+{
+    static std::mutex mu;
+    static int state[64] = {0};  // 0 unknown, 1 ok, 2 wrong arch
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
+        return fail(SPLAT_ENODEV, "no HIP device available");
+    std::lock_guard<std::mutex> lock(mu);
+    if (state[dev] == 0) {
+        hipDeviceProp_t p;
+        if (hipGetDeviceProperties(&p, dev) != hipSuccess) return fail(SPLAT_ENODEV, "hipGetDeviceProperties failed");
+        state[dev] = std::strncmp(p.gcnArchName, "gfx950", 6) == 0 ? 1 : 2;
+        if (state[dev] == 2) {
+            snprintf(g_err, sizeof g_err, "device %d is %s, this library is built for gfx950", dev, p.gcnArchName);
+            return SPLAT_ENODEV;
+        }
+    }
+    return state[dev] == 1 ? SPLAT_OK : fail(SPLAT_ENODEV, "device %d is not gfx950", dev);
+}
+
+int check_camera(const splat_camera *c, const char *what)
+{
+    if (!c) return fail(SPLAT_EINVAL, "%s camera is NULL", what);
+    if (c->width <= 0 || c->height <= 0 || (int64_t)c->width * c->height > (1ll << 31))
+        return fail(SPLAT_EINVAL, "%s camera size %dx%d out of range", what, c->width, c->height);
+    if (!(std::isfinite(c->tan_half_fov_y) && c->tan_half_fov_y > 0))
+        return fail(SPLAT_EINVAL, "%s camera tan_half_fov_y must be finite and positive", what);
+    const double *v[3] = {c->forward, c->right, c->up};
+    for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(c->eye[k])) return fail(SPLAT_EINVAL, "%s camera eye is not finite", what);
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            const double dot = v[i][0] * v[j][0] + v[i][1] * v[j][1] + v[i][2] * v[j][2];
+            if (!(std::fabs(dot - (i == j ? 1.0 : 0.0)) <= 1e-9))
+                return fail(SPLAT_EINVAL, "%s camera basis is not orthonormal", what);
+        }
+    return SPLAT_OK;
+}
+
+int check_spheres(const splat_spheres *s, bool need_colour)
+{
+    if (!s) return fail(SPLAT_EINVAL, "spheres is NULL");
+    if (!s->centre_radius || !s->count) return fail(SPLAT_EINVAL, "spheres centre_radius/count is NULL");
+    if (need_colour && !s->rgba) return fail(SPLAT_EINVAL, "spheres rgba is NULL");
+    if (s->rgba_dtype != SPLAT_F16 && s->rgba_dtype != SPLAT_F32)
+        return fail(SPLAT_EUNSUPPORTED, "unknown colour dtype %d", s->rgba_dtype);
+    if (s->capacity == 0 || s->capacity > 0x7fffffffu) return fail(SPLAT_EINVAL, "sphere capacity out of range");
+    return SPLAT_OK;
+}
+
+int check_bvh(const splat_bvh *b)
+{
+    if (!b || !b->mem) return fail(SPLAT_EINVAL, "bvh or bvh->mem is NULL");
+    if (reinterpret_cast<uintptr_t>(b->mem) % 256) return fail(SPLAT_EINVAL, "bvh->mem must be 256-byte aligned");
+    if (b->capacity == 0 || b->capacity > 0x7fffffffu) return fail(SPLAT_EINVAL, "bvh capacity out of range");
+    return SPLAT_OK;
+}
+
+int resolve_opts(const splat_trace_opts *o, splat_trace_opts *out)
+{
+    if (!o) return fail(SPLAT_EINVAL, "opts is NULL");
+    *out = *o;
+    if (out->kbuf == 0) out->kbuf = 8;
+    if (out->kbuf != 1 && out->kbuf != 2 && out->kbuf != 4 && out->kbuf != 8 && out->kbuf != 16)
+        return fail(SPLAT_EUNSUPPORTED, "kbuf %d not in {1,2,4,8,16}", out->kbuf);
+    if (out->tile_w == 0 && out->tile_h == 0) {
+        out->tile_w = 8;
+        out->tile_h = 8;
+    }
+    const bool shape_ok = (out->tile_w == 8 && out->tile_h == 8) || (out->tile_w == 16 && out->tile_h == 4) ||
+                          (out->tile_w == 32 && out->tile_h == 2) || (out->tile_w == 64 && out->tile_h == 1) ||
+                          (out->tile_w == 4 && out->tile_h == 16);
+    if (!shape_ok) return fail(SPLAT_EUNSUPPORTED, "tile %dx%d is not a 64-pixel shape", out->tile_w, out->tile_h);
+    if (out->mode != SPLAT_ALPHA_CONSTANT && out->mode != SPLAT_ALPHA_SOFT)
+        return fail(SPLAT_EUNSUPPORTED, "unknown alpha mode %d", out->mode);
+    if (std::isnan(out->alpha_stop)) return fail(SPLAT_EINVAL, "alpha_stop is NaN");
+    if (!(out->t_max > 0)) return fail(SPLAT_EINVAL, "t_max must be positive");
+    return SPLAT_OK;
+}
+
+int hip_status(hipError_t e, const char *what)
+{
+    if (e == hipSuccess) return SPLAT_OK;
+    return fail(SPLAT_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+}  // namespace
+
+extern "C" {
+
+int splat_version(void) { return 100; }
+
+const char *splat_last_error(void) { return g_err; }
+
+size_t splat_bvh_bytes(uint32_t capacity) { return BvhLayout(capacity).total; }
+
+size_t splat_workspace_bytes(int32_t op, uint32_t capacity, int32_t width, int32_t height)
+{
+    switch (op) {
+    case SPLAT_OP_UNPROJECT:
+        return (width > 0 && height > 0) ? unproject_ws_bytes((int64_t)width * height) : 0;
+    case SPLAT_OP_BUILD: return BuildLayout(capacity).total;
+    case SPLAT_OP_TRACE:
+    case SPLAT_OP_BACKWARD: return 0;
+    case SPLAT_OP_BATCHED: return 256;
+    default: return 0;
+    }
+}
+
+int splat_unproject(const splat_camera *src, const float *rgba_premul, const float *depth, float radius_scale,
+                    const splat_spheres *out, void *ws, size_t ws_bytes, void *stream)
+{
+    int rc;
+    if ((rc = check_camera(src, "source"))) return rc;
+    if (!rgba_premul || !depth) return fail(SPLAT_EINVAL, "rgba_premul/depth is NULL");
+    if ((rc = check_spheres(out, true))) return rc;
+    if (!std::isfinite(radius_scale) || radius_scale < 0) return fail(SPLAT_EINVAL, "radius_scale must be >= 0");
+    const int64_t pixels = (int64_t)src->width * src->height;
+    if ((int64_t)out->capacity < pixels)
+        return fail(SPLAT_ENOSPC, "sphere capacity %u < %lld source pixels", out->capacity, (long long)pixels);
+    const size_t need = unproject_ws_bytes(pixels);
+    if (!ws || ws_bytes < need) return fail(SPLAT_ENOSPC, "unproject workspace needs %zu bytes", need);
+    if ((rc = check_device())) return rc;
+    return hip_status(launch_unproject(make_cam(*src), rgba_premul, depth, radius_scale, *out, ws,
+                                       static_cast<hipStream_t>(stream)),
+                      "unproject launch");
+}
+
+int splat_build_bvh(const splat_spheres *sph, const splat_bvh *bvh, int32_t refit_only, void *ws, size_t ws_bytes,
+                    void *stream)
+{
+    int rc;
+    if ((rc = check_spheres(sph, true))) return rc;
+    if ((rc = check_bvh(bvh))) return rc;
+    if (sph->capacity > bvh->capacity)
+        return fail(SPLAT_ENOSPC, "sphere capacity %u exceeds bvh capacity %u", sph->capacity, bvh->capacity);
+    if (!refit_only) {
+        const size_t need = BuildLayout(sph->capacity).total;
+        if (!ws || ws_bytes < need) return fail(SPLAT_ENOSPC, "build workspace needs %zu bytes", need);
+    }
+    if ((rc = check_device())) return rc;
+    return hip_status(launch_build(*sph, *bvh, refit_only != 0, ws, static_cast<hipStream_t>(stream)),
+                      "build launch");
+}
+
+static int trace_common(const splat_bvh *bvh, const splat_spheres *sph, const splat_camera *cam,
+                        const splat_trace_opts *opts, TraceArgs &a)
+{
+    int rc;
+    if ((rc = check_bvh(bvh))) return rc;
+    if ((rc = check_spheres(sph, true))) return rc;
+    if ((rc = check_camera(cam, "target"))) return rc;
+    splat_trace_opts o;
+    if ((rc = resolve_opts(opts, &o))) return rc;
+    std::memset(&a, 0, sizeof a);
+    a.bvh_mem = bvh->mem;
+    a.bvh_capacity = bvh->capacity < sph->capacity ? bvh->capacity : sph->capacity;
+    a.centre_radius = reinterpret_cast<const float4 *>(sph->centre_radius);
+    a.rgba = sph->rgba;
+    a.half = sph->rgba_dtype == SPLAT_F16;
+    a.cam = make_cam(*cam);
+    a.alpha_stop = o.alpha_stop;
+    a.mode = o.mode;
+    a.t_max = o.t_max;
+    a.kbuf = o.kbuf;
+    a.tile_w = o.tile_w;
+    a.tile_h = o.tile_h;
+    return SPLAT_OK;
+}
+
+int splat_trace(const splat_bvh *bvh, const splat_spheres *sph, const splat_camera *cam, const splat_trace_opts *opts,
+                float *out_rgba, uint32_t *out_hits, void *stream)
+{
+    TraceArgs a;
+    int rc;
+    if ((rc = trace_common(bvh, sph, cam, opts, a))) return rc;
+    if (!out_rgba) return fail(SPLAT_EINVAL, "out_rgba is NULL");
+    a.out = reinterpret_cast<float4 *>(out_rgba);
+    a.hits = out_hits;
+    if ((rc = check_device())) return rc;
+    return hip_status(launch_trace(a, false, static_cast<hipStream_t>(stream)), "trace launch");
+}
+
+int splat_trace_backward(const splat_bvh *bvh, const splat_spheres *sph, const splat_camera *cam,
+                         const splat_trace_opts *opts, const float *out_rgba, const float *grad_rgba,
+                         const splat_grads *grads, void *stream)
+{
+    TraceArgs a;
+    int rc;
+    if ((rc = trace_common(bvh, sph, cam, opts, a))) return rc;
+    if (!out_rgba || !grad_rgba) return fail(SPLAT_EINVAL, "out_rgba/grad_rgba is NULL");
+    if (!grads || !grads->d_rgb || !grads->d_alpha) return fail(SPLAT_EINVAL, "grads d_rgb/d_alpha is NULL");
+    if (a.mode == SPLAT_ALPHA_SOFT && (!grads->d_radius || !grads->d_centre))
+        return fail(SPLAT_EINVAL, "soft mode needs d_radius and d_centre");
+    a.fwd = reinterpret_cast<const float4 *>(out_rgba);
+    a.grad = reinterpret_cast<const float4 *>(grad_rgba);
+    a.d_rgb = grads->d_rgb;
+    a.d_alpha = grads->d_alpha;
+    a.d_radius = grads->d_radius;
+    a.d_centre = grads->d_centre;
+    if ((rc = check_device())) return rc;
+    return hip_status(launch_trace(a, true, static_cast<hipStream_t>(stream)), "backward launch");
+}
+
+int splat_trace_batched(const splat_batch_job *jobs, const uint32_t *tile_offsets, int32_t n_jobs,
+                        uint32_t total_tiles, const splat_trace_opts *opts, int32_t max_waves, void *ws,
+                        size_t ws_bytes, void *stream)
+{
+    int rc;
+    if (!jobs || !tile_offsets) return fail(SPLAT_EINVAL, "jobs/tile_offsets is NULL");
+    if (n_jobs <= 0) return fail(SPLAT_EINVAL, "n_jobs must be positive");
+    splat_trace_opts o;
+    if ((rc = resolve_opts(opts, &o))) return rc;
+    if (!ws || ws_bytes < 256) return fail(SPLAT_ENOSPC, "batched workspace needs 256 bytes");
+    if (max_waves < 0) return fail(SPLAT_EINVAL, "max_waves must be >= 0");
+    if ((rc = check_device())) return rc;
+    int waves = max_waves;
+    if (waves == 0) {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            return fail(SPLAT_EHIP, "cannot query compute units");
+        waves = cus * 16;
+    }
+    return hip_status(launch_trace_batched(jobs, tile_offsets, n_jobs, total_tiles, o, waves, ws,
+                                           static_cast<hipStream_t>(stream)),
+                      "batched launch");
+}
+
+}  // extern "C"

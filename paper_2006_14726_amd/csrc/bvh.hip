@@ -1,0 +1,443 @@
+// LBVH construction over the spheres (Sec. 3.1: the client builds a linear
+// BVH over the received samples).
+//
+//   bounds   block partial min/max of the centres
+//   morton   every block folds the partials; 30-bit Morton code per centre
+//   sort     stable LSD radix sort of (code, id), 8-bit digits, 4 passes:
+//            tile histograms -> one-block scan -> stable LDS scatter
+//   karras   radix-tree hierarchy: one thread per internal node finds its
+//            key range and split from common-prefix lengths of the sorted
+//            codes (ties broken by the sorted position)
+//   refit    bottom-up: each leaf writes its sphere into its parent; the
+//            second thread to reach a node (agent-scope acq_rel counter)
+//            unions the two child boxes and climbs on
+//
+// All sizes are read from device memory (the sphere count), so the sequence
+// can be captured in a HIP graph.
+#include "common.h"
+#include "kernels.h"
+
+namespace splat {
+
+constexpr int kBoundsBlocks = 256;
+
+__device__ inline float wave_min(float v)
+{
+    for (int off = 32; off > 0; off >>= 1) v = fminf(v, __shfl_xor(v, off, kWave));
+    return v;
+}
+__device__ inline float wave_max(float v)
+{
+    for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, kWave));
+    return v;
+}
+
+__global__ void __launch_bounds__(256)
+k_bounds_partial(const float4 *__restrict__ cr, const uint32_t *__restrict__ count, uint32_t cap,
+                 float *__restrict__ partial)
+{
+    const uint32_t n = min(*count, cap);
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+        const float4 c = cr[i];
+        lo[0] = fminf(lo[0], c.x); lo[1] = fminf(lo[1], c.y); lo[2] = fminf(lo[2], c.z);
+        hi[0] = fmaxf(hi[0], c.x); hi[1] = fmaxf(hi[1], c.y); hi[2] = fmaxf(hi[2], c.z);
+    }
+    __shared__ float s[4][6];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = wave_min(lo[a]);
+        hi[a] = wave_max(hi[a]);
+    }
+    if (lane == 0)
+        for (int a = 0; a < 3; ++a) { s[w][a] = lo[a]; s[w][3 + a] = hi[a]; }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        float v = s[0][threadIdx.x];
+        for (int k = 1; k < 4; ++k) v = threadIdx.x < 3 ? fminf(v, s[k][threadIdx.x]) : fmaxf(v, s[k][threadIdx.x]);
+        partial[blockIdx.x * 8 + threadIdx.x] = v;
+    }
+}
+
+__device__ inline uint32_t expand_bits10(uint32_t v)
+{
+    v = (v | (v << 16)) & 0x030000FFu;
+    v = (v | (v << 8)) & 0x0300F00Fu;
+    v = (v | (v << 4)) & 0x030C30C3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+
+// Bit 3k+2 of a code is x, 3k+1 is y, 3k is z.
+__global__ void __launch_bounds__(256)
+k_morton(const float4 *__restrict__ cr, const uint32_t *__restrict__ count, uint32_t cap, const float *__restrict__ partial,
+         BvhHeader *__restrict__ hdr, uint32_t *__restrict__ keys, uint32_t *__restrict__ vals)
+{
+    __shared__ float box[6];
+    if (threadIdx.x < 6) {
+        float v = partial[threadIdx.x];
+        for (int b = 1; b < kBoundsBlocks; ++b) {
+            const float u = partial[b * 8 + threadIdx.x];
+            v = threadIdx.x < 3 ? fminf(v, u) : fmaxf(v, u);
+        }
+        box[threadIdx.x] = v;
+    }
+    __syncthreads();
+    const uint32_t n = min(*count, cap);
+    const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (blockIdx.x == 0 && threadIdx.x < 6) {
+        if (threadIdx.x < 3) hdr->cen_lo[threadIdx.x] = box[threadIdx.x];
+        else hdr->cen_hi[threadIdx.x - 3] = box[threadIdx.x];
+        if (threadIdx.x == 0) hdr->n = n;
+    }
+    if (i >= n) return;
+    const float4 c = cr[i];
+    const float p[3] = {c.x, c.y, c.z};
+    uint32_t q[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float ext = box[3 + a] - box[a];
+        const float u = ext > 0.0f ? (p[a] - box[a]) / ext : 0.0f;
+        int v = (int)(u * 1024.0f);
+        q[a] = (uint32_t)(v < 0 ? 0 : (v > 1023 ? 1023 : v));
+    }
+    keys[i] = (expand_bits10(q[0]) << 2) | (expand_bits10(q[1]) << 1) | expand_bits10(q[2]);
+    vals[i] = i;
+}
+
+// ---------------------------------------------------------------- radix sort
+
+__global__ void __launch_bounds__(kSortBlock)
+k_sort_hist(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ count, uint32_t cap, int shift,
+            uint32_t *__restrict__ hist, uint32_t tiles)
+{
+    __shared__ uint32_t h[kSortBins];
+    for (int d = threadIdx.x; d < kSortBins; d += kSortBlock) h[d] = 0;
+    __syncthreads();
+    const uint32_t n = min(*count, cap);
+    const uint32_t base = blockIdx.x * kSortTile;
+#pragma unroll
+    for (int it = 0; it < kSortItems; ++it) {
+        const uint32_t i = base + it * kSortBlock + threadIdx.x;
+        if (i < n) atomicAdd(&h[(keys[i] >> shift) & (kSortBins - 1)], 1u);
+    }
+    __syncthreads();
+    for (int d = threadIdx.x; d < kSortBins; d += kSortBlock) hist[(size_t)d * tiles + blockIdx.x] = h[d];
+}
+
+// One block of 1024 threads: exclusive scan of data[0..n) in place; optional total.
+__global__ void __launch_bounds__(1024)
+k_scan_exclusive(uint32_t *__restrict__ data, uint32_t n)
+{
+    __shared__ uint32_t part[1024];
+    const uint32_t per = (n + 1023) / 1024;
+    const uint32_t lo = threadIdx.x * per, hi = min(n, lo + per);
+    uint32_t s = 0;
+    for (uint32_t i = lo; i < hi; ++i) s += data[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const uint32_t v = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0u;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    uint32_t run = threadIdx.x ? part[threadIdx.x - 1] : 0u;
+    for (uint32_t i = lo; i < hi; ++i) {
+        const uint32_t c = data[i];
+        data[i] = run;
+        run += c;
+    }
+}
+
+// Stable scatter of one tile.  Wave w owns the contiguous keys
+// [base + w*64*kSortItems, +64*kSortItems), visited in 64-key rounds; lanes
+// holding the same digit find each other with 8 ballots and rank by lane.
+__global__ void __launch_bounds__(kSortBlock)
+k_sort_scatter(const uint32_t *__restrict__ keys_in, const uint32_t *__restrict__ vals_in,
+               uint32_t *__restrict__ keys_out, uint32_t *__restrict__ vals_out, const uint32_t *__restrict__ count,
+               uint32_t cap, int shift, const uint32_t *__restrict__ hist, uint32_t tiles)
+{
+    constexpr int kWaves = kSortBlock / kWave;
+    __shared__ uint32_t cnt[kWaves][kSortBins];
+    __shared__ uint32_t local_start[kSortBins];
+    __shared__ uint32_t global_start[kSortBins];
+    __shared__ uint32_t skeys[kSortTile];
+    __shared__ uint32_t svals[kSortTile];
+
+    const uint32_t n = min(*count, cap);
+    const uint32_t base = blockIdx.x * kSortTile;
+    if (base >= n) return;
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    for (int d = threadIdx.x; d < kWaves * kSortBins; d += kSortBlock) (&cnt[0][0])[d] = 0;
+    __syncthreads();
+
+    uint32_t key[kSortItems], val[kSortItems], rank[kSortItems];
+    const uint64_t lt = (1ull << lane) - 1;
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+        const uint32_t i = base + (uint32_t)(w * kSortItems + r) * kWave + lane;
+        const bool ok = i < n;
+        key[r] = ok ? keys_in[i] : 0u;
+        val[r] = ok ? vals_in[i] : 0u;
+        const uint32_t d = (key[r] >> shift) & (kSortBins - 1);
+        uint64_t peers = __ballot(ok);
+#pragma unroll
+        for (int b = 0; b < kSortBits; ++b) {
+            const uint64_t bb = __ballot((d >> b) & 1u);
+            peers &= ((d >> b) & 1u) ? bb : ~bb;
+        }
+        const uint32_t before = cnt[w][d];
+        rank[r] = before + (uint32_t)__popcll(peers & lt);
+        const bool leader = ok && (peers & lt) == 0;
+        if (leader) cnt[w][d] = before + (uint32_t)__popcll(peers);
+        if (!ok) rank[r] = 0xffffffffu;
+    }
+    __syncthreads();
+    // digit totals: exclusive prefix over waves (in place), then over digits
+    if (threadIdx.x < kSortBins) {
+        const int d = threadIdx.x;
+        uint32_t run = 0;
+        for (int k = 0; k < kWaves; ++k) {
+            const uint32_t t = cnt[k][d];
+            cnt[k][d] = run;
+            run += t;
+        }
+        local_start[d] = run;  // total, scanned below
+        global_start[d] = hist[(size_t)d * tiles + blockIdx.x];
+    }
+    __syncthreads();
+    if (threadIdx.x < kWave) {
+        // exclusive scan of 256 digit totals by one wave: 4 per lane
+        uint32_t v[4], s = 0;
+        for (int k = 0; k < 4; ++k) { v[k] = local_start[threadIdx.x * 4 + k]; s += v[k]; }
+        uint32_t incl = s;
+        for (int off = 1; off < kWave; off <<= 1) {
+            const uint32_t o = __shfl_up(incl, off, kWave);
+            if (threadIdx.x >= (unsigned)off) incl += o;
+        }
+        uint32_t run = incl - s;
+        for (int k = 0; k < 4; ++k) { local_start[threadIdx.x * 4 + k] = run; run += v[k]; }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+        if (rank[r] == 0xffffffffu) continue;
+        const uint32_t d = (key[r] >> shift) & (kSortBins - 1);
+        const uint32_t pos = local_start[d] + cnt[w][d] + rank[r];
+        skeys[pos] = key[r];
+        svals[pos] = val[r];
+    }
+    __syncthreads();
+    const uint32_t m = min((uint32_t)kSortTile, n - base);
+    for (uint32_t i = threadIdx.x; i < m; i += kSortBlock) {
+        const uint32_t k = skeys[i];
+        const uint32_t d = (k >> shift) & (kSortBins - 1);
+        const uint32_t o = global_start[d] + i - local_start[d];
+        keys_out[o] = k;
+        vals_out[o] = svals[i];
+    }
+}
+
+// ---------------------------------------------------------------- hierarchy
+
+__device__ inline int common_prefix(const uint32_t *__restrict__ keys, int n, int i, int j)
+{
+    if (j < 0 || j >= n) return -1;
+    const uint32_t a = keys[i], b = keys[j];
+    if (a != b) return __clz(a ^ b);
+    return 32 + __clz((uint32_t)i ^ (uint32_t)j);
+}
+
+__device__ inline void set_ref(Node *nodes, uint32_t node, int side, uint32_t ref)
+{
+    nodes[node].f[12 + side] = __uint_as_float(ref);
+}
+
+__global__ void __launch_bounds__(256)
+k_karras(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ vals, const uint32_t *__restrict__ count,
+         uint32_t cap,
+         Node *__restrict__ nodes, uint32_t *__restrict__ leaf_parent, uint32_t *__restrict__ node_parent,
+         uint32_t *__restrict__ leaf_ids, uint32_t *__restrict__ flags)
+{
+    const int n = (int)min(*count, cap);
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) leaf_ids[i] = vals[i];
+    if (n == 1 && i == 0) {
+        // a single sphere: a root with one leaf and one empty child
+        set_ref(nodes, 0, 0, kLeafBit | vals[0]);
+        set_ref(nodes, 0, 1, kEmpty);
+        nodes[0].f[14] = __uint_as_float(3u);
+        leaf_parent[0] = 0u;
+        node_parent[0] = kEmpty;
+        flags[0] = 0u;
+        return;
+    }
+    if (i >= n - 1) return;
+    flags[i] = 0u;
+    const int d = common_prefix(keys, n, i, i + 1) > common_prefix(keys, n, i, i - 1) ? 1 : -1;
+    const int dmin = common_prefix(keys, n, i, i - d);
+    int lmax = 2;
+    while (common_prefix(keys, n, i, i + lmax * d) > dmin) lmax <<= 1;
+    int l = 0;
+    for (int t = lmax >> 1; t >= 1; t >>= 1)
+        if (common_prefix(keys, n, i, i + (l + t) * d) > dmin) l += t;
+    const int j = i + l * d;
+    const int dnode = common_prefix(keys, n, i, j);
+    int s = 0, t = l;
+    do {
+        t = (t + 1) >> 1;
+        if (common_prefix(keys, n, i, i + (s + t) * d) > dnode) s += t;
+    } while (t > 1);
+    const int gamma = i + s * d + (d < 0 ? -1 : 0);
+    const int lo = min(i, j), hi = max(i, j);
+    const bool left_leaf = lo == gamma, right_leaf = hi == gamma + 1;
+    set_ref(nodes, i, 0, left_leaf ? (kLeafBit | vals[gamma]) : (uint32_t)gamma);
+    set_ref(nodes, i, 1, right_leaf ? (kLeafBit | vals[gamma + 1]) : (uint32_t)(gamma + 1));
+    uint32_t axis = 3u;
+    if (dnode < 32) axis = 2u - (uint32_t)((31 - dnode) % 3);
+    nodes[i].f[14] = __uint_as_float(axis);
+    if (left_leaf) leaf_parent[gamma] = (uint32_t)i << 1;
+    else node_parent[gamma] = (uint32_t)i << 1;
+    if (right_leaf) leaf_parent[gamma + 1] = ((uint32_t)i << 1) | 1u;
+    else node_parent[gamma + 1] = ((uint32_t)i << 1) | 1u;
+    if (i == 0) node_parent[0] = kEmpty;
+}
+
+__global__ void __launch_bounds__(256) k_zero_flags(uint32_t *__restrict__ flags, const uint32_t *__restrict__ count,
+                                                    uint32_t cap)
+{
+    const uint32_t n = min(*count, cap);
+    const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i < (n > 1 ? n - 1 : 1)) flags[i] = 0u;
+}
+
+// Box of a child slot: the stored box of an internal child, or the sphere's
+// box c +- r rounded outward to float for a leaf child.
+__device__ inline void slot_box(const Node &nd, int side, float lo[3], float hi[3])
+{
+    const uint32_t ref = __float_as_uint(nd.f[12 + side]);
+    const float *s = nd.f + 6 * side;
+    if (ref == kEmpty) {
+        for (int a = 0; a < 3; ++a) { lo[a] = INFINITY; hi[a] = -INFINITY; }
+    } else if (ref & kLeafBit) {
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = nextafterf(s[a] - s[3], -INFINITY);
+            hi[a] = nextafterf(s[a] + s[3], INFINITY);
+        }
+    } else {
+        for (int a = 0; a < 3; ++a) { lo[a] = s[a]; hi[a] = s[3 + a]; }
+    }
+}
+
+__device__ inline float sphere_alpha_a(const void *rgba, int half, uint32_t id)
+{
+    if (half) return half_to_float(reinterpret_cast<const ushort4 *>(rgba)[id].w);
+    return reinterpret_cast<const float4 *>(rgba)[id].w;
+}
+
+__global__ void __launch_bounds__(256)
+k_refit(const float4 *__restrict__ cr, const void *__restrict__ rgba, int half, const uint32_t *__restrict__ count,
+        uint32_t cap,
+        Node *nodes, const uint32_t *__restrict__ leaf_parent, const uint32_t *__restrict__ node_parent,
+        const uint32_t *__restrict__ leaf_ids, uint32_t *flags, BvhHeader *__restrict__ hdr)
+{
+    const uint32_t n = min(*count, cap);
+    const uint32_t n_nodes = n > 1 ? n - 1 : 1;
+    const uint32_t j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= n) return;
+    const uint32_t id = leaf_ids[j];
+    if (id >= n) return;  // only after a refit of a hierarchy that was never built
+    const float4 c = cr[id];
+    const float a = sphere_alpha_a(rgba, half, id);
+    uint32_t pp = leaf_parent[j];
+    uint32_t p = pp >> 1;
+    if (p >= n_nodes) return;
+    {
+        float *s = nodes[p].f + 6 * (pp & 1u);
+        s[0] = c.x; s[1] = c.y; s[2] = c.z; s[3] = c.w; s[4] = a; s[5] = 0.0f;
+    }
+    if (n == 1) {
+        float *s = nodes[0].f + 6;
+        for (int k = 0; k < 3; ++k) { s[k] = INFINITY; s[3 + k] = -INFINITY; }
+        const float ctr[3] = {c.x, c.y, c.z};
+        for (int k = 0; k < 3; ++k) {
+            hdr->scene_lo[k] = nextafterf(ctr[k] - c.w, -INFINITY);
+            hdr->scene_hi[k] = nextafterf(ctr[k] + c.w, INFINITY);
+        }
+        return;
+    }
+    for (;;) {
+        const uint32_t old = __hip_atomic_fetch_add(&flags[p], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        // first arrival: the sibling subtree is not finished yet and its thread
+        // continues; a count above 1 only occurs in a corrupt hierarchy
+        if (old != 1u) return;
+        const Node nd = nodes[p];
+        float lo0[3], hi0[3], lo1[3], hi1[3];
+        slot_box(nd, 0, lo0, hi0);
+        slot_box(nd, 1, lo1, hi1);
+        float lo[3], hi[3];
+        for (int k = 0; k < 3; ++k) { lo[k] = fminf(lo0[k], lo1[k]); hi[k] = fmaxf(hi0[k], hi1[k]); }
+        pp = node_parent[p];
+        if (pp == kEmpty) {
+            for (int k = 0; k < 3; ++k) { hdr->scene_lo[k] = lo[k]; hdr->scene_hi[k] = hi[k]; }
+            return;
+        }
+        p = pp >> 1;
+        if (p >= n_nodes) return;
+        float *s = nodes[p].f + 6 * (pp & 1u);
+        s[0] = lo[0]; s[1] = lo[1]; s[2] = lo[2]; s[3] = hi[0]; s[4] = hi[1]; s[5] = hi[2];
+    }
+}
+
+// An empty sphere set: header n = 0 so that tracing returns background.
+__global__ void k_header_count(const uint32_t *__restrict__ count, uint32_t cap, BvhHeader *__restrict__ hdr)
+{
+    if (threadIdx.x == 0) hdr->n = min(*count, cap);
+}
+
+hipError_t launch_build(const splat_spheres &sph, const splat_bvh &bvh, bool refit_only, void *ws, hipStream_t s)
+{
+    const uint32_t cap = sph.capacity;
+    const BvhLayout L(bvh.capacity);
+    char *mem = static_cast<char *>(bvh.mem);
+    BvhHeader *hdr = reinterpret_cast<BvhHeader *>(mem + L.header);
+    Node *nodes = reinterpret_cast<Node *>(mem + L.nodes);
+    uint32_t *leaf_parent = reinterpret_cast<uint32_t *>(mem + L.leaf_parent);
+    uint32_t *node_parent = reinterpret_cast<uint32_t *>(mem + L.node_parent);
+    uint32_t *leaf_ids = reinterpret_cast<uint32_t *>(mem + L.leaf_ids);
+    uint32_t *flags = reinterpret_cast<uint32_t *>(mem + L.flags);
+    const float4 *cr = reinterpret_cast<const float4 *>(sph.centre_radius);
+    const int half = sph.rgba_dtype == SPLAT_F16;
+    const uint32_t blocks = (cap + 255) / 256 > 0 ? (cap + 255) / 256 : 1;
+
+    hipLaunchKernelGGL(k_header_count, dim3(1), dim3(64), 0, s, sph.count, cap, hdr);
+    if (!refit_only) {
+        const BuildLayout B(cap);
+        char *w = static_cast<char *>(ws);
+        uint32_t *ka = reinterpret_cast<uint32_t *>(w + B.keys_a), *va = reinterpret_cast<uint32_t *>(w + B.vals_a);
+        uint32_t *kb = reinterpret_cast<uint32_t *>(w + B.keys_b), *vb = reinterpret_cast<uint32_t *>(w + B.vals_b);
+        uint32_t *hist = reinterpret_cast<uint32_t *>(w + B.hist);
+        float *partial = reinterpret_cast<float *>(w + B.partial);
+        hipLaunchKernelGGL(k_bounds_partial, dim3(kBoundsBlocks), dim3(256), 0, s, cr, sph.count, cap, partial);
+        hipLaunchKernelGGL(k_morton, dim3(blocks), dim3(256), 0, s, cr, sph.count, cap, partial, hdr, ka, va);
+        for (int shift = 0; shift < kMortonBits; shift += kSortBits) {
+            hipLaunchKernelGGL(k_sort_hist, dim3(B.tiles), dim3(kSortBlock), 0, s, ka, sph.count, cap, shift, hist,
+                               B.tiles);
+            hipLaunchKernelGGL(k_scan_exclusive, dim3(1), dim3(1024), 0, s, hist, (uint32_t)kSortBins * B.tiles);
+            hipLaunchKernelGGL(k_sort_scatter, dim3(B.tiles), dim3(kSortBlock), 0, s, ka, va, kb, vb, sph.count, cap, shift,
+                               hist, B.tiles);
+            uint32_t *t = ka; ka = kb; kb = t;
+            t = va; va = vb; vb = t;
+        }
+        hipLaunchKernelGGL(k_karras, dim3(blocks), dim3(256), 0, s, ka, va, sph.count, cap, nodes, leaf_parent,
+                           node_parent, leaf_ids, flags);
+    } else {
+        hipLaunchKernelGGL(k_zero_flags, dim3(blocks), dim3(256), 0, s, flags, sph.count, cap);
+    }
+    hipLaunchKernelGGL(k_refit, dim3(blocks), dim3(256), 0, s, cr, sph.rgba, half, sph.count, cap, nodes, leaf_parent,
+                       node_parent, leaf_ids, flags, hdr);
+    return hipGetLastError();
+}
+
+}  // namespace splat

@@ -1,0 +1,180 @@
+// Device-side definitions shared by the splat kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/splat.h"
+
+namespace splat {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------- camera
+
+// Camera as kernels see it (same fields as splat_camera, passed by value).
+struct Cam {
+    double eye[3], fwd[3], right[3], up[3];
+    double tan_half;
+    int32_t w, h;
+};
+
+__host__ inline Cam make_cam(const splat_camera &c)
+{
+    Cam k;
+    for (int a = 0; a < 3; ++a) {
+        k.eye[a] = c.eye[a];
+        k.fwd[a] = c.forward[a];
+        k.right[a] = c.right[a];
+        k.up[a] = c.up[a];
+    }
+    k.tan_half = c.tan_half_fov_y;
+    k.w = c.width;
+    k.h = c.height;
+    return k;
+}
+
+// Unit direction of the ray through the centre of pixel (x, y), in double.
+__device__ inline void pixel_ray(const Cam &c, int x, int y, double d[3])
+{
+    const double aspect = (double)c.w / (double)c.h;
+    const double sx = ((2.0 * x + 1.0) / (double)c.w - 1.0) * c.tan_half * aspect;
+    const double sy = (1.0 - (2.0 * y + 1.0) / (double)c.h) * c.tan_half;
+    double v0 = c.fwd[0] + sx * c.right[0] + sy * c.up[0];
+    double v1 = c.fwd[1] + sx * c.right[1] + sy * c.up[1];
+    double v2 = c.fwd[2] + sx * c.right[2] + sy * c.up[2];
+    const double len = sqrt(v0 * v0 + v1 * v1 + v2 * v2);
+    d[0] = v0 / len;
+    d[1] = v1 / len;
+    d[2] = v2 / len;
+}
+
+// ---------------------------------------------------------------- half
+
+// IEEE binary16 bits of a double, round to nearest even, by integer
+// manipulation of the binary64 encoding (one rounding, no float detour).
+__device__ inline uint16_t half_bits_rne(double v)
+{
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint16_t sign = (uint16_t)((b >> 48) & 0x8000u);
+    const int e = (int)((b >> 52) & 0x7ff);
+    uint64_t m = b & 0xfffffffffffffull;
+    if (e == 0x7ff) return (uint16_t)(sign | (m ? 0x7e00u : 0x7c00u));
+    if (e == 0) return sign;                 // binary64 subnormals underflow to zero
+    const int E = e - 1023;                  // value = 1.m * 2^E
+    if (E > 15) return (uint16_t)(sign | 0x7c00u);
+    m |= 1ull << 52;                         // 53-bit significand
+    int shift;                               // bits dropped from the 53-bit significand
+    uint32_t exp_field;
+    if (E >= -14) {
+        shift = 42;                          // keep 11 bits (implicit + 10)
+        exp_field = (uint32_t)(E + 15);
+    } else {
+        shift = 42 + (-14 - E);              // subnormal: fewer bits kept
+        exp_field = 0;
+        if (shift > 63) return sign;
+    }
+    uint64_t kept = m >> shift;
+    const uint64_t rem = m & ((1ull << shift) - 1);
+    const uint64_t half = 1ull << (shift - 1);
+    if (rem > half || (rem == half && (kept & 1))) kept += 1;
+    uint32_t bits;
+    if (exp_field == 0) {
+        bits = (uint32_t)kept;               // may carry into the smallest normal: still right
+    } else {
+        if (kept == (1ull << 11)) {          // significand overflow
+            kept >>= 1;
+            exp_field += 1;
+            if (exp_field >= 31) return (uint16_t)(sign | 0x7c00u);
+        }
+        bits = (exp_field << 10) | (uint32_t)(kept & 0x3ff);
+    }
+    return (uint16_t)(sign | bits);
+}
+
+__device__ inline float half_to_float(uint16_t h)
+{
+    return (float)__builtin_bit_cast(_Float16, h);  // exact widening
+}
+
+// ---------------------------------------------------------------- BVH layout
+
+// Child references in a node.
+constexpr uint32_t kLeafBit = 0x80000000u;
+constexpr uint32_t kEmpty = 0xffffffffu;
+
+// Node: two child slots of 6 floats each, then two references and metadata.
+//   internal child: lo.xyz, hi.xyz of its box (float, rounded outward)
+//   leaf child:     centre.xyz, radius, alpha a, unused
+//   f[12], f[13]:   child references (node index, kLeafBit | sphere id, kEmpty)
+//   f[14]:          split axis of the node (0 x, 1 y, 2 z, 3 none)
+struct __align__(64) Node {
+    float f[16];
+};
+
+struct __align__(256) BvhHeader {
+    uint32_t n;            // spheres at build time
+    uint32_t pad0;
+    float scene_lo[3];     // box of all leaves (root box)
+    float scene_hi[3];
+    float cen_lo[3];       // bounds of the centres (Morton quantisation)
+    float cen_hi[3];
+    uint32_t pad[50];
+};
+static_assert(sizeof(BvhHeader) == 256, "header size");
+
+__host__ __device__ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Offsets inside splat_bvh.mem.
+struct BvhLayout {
+    size_t header, nodes, leaf_parent, node_parent, leaf_ids, flags, total;
+    __host__ __device__ explicit BvhLayout(uint32_t cap)
+    {
+        const size_t c = cap < 1 ? 1 : cap;
+        header = 0;
+        nodes = align256(sizeof(BvhHeader));
+        leaf_parent = align256(nodes + c * sizeof(Node));
+        node_parent = align256(leaf_parent + c * 4);
+        leaf_ids = align256(node_parent + c * 4);
+        flags = align256(leaf_ids + c * 4);
+        total = align256(flags + c * 4);
+    }
+};
+
+// Radix-sort layout in the build workspace.
+constexpr int kSortBits = 8;
+constexpr int kSortBins = 1 << kSortBits;
+constexpr int kSortBlock = 256;                  // threads per sort block
+constexpr int kSortItems = 8;                    // keys per thread
+constexpr int kSortTile = kSortBlock * kSortItems;
+constexpr int kMortonBits = 30;
+
+struct BuildLayout {
+    size_t keys_a, vals_a, keys_b, vals_b, hist, partial, total;
+    uint32_t tiles;
+    __host__ __device__ explicit BuildLayout(uint32_t cap)
+    {
+        const size_t c = cap < 1 ? 1 : cap;
+        tiles = (uint32_t)((c + kSortTile - 1) / kSortTile);
+        keys_a = 0;
+        vals_a = align256(keys_a + c * 4);
+        keys_b = align256(vals_a + c * 4);
+        vals_b = align256(keys_b + c * 4);
+        hist = align256(vals_b + c * 4);
+        partial = align256(hist + (size_t)kSortBins * tiles * 4);
+        total = align256(partial + 1024 * 8 * sizeof(float));
+    }
+};
+
+// Unprojection workspace: per-block valid counts and their exclusive scan.
+constexpr int kUnprojBlock = 256;
+constexpr int kUnprojItems = 4;
+constexpr int kUnprojTile = kUnprojBlock * kUnprojItems;
+
+__host__ __device__ inline size_t unproject_ws_bytes(int64_t pixels)
+{
+    const size_t blocks = (size_t)((pixels + kUnprojTile - 1) / kUnprojTile);
+    return align256((blocks + 1) * 4);
+}
+
+}  // namespace splat

@@ -1,0 +1,40 @@
+// Host-side launchers implemented by the kernel translation units.
+#pragma once
+
+#include "common.h"
+
+namespace splat {
+
+struct TraceArgs {
+    const void *bvh_mem;
+    uint32_t bvh_capacity;
+    const float4 *centre_radius;
+    const void *rgba;
+    int32_t half;               // colour dtype is half4
+    Cam cam;
+    float alpha_stop;
+    int32_t mode;
+    double t_max;
+    int32_t kbuf;
+    int32_t tile_w, tile_h;
+    float4 *out;                // forward output
+    uint32_t *hits;             // nullable
+    // backward only
+    const float4 *fwd;          // forward output of the same call
+    const float4 *grad;         // dL/d out
+    float *d_rgb, *d_alpha, *d_radius, *d_centre;
+};
+
+hipError_t launch_unproject(const Cam &cam, const float *rgba, const float *depth, float radius_scale,
+                            const splat_spheres &out, void *ws, hipStream_t s);
+
+hipError_t launch_build(const splat_spheres &sph, const splat_bvh &bvh, bool refit_only, void *ws,
+                        hipStream_t s);
+
+hipError_t launch_trace(const TraceArgs &a, bool backward, hipStream_t s);
+
+hipError_t launch_trace_batched(const splat_batch_job *jobs, const uint32_t *tile_offsets, int32_t n_jobs,
+                                uint32_t total_tiles, const splat_trace_opts &o, int32_t waves, void *ws,
+                                hipStream_t s);
+
+}  // namespace splat

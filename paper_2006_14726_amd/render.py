@@ -1,0 +1,220 @@
+"""Torch-facing wrappers of the C ABI: tensors in, tensors out.
+
+Torch only provides device memory and the current stream; every step runs
+in the HIP kernels of libsplat.so.  Nothing here synchronises unless a
+function says so.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+from dataclasses import dataclass, field
+
+import torch
+
+from . import _lib
+
+
+def _ptr(t: torch.Tensor | None):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _require_cuda(t: torch.Tensor, name: str, dtype=None, contiguous=True):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if contiguous and not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+_workspaces: dict = {}
+
+
+def workspace(nbytes: int, device, tag: str) -> torch.Tensor:
+    """Grow-only scratch buffer per (device, tag)."""
+    key = (str(device), tag)
+    ws = _workspaces.get(key)
+    if ws is None or ws.numel() < nbytes:
+        ws = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+        _workspaces[key] = ws
+    return ws
+
+
+@dataclass
+class Spheres:
+    """Sphere set in device memory (capacity slots, `count` used)."""
+    centre_radius: torch.Tensor            # float32 [cap, 4]
+    rgba: torch.Tensor                     # float16 or float32 [cap, 4], straight colour + alpha
+    count: torch.Tensor                    # int32 [1] on the device
+    src_index: torch.Tensor | None = None  # int32 [cap]
+
+    @property
+    def capacity(self) -> int:
+        return self.centre_radius.shape[0]
+
+    @property
+    def half(self) -> bool:
+        return self.rgba.dtype == torch.float16
+
+    def struct(self) -> _lib.splat_spheres:
+        s = _lib.splat_spheres()
+        s.centre_radius = self.centre_radius.data_ptr()
+        s.rgba = self.rgba.data_ptr()
+        s.rgba_dtype = _lib.SPLAT_F16 if self.half else _lib.SPLAT_F32
+        s.src_index = None if self.src_index is None else self.src_index.data_ptr()
+        s.count = self.count.data_ptr()
+        s.capacity = self.capacity
+        return s
+
+    def n(self) -> int:
+        """Number of spheres (reads the device count: synchronises)."""
+        return int(self.count.item())
+
+
+def spheres_from_tensors(centre_radius: torch.Tensor, rgba: torch.Tensor) -> Spheres:
+    """Wrap existing [N, 4] tensors as a sphere set of N spheres."""
+    _require_cuda(centre_radius, "centre_radius", torch.float32)
+    _require_cuda(rgba, "rgba")
+    if rgba.dtype not in (torch.float16, torch.float32):
+        raise ValueError("rgba must be float16 or float32")
+    n = centre_radius.shape[0]
+    if centre_radius.shape != (n, 4) or rgba.shape != (n, 4) or n == 0:
+        raise ValueError("centre_radius and rgba must both be [N, 4] with N >= 1")
+    count = torch.full((1,), n, dtype=torch.int32, device=centre_radius.device)
+    return Spheres(centre_radius, rgba, count)
+
+
+def alloc_spheres(capacity: int, device, half: bool = True) -> Spheres:
+    return Spheres(torch.empty((capacity, 4), dtype=torch.float32, device=device),
+                   torch.empty((capacity, 4), dtype=torch.float16 if half else torch.float32, device=device),
+                   torch.zeros((1,), dtype=torch.int32, device=device),
+                   torch.empty((capacity,), dtype=torch.int32, device=device))
+
+
+def unproject(src_cam, rgba: torch.Tensor, depth: torch.Tensor, radius_scale: float = 1.0, half: bool = True,
+              out: Spheres | None = None) -> Spheres:
+    """Eq. 1 unprojection of a premultiplied RGBA + depth image into spheres (splat_unproject)."""
+    H, W = int(src_cam.height), int(src_cam.width)
+    _require_cuda(rgba, "rgba", torch.float32)
+    _require_cuda(depth, "depth", torch.float32)
+    if tuple(rgba.shape) != (H, W, 4) or tuple(depth.shape) != (H, W):
+        raise ValueError(f"rgba must be [{H}, {W}, 4] and depth [{H}, {W}]")
+    if out is None:
+        out = alloc_spheres(H * W, rgba.device, half)
+    lib = _lib.load()
+    need = lib.splat_workspace_bytes(_lib.SPLAT_OP_UNPROJECT, 0, W, H)
+    ws = workspace(need, rgba.device, "unproject")
+    cam = _lib.camera_struct(src_cam)
+    s = out.struct()
+    _lib.check(lib.splat_unproject(ctypes.byref(cam), _ptr(rgba), _ptr(depth), float(radius_scale), ctypes.byref(s),
+                                   _ptr(ws), ws.numel(), _stream()))
+    return out
+
+
+@dataclass
+class BVH:
+    mem: torch.Tensor  # uint8 [splat_bvh_bytes(capacity)]
+    capacity: int
+
+    def struct(self) -> _lib.splat_bvh:
+        b = _lib.splat_bvh()
+        b.mem = self.mem.data_ptr()
+        b.capacity = self.capacity
+        return b
+
+
+def alloc_bvh(capacity: int, device) -> BVH:
+    nbytes = _lib.load().splat_bvh_bytes(int(capacity))
+    return BVH(torch.zeros(nbytes, dtype=torch.uint8, device=device), int(capacity))
+
+
+def build_bvh(sph: Spheres, bvh: BVH | None = None, refit_only: bool = False) -> BVH:
+    """LBVH build (or refit of the previous hierarchy) over a sphere set (splat_build_bvh)."""
+    if bvh is None:
+        bvh = alloc_bvh(sph.capacity, sph.centre_radius.device)
+    lib = _lib.load()
+    need = lib.splat_workspace_bytes(_lib.SPLAT_OP_BUILD, sph.capacity, 0, 0)
+    ws = workspace(need, sph.centre_radius.device, "build")
+    s, b = sph.struct(), bvh.struct()
+    _lib.check(lib.splat_build_bvh(ctypes.byref(s), ctypes.byref(b), int(bool(refit_only)), _ptr(ws), ws.numel(),
+                                   _stream()))
+    return bvh
+
+
+@dataclass
+class TraceOptions:
+    alpha_stop: float = 0.99
+    t_max: float = math.inf
+    mode: int = _lib.SPLAT_ALPHA_CONSTANT
+    kbuf: int = 8
+    tile: tuple = field(default=(8, 8))
+
+    def struct(self) -> _lib.splat_trace_opts:
+        o = _lib.splat_trace_opts()
+        o.alpha_stop = float(self.alpha_stop)
+        o.t_max = float(self.t_max)
+        o.mode = int(self.mode)
+        o.kbuf = int(self.kbuf)
+        o.tile_w, o.tile_h = int(self.tile[0]), int(self.tile[1])
+        return o
+
+
+def trace(bvh: BVH, sph: Spheres, cam, opts: TraceOptions | None = None, out: torch.Tensor | None = None,
+          hits: torch.Tensor | None = None, want_hits: bool = True):
+    """Trace and composite from `cam` (splat_trace).  Returns (rgba [H, W, 4] float32, hits [H, W] int32 or None)."""
+    opts = opts or TraceOptions()
+    H, W = int(cam.height), int(cam.width)
+    dev = sph.centre_radius.device
+    if out is None:
+        out = torch.empty((H, W, 4), dtype=torch.float32, device=dev)
+    if hits is None and want_hits:
+        hits = torch.empty((H, W), dtype=torch.int32, device=dev)
+    _require_cuda(out, "out", torch.float32)
+    if tuple(out.shape) != (H, W, 4):
+        raise ValueError("out must be [H, W, 4]")
+    if hits is not None and (tuple(hits.shape) != (H, W) or hits.dtype != torch.int32):
+        raise ValueError("hits must be int32 [H, W]")
+    lib = _lib.load()
+    c, o, s, b = _lib.camera_struct(cam), opts.struct(), sph.struct(), bvh.struct()
+    _lib.check(lib.splat_trace(ctypes.byref(b), ctypes.byref(s), ctypes.byref(c), ctypes.byref(o), _ptr(out),
+                               _ptr(hits), _stream()))
+    return out, hits
+
+
+def trace_backward(bvh: BVH, sph: Spheres, cam, opts: TraceOptions, out_rgba: torch.Tensor, grad_rgba: torch.Tensor,
+                   grads: dict | None = None) -> dict:
+    """Accumulate dL/d(rgb, alpha, radius, centre) per sphere (splat_trace_backward)."""
+    dev = sph.centre_radius.device
+    cap = sph.capacity
+    if grads is None:
+        grads = {"rgb": torch.zeros((cap, 3), dtype=torch.float32, device=dev),
+                 "alpha": torch.zeros((cap,), dtype=torch.float32, device=dev),
+                 "radius": torch.zeros((cap,), dtype=torch.float32, device=dev),
+                 "centre": torch.zeros((cap, 3), dtype=torch.float32, device=dev)}
+    _require_cuda(out_rgba, "out_rgba", torch.float32)
+    _require_cuda(grad_rgba, "grad_rgba", torch.float32)
+    H, W = int(cam.height), int(cam.width)
+    if tuple(out_rgba.shape) != (H, W, 4) or tuple(grad_rgba.shape) != (H, W, 4):
+        raise ValueError("out_rgba and grad_rgba must be [H, W, 4]")
+    g = _lib.splat_grads()
+    g.d_rgb, g.d_alpha = grads["rgb"].data_ptr(), grads["alpha"].data_ptr()
+    g.d_radius, g.d_centre = grads["radius"].data_ptr(), grads["centre"].data_ptr()
+    lib = _lib.load()
+    c, o, s, b = _lib.camera_struct(cam), opts.struct(), sph.struct(), bvh.struct()
+    _lib.check(lib.splat_trace_backward(ctypes.byref(b), ctypes.byref(s), ctypes.byref(c), ctypes.byref(o),
+                                        _ptr(out_rgba), _ptr(grad_rgba), ctypes.byref(g), _stream()))
+    return grads
+
+
+def render(rgba: torch.Tensor, depth: torch.Tensor, src_cam, dst_cam, radius_scale: float = 1.0,
+           half: bool = True, opts: TraceOptions | None = None):
+    """Whole client path: unproject -> build -> trace.  Returns (image, hits, spheres, bvh)."""
+    sph = unproject(src_cam, rgba, depth, radius_scale, half)
+    bvh = build_bvh(sph)
+    img, hits = trace(bvh, sph, dst_cam, opts)
+    return img, hits, sph, bvh

@@ -1,0 +1,110 @@
+"""Shared test helpers: oracle comparison with exemptions, BVH structure checks."""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+
+TOL = 1e-4  # max abs per RGBA channel against the FP64 oracle
+
+
+def compare(gpu_rgba, gpu_n, orc: dict, tol: float = TOL) -> dict:
+    """Element-wise comparison of GPU output with the oracle on the same pixels.
+
+    Exempt: a grazing sphere (|disc| <= 1e-6 r^2) before the end of the
+    composited range, or more than one knife-edge.  A pixel with one
+    knife-edge passes if it matches either branch.  Everything else must
+    agree within `tol` per channel with an identical hit count.
+    """
+    g = np.asarray(gpu_rgba, dtype=np.float64).reshape(-1, 4)
+    n = np.asarray(gpu_n).reshape(-1).astype(np.int64)
+    flags = orc["flags"]
+    exempt = (flags & (oracle.FLAG_GRAZE | oracle.FLAG_MULTI_KNIFE)) != 0
+    err_main = np.abs(g - orc["rgba"]).max(axis=1)
+    ok_main = (err_main <= tol) & (n == orc["n"])
+    err_alt = np.abs(g - orc["alt_rgba"]).max(axis=1)
+    ok_alt = (err_alt <= tol) & (n == orc["alt_n"]) & ((flags & oracle.FLAG_KNIFE) != 0)
+    ok = ok_main | ok_alt | exempt
+    bad = np.nonzero(~ok)[0]
+    strict = ~exempt
+    return {
+        "pixels": g.shape[0],
+        "exempt": int(exempt.sum()),
+        "knife": int(((flags & oracle.FLAG_KNIFE) != 0).sum()),
+        "bad": bad,
+        "max_err": float(np.where(strict, np.minimum(err_main, np.where(ok_alt, err_alt, np.inf)), 0).max())
+        if g.shape[0] else 0.0,
+        "hits_checked": int(n[strict].sum()),
+    }
+
+
+def assert_parity(stats: dict, exempt_frac: float | None = 1e-4, context: str = ""):
+    bad = stats["bad"]
+    assert bad.size == 0, f"{context}: {bad.size} mismatching pixels, first {bad[:10].tolist()}"
+    if exempt_frac is not None:
+        assert stats["exempt"] <= max(1, exempt_frac * stats["pixels"]), f"{context}: too many exempt {stats}"
+
+
+# ---------------------------------------------------------------- BVH layout
+
+def _align(x):
+    return (x + 255) & ~255
+
+
+def bvh_layout(cap: int) -> dict:
+    c = max(cap, 1)
+    nodes = 256
+    leaf_parent = _align(nodes + c * 64)
+    node_parent = _align(leaf_parent + c * 4)
+    leaf_ids = _align(node_parent + c * 4)
+    return {"nodes": nodes, "leaf_parent": leaf_parent, "node_parent": node_parent, "leaf_ids": leaf_ids}
+
+
+LEAF = 0x80000000
+EMPTY = 0xFFFFFFFF
+
+
+def check_bvh(mem: np.ndarray, cap: int, cr: np.ndarray, alpha: np.ndarray) -> dict:
+    """Structure of a built BVH: every sphere in exactly one leaf slot with its exact data,
+    every internal node reached once, boxes containing their children, sphere boxes
+    containing the exact spheres, depth bounded."""
+    mem = np.ascontiguousarray(mem).view(np.uint8)
+    n = int(mem[:4].view(np.uint32)[0])
+    assert n == cr.shape[0]
+    scene = mem[8:32].view(np.float32).astype(np.float64)
+    lay = bvh_layout(cap)
+    n_nodes = max(n - 1, 1)
+    f = mem[lay["nodes"]: lay["nodes"] + n_nodes * 64].view(np.float32).reshape(n_nodes, 16)
+    refs = f[:, 12:14].copy().view(np.uint32)
+    leaf_ids = mem[lay["leaf_ids"]: lay["leaf_ids"] + n * 4].view(np.uint32)
+    assert np.array_equal(np.sort(leaf_ids), np.arange(n, dtype=np.uint32)), "leaf ids are not a permutation"
+    seen_leaf = np.zeros(n, dtype=np.int64)
+    seen_node = np.zeros(n_nodes, dtype=np.int64)
+    c64 = cr.astype(np.float64)
+    # iterative walk from the root with its box
+    stack = [(0, scene[:3], scene[3:], 0)]
+    max_depth = 0
+    while stack:
+        node, lo, hi, depth = stack.pop()
+        max_depth = max(max_depth, depth)
+        seen_node[node] += 1
+        for side in range(2):
+            ref = int(refs[node, side])
+            s = f[node, 6 * side: 6 * side + 6].astype(np.float64)
+            if ref == EMPTY:
+                assert n == 1 and side == 1
+                continue
+            if ref & LEAF:
+                sid = ref & ~LEAF
+                seen_leaf[sid] += 1
+                assert np.array_equal(f[node, 6 * side: 6 * side + 4], cr[sid]), "leaf sphere data differs"
+                assert f[node, 6 * side + 4] == alpha[sid], "leaf alpha differs"
+                clo, chi = c64[sid, :3] - c64[sid, 3], c64[sid, :3] + c64[sid, 3]
+            else:
+                clo, chi = s[:3], s[3:]
+                stack.append((ref, clo, chi, depth + 1))
+            assert np.all(clo >= lo) and np.all(chi <= hi), f"child box escapes node {node}"
+    assert np.all(seen_leaf == 1), "a sphere is missing or duplicated"
+    assert np.all(seen_node == 1), "an internal node is unreachable or shared"
+    assert max_depth < 64
+    return {"n": n, "depth": max_depth, "leaf_ids": leaf_ids.copy()}

@@ -1,0 +1,126 @@
+"""The C-ABI library loads, exports every declared symbol, and rejects bad
+arguments on the host before touching a device.  CPU only: no compute call
+reaches a GPU here."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+from paper_2006_14726_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "splat.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(splat_[a-z_]+)\s*\(", text)))
+
+
+def test_header_and_binding_agree():
+    assert declared_functions() == sorted(_lib.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib.load()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert lib.splat_version() == 100
+
+
+def test_sizes_are_pure_host_functions():
+    lib = _lib.load()
+    assert lib.splat_bvh_bytes(1) >= 256 + 64
+    assert lib.splat_bvh_bytes(1 << 20) >= (1 << 20) * 64
+    assert lib.splat_workspace_bytes(_lib.SPLAT_OP_UNPROJECT, 0, 1024, 1024) >= 1024 * 4
+    assert lib.splat_workspace_bytes(_lib.SPLAT_OP_BUILD, 1 << 20, 0, 0) >= (1 << 20) * 16
+    assert lib.splat_workspace_bytes(_lib.SPLAT_OP_BATCHED, 4, 0, 0) >= 4
+    assert lib.splat_workspace_bytes(99, 1, 1, 1) == 0
+
+
+def test_struct_layouts_match_the_header():
+    assert ctypes.sizeof(_lib.splat_camera) == 13 * 8 + 2 * 4
+    assert ctypes.sizeof(_lib.splat_spheres) == 8 + 8 + 4 + 4 + 8 + 8 + 8
+    assert ctypes.sizeof(_lib.splat_trace_opts) == 32
+    assert ctypes.sizeof(_lib.splat_batch_job) == 3 * 8 + 2 * 4 + 112 + 2 * 8
+
+
+class _Cam:
+    eye = (0.0, 0.0, 2.0)
+    forward = (0.0, 0.0, -1.0)
+    right = (1.0, 0.0, 0.0)
+    up = (0.0, 1.0, 0.0)
+    tan_half_fov_y = 0.4
+    width = 8
+    height = 8
+
+
+def _err(code):
+    return code, _lib.load().splat_last_error().decode()
+
+
+def test_null_and_bad_arguments_fail_on_the_host():
+    lib = _lib.load()
+    cam = _lib.camera_struct(_Cam())
+    sph = _lib.splat_spheres()
+    code, msg = _err(lib.splat_unproject(None, None, None, 1.0, ctypes.byref(sph), None, 0, None))
+    assert code == _lib.SPLAT_EINVAL and "camera" in msg
+    code, msg = _err(lib.splat_unproject(ctypes.byref(cam), None, None, 1.0, ctypes.byref(sph), None, 0, None))
+    assert code == _lib.SPLAT_EINVAL
+    bad = _lib.camera_struct(_Cam())
+    bad.up[:] = [0.0, 1.0, 0.1]
+    fake = ctypes.c_void_p(4096)
+    code, msg = _err(lib.splat_unproject(ctypes.byref(bad), fake, fake, 1.0, ctypes.byref(sph), fake, 1 << 20, None))
+    assert code == _lib.SPLAT_EINVAL and "orthonormal" in msg
+    # capacity too small for the source image
+    sph.centre_radius, sph.rgba, sph.count, sph.capacity, sph.rgba_dtype = 4096, 4096, 4096, 10, _lib.SPLAT_F16
+    code, msg = _err(lib.splat_unproject(ctypes.byref(cam), fake, fake, 1.0, ctypes.byref(sph), fake, 1 << 20, None))
+    assert code == _lib.SPLAT_ENOSPC
+    sph.capacity = 64
+    code, msg = _err(lib.splat_unproject(ctypes.byref(cam), fake, fake, 1.0, ctypes.byref(sph), fake, 0, None))
+    assert code == _lib.SPLAT_ENOSPC and "workspace" in msg
+    sph.rgba_dtype = 7
+    code, _ = _err(lib.splat_unproject(ctypes.byref(cam), fake, fake, 1.0, ctypes.byref(sph), fake, 1 << 20, None))
+    assert code == _lib.SPLAT_EUNSUPPORTED
+
+
+def test_trace_option_validation():
+    lib = _lib.load()
+    cam = _lib.camera_struct(_Cam())
+    sph = _lib.splat_spheres()
+    sph.centre_radius, sph.rgba, sph.count, sph.capacity, sph.rgba_dtype = 4096, 4096, 4096, 64, _lib.SPLAT_F32
+    bvh = _lib.splat_bvh()
+    bvh.mem, bvh.capacity = 256 * 64, 64
+    out = ctypes.c_void_p(4096)
+    for kw, code in [({"kbuf": 3}, _lib.SPLAT_EUNSUPPORTED), ({"tile_w": 8, "tile_h": 4}, _lib.SPLAT_EUNSUPPORTED),
+                     ({"mode": 5}, _lib.SPLAT_EUNSUPPORTED), ({"alpha_stop": math.nan}, _lib.SPLAT_EINVAL),
+                     ({"t_max": 0.0}, _lib.SPLAT_EINVAL)]:
+        o = _lib.splat_trace_opts()
+        o.alpha_stop, o.t_max = 0.99, math.inf
+        for k, v in kw.items():
+            setattr(o, k, v)
+        got, msg = _err(lib.splat_trace(ctypes.byref(bvh), ctypes.byref(sph), ctypes.byref(cam), ctypes.byref(o),
+                                        out, None, None))
+        assert got == code, (kw, msg)
+    o = _lib.splat_trace_opts()
+    o.alpha_stop, o.t_max = 0.99, math.inf
+    bvh.mem = 256 * 64 + 4  # misaligned
+    got, msg = _err(lib.splat_trace(ctypes.byref(bvh), ctypes.byref(sph), ctypes.byref(cam), ctypes.byref(o), out,
+                                    None, None))
+    assert got == _lib.SPLAT_EINVAL and "aligned" in msg
+
+
+def test_no_device_is_reported_not_crashed():
+    """With valid arguments and no GPU in this container the call returns ENODEV."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    lib = _lib.load()
+    cam = _lib.camera_struct(_Cam())
+    sph = _lib.splat_spheres()
+    sph.centre_radius, sph.rgba, sph.count, sph.capacity, sph.rgba_dtype = 4096, 4096, 4096, 64, _lib.SPLAT_F32
+    fake = ctypes.c_void_p(4096)
+    code, msg = _err(lib.splat_unproject(ctypes.byref(cam), fake, fake, 1.0, ctypes.byref(sph), fake, 1 << 20, None))
+    assert code == _lib.SPLAT_ENODEV, msg

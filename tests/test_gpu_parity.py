@@ -1,0 +1,265 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Every input is seeded and synthetic; the oracle never consumes anything the
+GPU produced: trace parity feeds both sides the same sphere arrays (from the
+input generator or from the oracle's own unprojection), and the GPU's
+unprojection is compared with the oracle's separately.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from helpers import assert_parity, check_bvh, compare
+
+pytestmark = pytest.mark.gpu
+
+NEVER = 2.0
+
+
+@pytest.fixture(scope="module")
+def sp():
+    import paper_2006_14726_amd as sp
+    sp.load_library()
+    return sp
+
+
+def up(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def gpu_trace(sp, cr, col, cam, **opts):
+    sph = sp.spheres_from_tensors(up(cr), up(col))
+    bvh = sp.build_bvh(sph)
+    img, hits = sp.trace(bvh, sph, cam, sp.TraceOptions(**opts))
+    torch.cuda.synchronize()
+    return img.cpu().numpy().reshape(-1, 4), hits.cpu().numpy().reshape(-1), sph, bvh
+
+
+def ulp_diff(a, b):
+    ai = a.view(np.int32).astype(np.int64)
+    bi = b.view(np.int32).astype(np.int64)
+    return np.abs(ai - bi)
+
+
+# ---------------------------------------------------------------- unprojection
+
+@pytest.mark.parametrize("work,scale,half", [(synth.TINY, 1.0, False), (synth.CLIENT_FRAME, 1.0, True),
+                                             (synth.DIFF, 0.5, False)])
+def test_unproject_matches_oracle(sp, work, scale, half):
+    rgba, depth, src, _ = synth.source_image(work)
+    print(f"unproject {work.name} s={scale} half={half}", flush=True)
+    ocr, ocol, oidx = oracle.unproject(src, rgba, depth, scale, half)
+    s = sp.unproject(src, up(rgba), up(depth), scale, half)
+    torch.cuda.synchronize()
+    n = s.n()
+    assert n == len(oidx)
+    assert np.array_equal(s.src_index[:n].cpu().numpy().astype(np.uint32), oidx)
+    gcr = s.centre_radius[:n].cpu().numpy()
+    assert ulp_diff(gcr, ocr).max() <= 1, "centre/radius beyond 1 ulp"
+    gcol = s.rgba[:n].cpu().numpy()
+    assert np.array_equal(gcol.view(np.uint16 if half else np.uint32), ocol.view(np.uint16 if half else np.uint32))
+
+
+def test_unproject_invalid_pixels_are_dropped(sp):
+    rng = np.random.default_rng(4)
+    cam = synth.source_camera(37, 23)
+    rgba = rng.uniform(0.05, 0.4, size=(23, 37, 4)).astype(np.float32)
+    rgba[..., 3] = rng.uniform(0.5, 1.0, size=(23, 37))
+    depth = rng.uniform(1.5, 2.5, size=(23, 37)).astype(np.float32)
+    flat = depth.ravel()
+    flat[::5] = np.inf
+    flat[1::7] = np.nan
+    flat[2::11] = 0.0
+    flat[3::13] = -2.0
+    rgba.reshape(-1, 4)[4::17, 3] = 0.0
+    ocr, ocol, oidx = oracle.unproject(cam, rgba, depth, 1.0, True)
+    s = sp.unproject(cam, up(rgba), up(depth), 1.0, True)
+    n = s.n()
+    assert n == len(oidx) and np.array_equal(s.src_index[:n].cpu().numpy().astype(np.uint32), oidx)
+
+
+# ---------------------------------------------------------------- BVH
+
+@pytest.mark.parametrize("n", [1, 2, 3, 63, 64, 65, 2047, 2048, 2049, 5000])
+def test_bvh_structure(sp, n):
+    cr, col = synth.random_spheres(n, seed=100 + n)
+    print(f"bvh n={n}", flush=True)
+    sph = sp.spheres_from_tensors(up(cr), up(col))
+    bvh = sp.build_bvh(sph)
+    torch.cuda.synchronize()
+    info = check_bvh(bvh.mem.cpu().numpy(), bvh.capacity, cr, col[:, 3])
+    assert info["n"] == n
+
+
+def test_bvh_with_duplicate_codes(sp):
+    cr, col = synth.adversarial_spheres(3)
+    cr = np.concatenate([cr, np.repeat(cr[:1], 300, axis=0)])  # many identical Morton codes
+    col = np.concatenate([col, np.repeat(col[:1], 300, axis=0)])
+    sph = sp.spheres_from_tensors(up(cr), up(col))
+    bvh = sp.build_bvh(sph)
+    torch.cuda.synchronize()
+    check_bvh(bvh.mem.cpu().numpy(), bvh.capacity, cr, col[:, 3])
+
+
+def test_build_is_deterministic(sp):
+    """Bit-identical hierarchy over repeated builds (catches ordering races in sort and refit)."""
+    rgba, depth, src, _ = synth.source_image(synth.DIFF)
+    s = sp.unproject(src, up(rgba), up(depth), 1.0, False)
+    bvh = sp.build_bvh(s)
+    ref = bvh.mem.clone()
+    for _ in range(20):
+        sp.build_bvh(s, bvh)
+    torch.cuda.synchronize()
+    assert torch.equal(ref, bvh.mem)
+    n = s.n()
+    cr = s.centre_radius[:n].cpu().numpy()
+    col = s.rgba[:n].cpu().numpy()
+    check_bvh(bvh.mem.cpu().numpy(), bvh.capacity, cr, col[:, 3])
+
+
+def test_refit_matches_full_build(sp):
+    cr, col = synth.random_spheres(3000, seed=7)
+    sph = sp.spheres_from_tensors(up(cr), up(col))
+    bvh = sp.build_bvh(sph)
+    sph.centre_radius[:, 3] *= 1.5
+    sph.rgba[:, 3] *= 0.5
+    sp.build_bvh(sph, bvh, refit_only=True)
+    fresh = sp.build_bvh(sph)
+    torch.cuda.synchronize()
+    assert torch.equal(bvh.mem, fresh.mem)
+
+
+# ---------------------------------------------------------------- trace
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+@pytest.mark.parametrize("mode,stop", [(0, 0.99), (0, NEVER), (0, 0.0), (1, 0.99), (1, NEVER)])
+def test_trace_random_scenes(sp, seed, mode, stop):
+    cr, col = synth.random_spheres(200, seed=seed, r_lo=0.02, r_hi=0.12)
+    cam = synth.rotated_camera(synth.source_camera(45, 37), 8.0 * seed, 3.0)
+    print(f"random seed={seed} mode={mode} stop={stop}", flush=True)
+    g, n, _, _ = gpu_trace(sp, cr, col, cam, alpha_stop=stop, mode=mode)
+    orc = oracle.render(cr, col, cam, alpha_stop=stop, mode=mode)
+    st = compare(g, n, orc)
+    assert_parity(st, exempt_frac=None, context=f"seed {seed}")
+    assert st["exempt"] <= 3
+    assert st["hits_checked"] > (100 if stop == 0.0 else 200)
+
+
+@pytest.mark.parametrize("half", [False, True])
+def test_trace_adversarial_scene(sp, half):
+    cr, col = synth.adversarial_spheres(5)
+    if half:
+        col = synth.to_half_rgba(col)
+    cam = synth.rotated_camera(synth.source_camera(64, 48), 12.0, -4.0)
+    for stop in (0.99, NEVER):
+        g, n, _, _ = gpu_trace(sp, cr, col, cam, alpha_stop=stop)
+        st = compare(g, n, oracle.render(cr, col, cam, alpha_stop=stop))
+        assert_parity(st, exempt_frac=None, context=f"adversarial stop={stop}")
+
+
+def test_result_independent_of_kbuf_and_tile(sp):
+    """The hit buffer size and the tile shape change the schedule, never the image."""
+    cr, col = synth.random_spheres(400, seed=11, r_lo=0.03, r_hi=0.15)
+    cam = synth.rotated_camera(synth.source_camera(67, 45), 6.0, 2.0)
+    sph = sp.spheres_from_tensors(up(cr), up(col))
+    bvh = sp.build_bvh(sph)
+    ref = None
+    for stop in (0.99, NEVER):
+        ref = None
+        for k in (1, 2, 4, 8, 16):
+            for tile in ((8, 8), (16, 4), (32, 2)):
+                img, hits = sp.trace(bvh, sph, cam, sp.TraceOptions(alpha_stop=stop, kbuf=k, tile=tile))
+                if ref is None:
+                    ref = (img.clone(), hits.clone())
+                    if stop == NEVER:
+                        assert int(hits.max()) > 16  # several restarts at k = 1, 2, 4, 8
+                else:
+                    assert torch.equal(img, ref[0]) and torch.equal(hits, ref[1]), (k, tile)
+
+
+def test_tiny_config_full_frame(sp):
+    """64x64 source, radius = 1 footprint, target rotated 5 deg, all float32: every pixel."""
+    rgba, depth, src, dst = synth.source_image(synth.TINY)
+    cr, col, _ = oracle.unproject(src, rgba, depth, 1.0, False)
+    g, n, _, _ = gpu_trace(sp, cr, col, dst)
+    st = compare(g, n, oracle.render(cr, col, dst))
+    assert_parity(st, context="tiny")
+    assert st["hits_checked"] > 100
+
+
+@pytest.mark.parametrize("scale", [0.5, 1.0, 2.0])
+def test_client_frame_sampled(sp, scale):
+    """1024^2 source -> 1920x1080 after 10 deg yaw + 3 deg pitch, half colours, full-size launch;
+    the oracle checks one random pixel per 32x32 tile plus 512 random pixels."""
+    rgba, depth, src, dst = synth.source_image(synth.CLIENT_FRAME)
+    cr, col, _ = oracle.unproject(src, rgba, depth, scale, True)
+    print(f"client frame s={scale}: {len(cr)} spheres", flush=True)
+    g, n, _, _ = gpu_trace(sp, cr, col, dst)
+    rng = np.random.default_rng(int(scale * 10))
+    W, H = dst.width, dst.height
+    tx, ty = np.meshgrid(np.arange(0, W, 32), np.arange(0, H, 32))
+    px = np.minimum(tx + rng.integers(0, 32, tx.shape), W - 1)
+    py = np.minimum(ty + rng.integers(0, 32, ty.shape), H - 1)
+    pix = np.unique(np.concatenate([(py * W + px).ravel(), rng.integers(0, W * H, 512)]))
+    orc = oracle.render(cr, col, dst, pixels=pix)
+    st = compare(g[pix], n[pix], orc)
+    assert_parity(st, exempt_frac=1e-4, context=f"client s={scale}")
+    assert (n[pix] > 0).mean() > 0.3
+
+
+def test_identity_reprojection_on_gpu(sp):
+    rgba, depth, src, _ = synth.source_image(synth.TINY)
+    s = sp.unproject(src, up(rgba), up(depth), 0.01, False)
+    bvh = sp.build_bvh(s)
+    img, hits = sp.trace(bvh, s, src)
+    img = img.cpu().numpy()
+    has = np.isfinite(depth) & (depth > 0)
+    assert np.abs(img[has] - rgba[has]).max() <= 1e-6
+    assert np.all(img[~has] == 0)
+    assert np.all(hits.cpu().numpy()[has] == 1)
+
+
+def test_alpha_monotone_in_t_max_on_gpu(sp):
+    rgba, depth, src, dst = synth.source_image(synth.TINY)
+    s = sp.unproject(src, up(rgba), up(depth), 1.0, False)
+    bvh = sp.build_bvh(s)
+    prev = None
+    for t_max in (1.0, 1.9, 2.1, 2.3, 2.6, float("inf")):
+        img, _ = sp.trace(bvh, s, dst, sp.TraceOptions(t_max=t_max))
+        A = img[..., 3]
+        assert bool((img[..., :3] <= A[..., None] + 1e-6).all()) and bool((A <= 1 + 1e-6).all())
+        if prev is not None:
+            assert bool((A >= prev).all())
+        prev = A
+
+
+def test_empty_and_single_sphere(sp):
+    cam = synth.rotated_camera(synth.source_camera(19, 13), 3.0)
+    empty = sp.alloc_spheres(16, "cuda:0", half=False)
+    bvh = sp.build_bvh(empty)
+    img, hits = sp.trace(bvh, empty, cam)
+    assert float(img.abs().max()) == 0.0 and int(hits.max()) == 0
+    cr = np.array([[0.5, 0.5, 0.5, 0.2]], dtype=np.float32)
+    col = np.array([[0.2, 0.4, 0.6, 0.7]], dtype=np.float32)
+    g, n, _, _ = gpu_trace(sp, cr, col, cam)
+    assert_parity(compare(g, n, oracle.render(cr, col, cam)), exempt_frac=None)
+    assert n.max() == 1
+
+
+@pytest.mark.parametrize("w,h", [(1, 1), (7, 5), (65, 3), (3, 130)])
+def test_ragged_image_sizes(sp, w, h):
+    cr, col = synth.random_spheres(150, seed=w * h, r_lo=0.03, r_hi=0.15)
+    cam = synth.rotated_camera(synth.source_camera(w, h), 4.0)
+    for tile in ((8, 8), (32, 2)):
+        g, n, _, _ = gpu_trace(sp, cr, col, cam, tile=tile)
+        assert_parity(compare(g, n, oracle.render(cr, col, cam)), exempt_frac=None)
+
+
+def test_errors_on_device(sp):
+    cam = synth.source_camera(8, 8)
+    s = sp.alloc_spheres(10, "cuda:0")
+    with pytest.raises(sp.SplatError) as e:
+        sp.unproject(cam, up(np.zeros((8, 8, 4), np.float32)), up(np.zeros((8, 8), np.float32)), 1.0, out=s)
+    assert e.value.code == 2
