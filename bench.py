@@ -33,6 +33,8 @@ def parse():
     p.add_argument("--tile", type=str, default="8x8")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--no-bwd", action="store_true", help="skip the fwd+bwd measurement")
+    p.add_argument("--calib-copy-mib", type=int, default=0,
+                   help="run one plain device copy of this many MiB first (scales the HBM byte counters)")
     return p.parse_args()
 
 
@@ -57,6 +59,13 @@ def main():
 
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
+    if args.calib_copy_mib > 0:
+        n_words = args.calib_copy_mib * (1 << 20) // 4
+        a = torch.ones(n_words, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     work = synth.CLIENT_FRAME
     rgba_np, depth_np, src, dst = synth.source_image(work)
     rgba = torch.from_numpy(rgba_np).to(dev)

@@ -103,8 +103,11 @@ typedef struct splat_bvh {
  *   mode        SPLAT_ALPHA_CONSTANT or SPLAT_ALPHA_SOFT
  *   kbuf        hits gathered per traversal pass: 1, 2, 4, 8 or 16 (0 = 8);
  *               the result does not depend on it
- *   tile_w/h    pixels per 64-lane wavefront: 8x8, 16x4 or 32x2 (0 = 8x8);
- *               the result does not depend on it
+ *   tile_w/h    pixels per 64-lane wavefront: 8x8, 16x4, 32x2, 64x1 or 4x16
+ *               (0x0 = 8x8); the result does not depend on it
+ *   schedule    tile -> XCD assignment: 0 super-tiles of 8x8 tiles dealt
+ *               round robin to the XCDs, 1 one contiguous band per XCD; the
+ *               result does not depend on it
  */
 typedef struct splat_trace_opts {
     float alpha_stop;
@@ -113,7 +116,7 @@ typedef struct splat_trace_opts {
     int32_t kbuf;
     int32_t tile_w;
     int32_t tile_h;
-    int32_t reserved;
+    int32_t schedule;
 } splat_trace_opts;
 
 /* Per-sphere gradients, device float arrays indexed by sphere id; accumulated into (+=). */
@@ -190,7 +193,8 @@ int splat_trace(const splat_bvh *bvh, const splat_spheres *sph, const splat_came
  * dL/dr and dL/dc of every sphere into `grads` (+=; zero them first).  The
  * ordered hits are recomputed by a second traversal, not stored.  Radius
  * and centre gradients are zero in SPLAT_ALPHA_CONSTANT mode.
- *   out_rgba   device float4 [height][width]: the forward output of the same call
+ *   out_rgba   device float4 [height][width]: the forward output of the same
+ *              call (checked for NULL; the hits are recomputed, not read from it)
  *   grad_rgba  device float4 [height][width]
  */
 int splat_trace_backward(const splat_bvh *bvh, const splat_spheres *sph, const splat_camera *cam,

@@ -22,7 +22,8 @@ def build(verbose: bool = False, extra: list[str] | None = None, out: str = LIB)
     """Compile every csrc/*.hip into one shared library; raises on failure."""
     srcs = [os.path.join(CSRC, s) for s in SOURCES]
     tmp = out + ".tmp"
-    cmd = ["hipcc", *FLAGS, *(extra or []), "-o", tmp, *srcs]
+    include = os.path.join(os.path.dirname(HERE), "include")
+    cmd = ["hipcc", *FLAGS, "-I", include, *(extra or []), "-o", tmp, *srcs]
     if verbose:
         print(" ".join(cmd), file=sys.stderr)
     subprocess.check_call(cmd)

@@ -99,6 +99,8 @@ int resolve_opts(const splat_trace_opts *o, splat_trace_opts *out)
     if (!shape_ok) return fail(SPLAT_EUNSUPPORTED, "tile %dx%d is not a 64-pixel shape", out->tile_w, out->tile_h);
     if (out->mode != SPLAT_ALPHA_CONSTANT && out->mode != SPLAT_ALPHA_SOFT)
         return fail(SPLAT_EUNSUPPORTED, "unknown alpha mode %d", out->mode);
+    if (out->schedule != 0 && out->schedule != 1)
+        return fail(SPLAT_EUNSUPPORTED, "unknown schedule %d", out->schedule);
     if (std::isnan(out->alpha_stop)) return fail(SPLAT_EINVAL, "alpha_stop is NaN");
     if (!(out->t_max > 0)) return fail(SPLAT_EINVAL, "t_max must be positive");
     return SPLAT_OK;
@@ -191,6 +193,7 @@ static int trace_common(const splat_bvh *bvh, const splat_spheres *sph, const sp
     a.kbuf = o.kbuf;
     a.tile_w = o.tile_w;
     a.tile_h = o.tile_h;
+    a.schedule = o.schedule;
     return SPLAT_OK;
 }
 
@@ -218,7 +221,6 @@ int splat_trace_backward(const splat_bvh *bvh, const splat_spheres *sph, const s
     if (!grads || !grads->d_rgb || !grads->d_alpha) return fail(SPLAT_EINVAL, "grads d_rgb/d_alpha is NULL");
     if (a.mode == SPLAT_ALPHA_SOFT && (!grads->d_radius || !grads->d_centre))
         return fail(SPLAT_EINVAL, "soft mode needs d_radius and d_centre");
-    a.fwd = reinterpret_cast<const float4 *>(out_rgba);
     a.grad = reinterpret_cast<const float4 *>(grad_rgba);
     a.d_rgb = grads->d_rgb;
     a.d_alpha = grads->d_alpha;

@@ -125,29 +125,43 @@ k_sort_hist(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ coun
     for (int d = threadIdx.x; d < kSortBins; d += kSortBlock) hist[(size_t)d * tiles + blockIdx.x] = h[d];
 }
 
-// One block of 1024 threads: exclusive scan of data[0..n) in place; optional total.
-__global__ void __launch_bounds__(1024)
-k_scan_exclusive(uint32_t *__restrict__ data, uint32_t n)
+// One block per digit: exclusive scan of that digit's per-tile counts (a
+// contiguous row of the digit-major histogram) in place, and the digit total.
+__global__ void __launch_bounds__(256)
+k_scan_digits(uint32_t *__restrict__ hist, uint32_t tiles, uint32_t *__restrict__ totals)
 {
-    __shared__ uint32_t part[1024];
-    const uint32_t per = (n + 1023) / 1024;
-    const uint32_t lo = threadIdx.x * per, hi = min(n, lo + per);
-    uint32_t s = 0;
-    for (uint32_t i = lo; i < hi; ++i) s += data[i];
-    part[threadIdx.x] = s;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const uint32_t v = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0u;
+    __shared__ uint32_t wsum[4];
+    uint32_t *row = hist + (size_t)blockIdx.x * tiles;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t carry = 0;
+    for (uint32_t base = 0; base < tiles; base += 1024) {
+        uint32_t v[4], s = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t i = base + threadIdx.x * 4 + k;
+            v[k] = i < tiles ? row[i] : 0u;
+            s += v[k];
+        }
+        uint32_t incl = s;
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t o = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += o;
+        }
+        if (lane == 63) wsum[w] = incl;
         __syncthreads();
-        part[threadIdx.x] += v;
+        uint32_t before = carry;
+        for (int k = 0; k < w; ++k) before += wsum[k];
+        uint32_t run = before + incl - s;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t i = base + threadIdx.x * 4 + k;
+            if (i < tiles) row[i] = run;
+            run += v[k];
+        }
+        carry += wsum[0] + wsum[1] + wsum[2] + wsum[3];
         __syncthreads();
     }
-    uint32_t run = threadIdx.x ? part[threadIdx.x - 1] : 0u;
-    for (uint32_t i = lo; i < hi; ++i) {
-        const uint32_t c = data[i];
-        data[i] = run;
-        run += c;
-    }
+    if (threadIdx.x == 0) totals[blockIdx.x] = carry;
 }
 
 // Stable scatter of one tile.  Wave w owns the contiguous keys
@@ -156,12 +170,14 @@ k_scan_exclusive(uint32_t *__restrict__ data, uint32_t n)
 __global__ void __launch_bounds__(kSortBlock)
 k_sort_scatter(const uint32_t *__restrict__ keys_in, const uint32_t *__restrict__ vals_in,
                uint32_t *__restrict__ keys_out, uint32_t *__restrict__ vals_out, const uint32_t *__restrict__ count,
-               uint32_t cap, int shift, const uint32_t *__restrict__ hist, uint32_t tiles)
+               uint32_t cap, int shift, const uint32_t *__restrict__ hist, const uint32_t *__restrict__ totals,
+               uint32_t tiles)
 {
     constexpr int kWaves = kSortBlock / kWave;
     __shared__ uint32_t cnt[kWaves][kSortBins];
     __shared__ uint32_t local_start[kSortBins];
     __shared__ uint32_t global_start[kSortBins];
+    __shared__ uint32_t digit_base[kSortBins];
     __shared__ uint32_t skeys[kSortTile];
     __shared__ uint32_t svals[kSortTile];
 
@@ -203,21 +219,34 @@ k_sort_scatter(const uint32_t *__restrict__ keys_in, const uint32_t *__restrict_
             cnt[k][d] = run;
             run += t;
         }
-        local_start[d] = run;  // total, scanned below
-        global_start[d] = hist[(size_t)d * tiles + blockIdx.x];
+        local_start[d] = run;  // tile total of the digit, scanned below
+        digit_base[d] = totals[d];
     }
     __syncthreads();
     if (threadIdx.x < kWave) {
-        // exclusive scan of 256 digit totals by one wave: 4 per lane
-        uint32_t v[4], s = 0;
-        for (int k = 0; k < 4; ++k) { v[k] = local_start[threadIdx.x * 4 + k]; s += v[k]; }
-        uint32_t incl = s;
+        // exclusive scans over the 256 digits, by one wave, 4 digits per lane:
+        // of this tile's digit totals, and of the global digit totals
+        uint32_t v[4], u[4], s = 0, t = 0;
+        for (int k = 0; k < 4; ++k) {
+            v[k] = local_start[threadIdx.x * 4 + k];
+            u[k] = digit_base[threadIdx.x * 4 + k];
+            s += v[k];
+            t += u[k];
+        }
+        uint32_t incl = s, incl2 = t;
         for (int off = 1; off < kWave; off <<= 1) {
             const uint32_t o = __shfl_up(incl, off, kWave);
-            if (threadIdx.x >= (unsigned)off) incl += o;
+            const uint32_t o2 = __shfl_up(incl2, off, kWave);
+            if (threadIdx.x >= (unsigned)off) { incl += o; incl2 += o2; }
         }
-        uint32_t run = incl - s;
-        for (int k = 0; k < 4; ++k) { local_start[threadIdx.x * 4 + k] = run; run += v[k]; }
+        uint32_t run = incl - s, run2 = incl2 - t;
+        for (int k = 0; k < 4; ++k) {
+            const int d = threadIdx.x * 4 + k;
+            local_start[d] = run;
+            global_start[d] = run2 + hist[(size_t)d * tiles + blockIdx.x];
+            run += v[k];
+            run2 += u[k];
+        }
     }
     __syncthreads();
 #pragma unroll
@@ -258,7 +287,7 @@ __global__ void __launch_bounds__(256)
 k_karras(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ vals, const uint32_t *__restrict__ count,
          uint32_t cap,
          Node *__restrict__ nodes, uint32_t *__restrict__ leaf_parent, uint32_t *__restrict__ node_parent,
-         uint32_t *__restrict__ leaf_ids, uint32_t *__restrict__ flags)
+         uint32_t *__restrict__ leaf_ids, uint32_t *__restrict__ flags, uint2 *__restrict__ ranges)
 {
     const int n = (int)min(*count, cap);
     const int i = blockIdx.x * 256 + threadIdx.x;
@@ -271,6 +300,7 @@ k_karras(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ vals, c
         leaf_parent[0] = 0u;
         node_parent[0] = kEmpty;
         flags[0] = 0u;
+        ranges[0] = make_uint2(0u, 0u);
         return;
     }
     if (i >= n - 1) return;
@@ -291,6 +321,7 @@ k_karras(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ vals, c
     } while (t > 1);
     const int gamma = i + s * d + (d < 0 ? -1 : 0);
     const int lo = min(i, j), hi = max(i, j);
+    ranges[i] = make_uint2((uint32_t)lo, (uint32_t)hi);
     const bool left_leaf = lo == gamma, right_leaf = hi == gamma + 1;
     set_ref(nodes, i, 0, left_leaf ? (kLeafBit | vals[gamma]) : (uint32_t)gamma);
     set_ref(nodes, i, 1, right_leaf ? (kLeafBit | vals[gamma + 1]) : (uint32_t)(gamma + 1));
@@ -336,64 +367,111 @@ __device__ inline float sphere_alpha_a(const void *rgba, int half, uint32_t id)
     return reinterpret_cast<const float4 *>(rgba)[id].w;
 }
 
+// Box of node p from its two slots, written into its parent's slot (or the
+// header for the root).  Returns the parent reference (kEmpty at the root).
+__device__ inline uint32_t lift_box(Node *nodes, uint32_t p, const uint32_t *__restrict__ node_parent,
+                                    BvhHeader *__restrict__ hdr)
+{
+    const Node nd = nodes[p];
+    float lo0[3], hi0[3], lo1[3], hi1[3];
+    slot_box(nd, 0, lo0, hi0);
+    slot_box(nd, 1, lo1, hi1);
+    float lo[3], hi[3];
+    for (int k = 0; k < 3; ++k) { lo[k] = fminf(lo0[k], lo1[k]); hi[k] = fmaxf(hi0[k], hi1[k]); }
+    const uint32_t pp = node_parent[p];
+    if (pp == kEmpty) {
+        for (int k = 0; k < 3; ++k) { hdr->scene_lo[k] = lo[k]; hdr->scene_hi[k] = hi[k]; }
+        return kEmpty;
+    }
+    float *s = nodes[pp >> 1].f + 6 * (pp & 1u);
+    s[0] = lo[0]; s[1] = lo[1]; s[2] = lo[2]; s[3] = hi[0]; s[4] = hi[1]; s[5] = hi[2];
+    return pp;
+}
+
+// Refit, phase 1: one workgroup per chunk of kRefitChunk sorted leaves.  A
+// node whose leaf range lies inside the chunk has both subtrees in this
+// workgroup, so the second-arrival handshake needs only workgroup scope.  A
+// thread that reaches a node whose range crosses the chunk records the
+// arrival for phase 2 and stops.
 __global__ void __launch_bounds__(256)
-k_refit(const float4 *__restrict__ cr, const void *__restrict__ rgba, int half, const uint32_t *__restrict__ count,
-        uint32_t cap,
-        Node *nodes, const uint32_t *__restrict__ leaf_parent, const uint32_t *__restrict__ node_parent,
-        const uint32_t *__restrict__ leaf_ids, uint32_t *flags, BvhHeader *__restrict__ hdr)
+k_refit_local(const float4 *__restrict__ cr, const void *__restrict__ rgba, int half,
+              const uint32_t *__restrict__ count, uint32_t cap, Node *nodes, const uint32_t *__restrict__ leaf_parent,
+              const uint32_t *__restrict__ node_parent, const uint32_t *__restrict__ leaf_ids, uint32_t *flags,
+              const uint2 *__restrict__ ranges, uint32_t *__restrict__ cross, BvhHeader *hdr)
 {
     const uint32_t n = min(*count, cap);
     const uint32_t n_nodes = n > 1 ? n - 1 : 1;
-    const uint32_t j = blockIdx.x * 256 + threadIdx.x;
-    if (j >= n) return;
-    const uint32_t id = leaf_ids[j];
-    if (id >= n) return;  // only after a refit of a hierarchy that was never built
-    const float4 c = cr[id];
-    const float a = sphere_alpha_a(rgba, half, id);
-    uint32_t pp = leaf_parent[j];
-    uint32_t p = pp >> 1;
-    if (p >= n_nodes) return;
-    {
-        float *s = nodes[p].f + 6 * (pp & 1u);
-        s[0] = c.x; s[1] = c.y; s[2] = c.z; s[3] = c.w; s[4] = a; s[5] = 0.0f;
-    }
-    if (n == 1) {
-        float *s = nodes[0].f + 6;
-        for (int k = 0; k < 3; ++k) { s[k] = INFINITY; s[3 + k] = -INFINITY; }
-        const float ctr[3] = {c.x, c.y, c.z};
-        for (int k = 0; k < 3; ++k) {
-            hdr->scene_lo[k] = nextafterf(ctr[k] - c.w, -INFINITY);
-            hdr->scene_hi[k] = nextafterf(ctr[k] + c.w, INFINITY);
+    const uint32_t c_lo = blockIdx.x * kRefitChunk;
+    if (c_lo >= n) return;
+    const uint32_t c_hi = min(c_lo + kRefitChunk, n) - 1;
+    for (uint32_t j = c_lo + threadIdx.x; j <= c_hi; j += 256) {
+        const uint32_t id = leaf_ids[j];
+        if (id >= n) continue;  // only after a refit of a hierarchy that was never built
+        const float4 c = cr[id];
+        const float a = sphere_alpha_a(rgba, half, id);
+        const uint32_t pp = leaf_parent[j];
+        uint32_t p = pp >> 1;
+        if (p >= n_nodes) continue;
+        {
+            float *s = nodes[p].f + 6 * (pp & 1u);
+            s[0] = c.x; s[1] = c.y; s[2] = c.z; s[3] = c.w; s[4] = a; s[5] = 0.0f;
         }
-        return;
-    }
-    for (;;) {
-        const uint32_t old = __hip_atomic_fetch_add(&flags[p], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        // first arrival: the sibling subtree is not finished yet and its thread
-        // continues; a count above 1 only occurs in a corrupt hierarchy
-        if (old != 1u) return;
-        const Node nd = nodes[p];
-        float lo0[3], hi0[3], lo1[3], hi1[3];
-        slot_box(nd, 0, lo0, hi0);
-        slot_box(nd, 1, lo1, hi1);
-        float lo[3], hi[3];
-        for (int k = 0; k < 3; ++k) { lo[k] = fminf(lo0[k], lo1[k]); hi[k] = fmaxf(hi0[k], hi1[k]); }
-        pp = node_parent[p];
-        if (pp == kEmpty) {
-            for (int k = 0; k < 3; ++k) { hdr->scene_lo[k] = lo[k]; hdr->scene_hi[k] = hi[k]; }
-            return;
+        if (n == 1) {
+            float *s = nodes[0].f + 6;
+            for (int k = 0; k < 3; ++k) { s[k] = INFINITY; s[3 + k] = -INFINITY; }
+            lift_box(nodes, 0, node_parent, hdr);
+            continue;
         }
-        p = pp >> 1;
-        if (p >= n_nodes) return;
-        float *s = nodes[p].f + 6 * (pp & 1u);
-        s[0] = lo[0]; s[1] = lo[1]; s[2] = lo[2]; s[3] = hi[0]; s[4] = hi[1]; s[5] = hi[2];
+        for (;;) {
+            const uint2 r = ranges[p];
+            if (r.x < c_lo || r.y > c_hi) {
+                const uint32_t e = __hip_atomic_fetch_add(&hdr->n_cross, 1u, __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_AGENT);
+                if (e < 2 * cap) cross[e] = p;
+                break;
+            }
+            const uint32_t old = __hip_atomic_fetch_add(&flags[p], 1u, __ATOMIC_ACQ_REL,
+                                                        __HIP_MEMORY_SCOPE_WORKGROUP);
+            // first arrival: the sibling subtree is not finished and its thread
+            // continues; a count above 1 only occurs in a corrupt hierarchy
+            if (old != 1u) break;
+            const uint32_t up = lift_box(nodes, p, node_parent, hdr);
+            if (up == kEmpty) break;
+            p = up >> 1;
+            if (p >= n_nodes) break;
+        }
     }
 }
 
-// An empty sphere set: header n = 0 so that tracing returns background.
+// Refit, phase 2: one workgroup finishes the nodes whose range crosses a
+// chunk, starting from the arrivals recorded in phase 1.
+__global__ void __launch_bounds__(1024)
+k_refit_top(const uint32_t *__restrict__ count, uint32_t cap, Node *nodes, const uint32_t *__restrict__ node_parent,
+            uint32_t *flags, const uint32_t *__restrict__ cross, BvhHeader *hdr)
+{
+    const uint32_t n = min(*count, cap);
+    const uint32_t n_nodes = n > 1 ? n - 1 : 1;
+    const uint32_t m = min(hdr->n_cross, 2 * cap);
+    for (uint32_t e = threadIdx.x; e < m; e += 1024) {
+        uint32_t p = cross[e];
+        while (p < n_nodes) {
+            const uint32_t old = __hip_atomic_fetch_add(&flags[p], 1u, __ATOMIC_ACQ_REL,
+                                                        __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (old != 1u) break;
+            const uint32_t up = lift_box(nodes, p, node_parent, hdr);
+            if (up == kEmpty) break;
+            p = up >> 1;
+        }
+    }
+}
+
+// Header count (an empty sphere set traces as background) and the refit list reset.
 __global__ void k_header_count(const uint32_t *__restrict__ count, uint32_t cap, BvhHeader *__restrict__ hdr)
 {
-    if (threadIdx.x == 0) hdr->n = min(*count, cap);
+    if (threadIdx.x == 0) {
+        hdr->n = min(*count, cap);
+        hdr->n_cross = 0u;
+    }
 }
 
 hipError_t launch_build(const splat_spheres &sph, const splat_bvh &bvh, bool refit_only, void *ws, hipStream_t s)
@@ -407,9 +485,12 @@ hipError_t launch_build(const splat_spheres &sph, const splat_bvh &bvh, bool ref
     uint32_t *node_parent = reinterpret_cast<uint32_t *>(mem + L.node_parent);
     uint32_t *leaf_ids = reinterpret_cast<uint32_t *>(mem + L.leaf_ids);
     uint32_t *flags = reinterpret_cast<uint32_t *>(mem + L.flags);
+    uint2 *ranges = reinterpret_cast<uint2 *>(mem + L.ranges);
+    uint32_t *cross = reinterpret_cast<uint32_t *>(mem + L.cross);
     const float4 *cr = reinterpret_cast<const float4 *>(sph.centre_radius);
     const int half = sph.rgba_dtype == SPLAT_F16;
     const uint32_t blocks = (cap + 255) / 256 > 0 ? (cap + 255) / 256 : 1;
+    const uint32_t chunks = (cap + kRefitChunk - 1) / kRefitChunk > 0 ? (cap + kRefitChunk - 1) / kRefitChunk : 1;
 
     hipLaunchKernelGGL(k_header_count, dim3(1), dim3(64), 0, s, sph.count, cap, hdr);
     if (!refit_only) {
@@ -418,25 +499,27 @@ hipError_t launch_build(const splat_spheres &sph, const splat_bvh &bvh, bool ref
         uint32_t *ka = reinterpret_cast<uint32_t *>(w + B.keys_a), *va = reinterpret_cast<uint32_t *>(w + B.vals_a);
         uint32_t *kb = reinterpret_cast<uint32_t *>(w + B.keys_b), *vb = reinterpret_cast<uint32_t *>(w + B.vals_b);
         uint32_t *hist = reinterpret_cast<uint32_t *>(w + B.hist);
+        uint32_t *totals = reinterpret_cast<uint32_t *>(w + B.totals);
         float *partial = reinterpret_cast<float *>(w + B.partial);
         hipLaunchKernelGGL(k_bounds_partial, dim3(kBoundsBlocks), dim3(256), 0, s, cr, sph.count, cap, partial);
         hipLaunchKernelGGL(k_morton, dim3(blocks), dim3(256), 0, s, cr, sph.count, cap, partial, hdr, ka, va);
         for (int shift = 0; shift < kMortonBits; shift += kSortBits) {
             hipLaunchKernelGGL(k_sort_hist, dim3(B.tiles), dim3(kSortBlock), 0, s, ka, sph.count, cap, shift, hist,
                                B.tiles);
-            hipLaunchKernelGGL(k_scan_exclusive, dim3(1), dim3(1024), 0, s, hist, (uint32_t)kSortBins * B.tiles);
-            hipLaunchKernelGGL(k_sort_scatter, dim3(B.tiles), dim3(kSortBlock), 0, s, ka, va, kb, vb, sph.count, cap, shift,
-                               hist, B.tiles);
+            hipLaunchKernelGGL(k_scan_digits, dim3(kSortBins), dim3(256), 0, s, hist, B.tiles, totals);
+            hipLaunchKernelGGL(k_sort_scatter, dim3(B.tiles), dim3(kSortBlock), 0, s, ka, va, kb, vb, sph.count, cap,
+                               shift, hist, totals, B.tiles);
             uint32_t *t = ka; ka = kb; kb = t;
             t = va; va = vb; vb = t;
         }
         hipLaunchKernelGGL(k_karras, dim3(blocks), dim3(256), 0, s, ka, va, sph.count, cap, nodes, leaf_parent,
-                           node_parent, leaf_ids, flags);
+                           node_parent, leaf_ids, flags, ranges);
     } else {
         hipLaunchKernelGGL(k_zero_flags, dim3(blocks), dim3(256), 0, s, flags, sph.count, cap);
     }
-    hipLaunchKernelGGL(k_refit, dim3(blocks), dim3(256), 0, s, cr, sph.rgba, half, sph.count, cap, nodes, leaf_parent,
-                       node_parent, leaf_ids, flags, hdr);
+    hipLaunchKernelGGL(k_refit_local, dim3(chunks), dim3(256), 0, s, cr, sph.rgba, half, sph.count, cap, nodes,
+                       leaf_parent, node_parent, leaf_ids, flags, ranges, cross, hdr);
+    hipLaunchKernelGGL(k_refit_top, dim3(1), dim3(1024), 0, s, sph.count, cap, nodes, node_parent, flags, cross, hdr);
     return hipGetLastError();
 }
 

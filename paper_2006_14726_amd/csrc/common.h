@@ -4,7 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include "../../include/splat.h"
+#include "splat.h"
 
 namespace splat {
 
@@ -114,7 +114,7 @@ struct __align__(64) Node {
 
 struct __align__(256) BvhHeader {
     uint32_t n;            // spheres at build time
-    uint32_t pad0;
+    uint32_t n_cross;      // refit: entries in the list of chunk-crossing arrivals
     float scene_lo[3];     // box of all leaves (root box)
     float scene_hi[3];
     float cen_lo[3];       // bounds of the centres (Morton quantisation)
@@ -127,7 +127,7 @@ __host__ __device__ inline size_t align256(size_t x) { return (x + 255) & ~(size
 
 // Offsets inside splat_bvh.mem.
 struct BvhLayout {
-    size_t header, nodes, leaf_parent, node_parent, leaf_ids, flags, total;
+    size_t header, nodes, leaf_parent, node_parent, leaf_ids, flags, ranges, cross, total;
     __host__ __device__ explicit BvhLayout(uint32_t cap)
     {
         const size_t c = cap < 1 ? 1 : cap;
@@ -137,7 +137,9 @@ struct BvhLayout {
         node_parent = align256(leaf_parent + c * 4);
         leaf_ids = align256(node_parent + c * 4);
         flags = align256(leaf_ids + c * 4);
-        total = align256(flags + c * 4);
+        ranges = align256(flags + c * 4);       // first/last sorted leaf of each internal node
+        cross = align256(ranges + c * 8);       // refit arrivals at chunk-crossing nodes
+        total = align256(cross + c * 8);
     }
 };
 
@@ -149,8 +151,10 @@ constexpr int kSortItems = 8;                    // keys per thread
 constexpr int kSortTile = kSortBlock * kSortItems;
 constexpr int kMortonBits = 30;
 
+constexpr int kRefitChunk = 2048;                // leaves refit by one workgroup
+
 struct BuildLayout {
-    size_t keys_a, vals_a, keys_b, vals_b, hist, partial, total;
+    size_t keys_a, vals_a, keys_b, vals_b, hist, partial, totals, total;
     uint32_t tiles;
     __host__ __device__ explicit BuildLayout(uint32_t cap)
     {
@@ -162,7 +166,8 @@ struct BuildLayout {
         vals_b = align256(keys_b + c * 4);
         hist = align256(vals_b + c * 4);
         partial = align256(hist + (size_t)kSortBins * tiles * 4);
-        total = align256(partial + 1024 * 8 * sizeof(float));
+        totals = align256(partial + 1024 * 8 * sizeof(float));
+        total = align256(totals + kSortBins * 4);
     }
 };
 

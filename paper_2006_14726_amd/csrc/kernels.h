@@ -17,10 +17,10 @@ struct TraceArgs {
     double t_max;
     int32_t kbuf;
     int32_t tile_w, tile_h;
+    int32_t schedule;           // tile -> XCD assignment (0 super-tiles, 1 bands)
     float4 *out;                // forward output
     uint32_t *hits;             // nullable
     // backward only
-    const float4 *fwd;          // forward output of the same call
     const float4 *grad;         // dL/d out
     float *d_rgb, *d_alpha, *d_radius, *d_centre;
 };

@@ -5,17 +5,18 @@
 // One 64-lane wavefront traces one tile of pixels as a packet: the BVH walk
 // is wave-uniform (node fetched once per wave with scalar loads, stack of
 // node indices in LDS, a child is visited if any lane's ray meets its box),
-// while each lane keeps its own ordered hit buffer.  Per traversal pass a
-// lane gathers the K hits with the smallest keys (t0, sphere id) greater than
-// the last key it composited; nodes beyond the K-th key, or beyond the hit
-// at which the alpha stop is already certain, are pruned.  If a pass fills
-// the buffer without reaching the stop, the lane composites it and runs
-// another pass from its last key, so there is no cap on hits and the result
-// does not depend on K, the tile shape or the other lanes of the wave.
+// while each lane gathers its own hits.  Per traversal pass a lane keeps the
+// K hits with the smallest keys (t0, sphere id) greater than the last key it
+// composited, in an unsorted LDS buffer of its own; once the buffer is full,
+// nodes beyond its largest key are pruned.  The buffer is sorted once at the
+// end of the pass and composited; if it was full and the alpha stop was not
+// reached, the lane runs another pass from its last key.  So there is no cap
+// on hits, and the result depends neither on K, nor on the tile shape, nor
+// on the other lanes of the wave.
 //
-// Precision: ray and sphere test in double (exact enough to settle hits at
-// relative discriminants far below 1e-6), keys in double, boxes in float
-// with a conservative margin, compositing in float with explicitly rounded
+// Precision: ray and sphere test in double (hits are settled far below a
+// relative discriminant of 1e-6), keys in double, boxes in float with a
+// conservative margin, compositing in float with explicitly rounded
 // operations so that every pass performs the same arithmetic.
 #include "common.h"
 #include "kernels.h"
@@ -25,18 +26,13 @@ namespace splat {
 // ---------------------------------------------------------------- helpers
 
 __device__ inline uint32_t ufirst(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
-__device__ inline float ffirst(float v) { return __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(v))); }
 
-struct Key {
-    double t;
-    uint32_t id;
-};
 __device__ inline bool key_less(double ta, uint32_t ia, double tb, uint32_t ib)
 {
     return ta < tb || (ta == tb && ia < ib);
 }
 
-// One compositing step; the alpha part is shared by pruning and compositing.
+// One compositing step of the alpha channel.
 __device__ inline void alpha_step(float alpha, float &A, float &T, float &w)
 {
     w = __fmul_rn(T, alpha);
@@ -53,6 +49,11 @@ __device__ inline float4 load_colour(const void *rgba, int half, uint32_t id)
     return reinterpret_cast<const float4 *>(rgba)[id];
 }
 
+__device__ inline double wdot(const float4 &k, const float4 &g)
+{
+    return (double)k.x * g.x + (double)k.y * g.y + (double)k.z * g.z + (double)g.w;
+}
+
 // Per-lane ray state.
 struct Ray {
     double d[3];     // unit direction, double
@@ -65,14 +66,23 @@ struct Eye {
     double o[3];
     float of[3];
     float oP[3], oM[3];  // float eye moved by +margin / -margin (padded-box slab test)
-    float E;             // bound on float sphere-distance error
+    float E;             // bound on the float ray-to-centre distance error
+};
+
+// LDS of one wave: hit buffers (column per lane) and the traversal stack.
+template <int K>
+struct WaveLds {
+    double t[K][kWave];     // hit distance; in the backward, the transmittance before the hit
+    uint32_t id[K][kWave];
+    float al[K][kWave];
+    uint32_t stack[64];
 };
 
 // ---------------------------------------------------------------- one tile
 
 template <int K, bool BWD>
 __device__ void trace_tile(const TraceArgs &a, const Node *__restrict__ nodes, const BvhHeader *__restrict__ hdr,
-                           int tile_x, int tile_y, uint32_t *stack)
+                           int tile_x, int tile_y, WaveLds<K> &L)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int px = tile_x * a.tile_w + (lane % a.tile_w);
@@ -129,29 +139,24 @@ __device__ void trace_tile(const TraceArgs &a, const Node *__restrict__ nodes, c
     uint32_t lo_id = 0xffffffffu;
     bool active = inside && n_spheres > 0;
 
-    // backward state
+    // backward state.  A pixel whose hits fit one pass gets its gradients
+    // back to front from that pass alone.  Otherwise (phase 1) the remaining
+    // passes first sum G = sum_j T_j alpha_j w_j in double; then (phase 2)
+    // the passes are repeated from the first hit, and the remainder behind
+    // each pass is (G - P) / T with the prefix P and T in double.
     float4 g = make_float4(0, 0, 0, 0);
-    float G = 0.0f, P = 0.0f;  // total and running sum of T alpha (k.gC + gA)
-    if (BWD && inside) {
-        g = a.grad[(size_t)py * a.cam.w + px];
-        const float4 f = a.fwd[(size_t)py * a.cam.w + px];
-        G = f.x * g.x + f.y * g.y + f.z * g.z + f.w * g.w;
-    }
+    int phase = 0;
+    double G64 = 0.0, P64 = 0.0, T64 = 1.0;
+    if (BWD && inside) g = a.grad[(size_t)py * a.cam.w + px];
 
     while (__ballot(active)) {
         // ---- one traversal pass
-        double kt[K];
-        uint32_t kid[K];
-        float kal[K];
-#pragma unroll
-        for (int j = 0; j < K; ++j) { kt[j] = INFINITY; kid[j] = 0xffffffffu; kal[j] = 0.0f; }
-        uint32_t m = 0;
-        double pr_t = active ? a.t_max : -1.0;  // prune key
+        uint32_t m = 0, mx = 0;                  // buffered hits; slot of the largest once full
+        double pr_t = active ? a.t_max : -1.0;   // prune key: hits must be below it
         uint32_t pr_id = 0;
         float pr_f = active ? (float)(pr_t * (1.0 + 0x1p-20)) : -INFINITY;
         if (active && !(pr_f < INFINITY)) pr_f = INFINITY;
         const float lo_f = (float)(lo_t * (1.0 - 0x1p-20));
-        const float A0 = A, T0 = T;
 
         int sp = 0;
         uint32_t node = 0;
@@ -196,36 +201,26 @@ __device__ void trace_tile(const TraceArgs &a, const Node *__restrict__ nodes, c
                         const double u = q / (r * r);
                         al = (float)((double)s[4] * (1.0 - u) * (1.0 - u));
                     }
-                    // insert into the sorted buffer
-#pragma unroll
-                    for (int j = K - 1; j >= 1; --j) {
-                        const bool shift = key_less(t0, id, kt[j - 1], kid[j - 1]);
-                        const bool here = !shift && key_less(t0, id, kt[j], kid[j]);
-                        kt[j] = shift ? kt[j - 1] : (here ? t0 : kt[j]);
-                        kid[j] = shift ? kid[j - 1] : (here ? id : kid[j]);
-                        kal[j] = shift ? kal[j - 1] : (here ? al : kal[j]);
-                    }
-                    if (key_less(t0, id, kt[0], kid[0])) { kt[0] = t0; kid[0] = id; kal[0] = al; }
-                    m = m < K ? m + 1 : K;
-                    // new prune key: the hit at which the stop is certain, else the K-th
-                    double nt = m == K ? kt[K - 1] : a.t_max;
-                    uint32_t ni = m == K ? kid[K - 1] : 0u;
-                    float As = A0, Ts = T0, w;
-#pragma unroll
-                    for (int j = 0; j < K; ++j) {
-                        if ((uint32_t)j < m) {
-                            alpha_step(kal[j], As, Ts, w);
-                            if (As >= stop) {
-                                nt = kt[j];
-                                ni = kid[j];
-                                break;
-                            }
+                    // append, or replace the largest key of a full buffer
+                    const uint32_t slot = m < K ? m : mx;
+                    L.t[slot][lane] = t0;
+                    L.id[slot][lane] = id;
+                    L.al[slot][lane] = al;
+                    if (m < K) ++m;
+                    if (m == K) {
+                        // the largest buffered key becomes the prune key
+                        double bt = -1.0;
+                        uint32_t bi = 0, bj = 0;
+                        for (int j = 0; j < K; ++j) {
+                            const double tj = L.t[j][lane];
+                            const uint32_t ij = L.id[j][lane];
+                            if (key_less(bt, bi, tj, ij)) { bt = tj; bi = ij; bj = (uint32_t)j; }
                         }
+                        mx = bj;
+                        pr_t = bt;
+                        pr_id = bi;
+                        pr_f = (float)(pr_t * (1.0 + 0x1p-20));
                     }
-                    pr_t = nt;
-                    pr_id = ni;
-                    pr_f = (float)(pr_t * (1.0 + 0x1p-20));
-                    if (!(pr_f < INFINITY)) pr_f = INFINITY;
                 } else {
                     // padded-box slab test in float
                     const float t1x = (s[0] - eye.oP[0]) * ray.inv[0], t2x = (s[3] - eye.oM[0]) * ray.inv[0];
@@ -243,7 +238,7 @@ __device__ void trace_tile(const TraceArgs &a, const Node *__restrict__ nodes, c
                 const bool second_first = axis < 3 && ((neg_mask >> axis) & 1u);
                 // depth <= 63 for 62-bit (code, position) keys, so 64 slots never overflow
                 if (sp < 64) {
-                    if (lane == 0) stack[sp] = second_first ? r0 : r1;
+                    if (lane == 0) L.stack[sp] = second_first ? r0 : r1;
                     ++sp;
                 }
                 node = second_first ? r1 : r0;
@@ -254,85 +249,113 @@ __device__ void trace_tile(const TraceArgs &a, const Node *__restrict__ nodes, c
             } else {
                 if (sp == 0) break;
                 --sp;
-                node = ufirst(stack[sp]);
+                node = ufirst(L.stack[sp]);
             }
         }
 
+        if (!active) continue;
+        // ---- sort this pass's hits by key (insertion sort of the lane's column)
+        for (uint32_t i = 1; i < m; ++i) {
+            const double ti = L.t[i][lane];
+            const uint32_t ii = L.id[i][lane];
+            const float ai = L.al[i][lane];
+            uint32_t j = i;
+            while (j > 0 && key_less(ti, ii, L.t[j - 1][lane], L.id[j - 1][lane])) {
+                L.t[j][lane] = L.t[j - 1][lane];
+                L.id[j][lane] = L.id[j - 1][lane];
+                L.al[j][lane] = L.al[j - 1][lane];
+                --j;
+            }
+            L.t[j][lane] = ti;
+            L.id[j][lane] = ii;
+            L.al[j][lane] = ai;
+        }
+        const double last_t = m ? L.t[m - 1][lane] : 0.0;
+        const uint32_t last_id = m ? L.id[m - 1][lane] : 0u;
+
         // ---- composite this pass
-        if (active) {
-            bool done = false;
-            uint32_t used = 0;
-            float Tj[K];
-            float4 col[K];
-#pragma unroll
-            for (int j = 0; j < K; ++j) {
-                if ((uint32_t)j < m && !done) {
-                    col[j] = load_colour(a.rgba, half, kid[j]);
-                    Tj[j] = T;
-                    float w;
-                    alpha_step(kal[j], A, T, w);
-                    C[0] = __fadd_rn(C[0], __fmul_rn(w, col[j].x));
-                    C[1] = __fadd_rn(C[1], __fmul_rn(w, col[j].y));
-                    C[2] = __fadd_rn(C[2], __fmul_rn(w, col[j].z));
-                    ++n_hit;
-                    ++used;
-                    if (A >= stop) done = true;
-                }
-            }
-            const bool more = !done && m == K;
+        bool done = false;
+        uint32_t used = 0;
+        for (uint32_t j = 0; j < m && !done; ++j) {
+            const uint32_t id = L.id[j][lane];
+            const float al = L.al[j][lane];
+            const float4 col = load_colour(a.rgba, half, id);
+            float w;
+            alpha_step(al, A, T, w);
+            C[0] = __fadd_rn(C[0], __fmul_rn(w, col.x));
+            C[1] = __fadd_rn(C[1], __fmul_rn(w, col.y));
+            C[2] = __fadd_rn(C[2], __fmul_rn(w, col.z));
             if (BWD) {
-                // remainder behind the last hit of this pass, from full transmittance
-                float Pend = P;
-#pragma unroll
-                for (int j = 0; j < K; ++j) {
-                    if ((uint32_t)j < used) {
-                        const float wj = col[j].x * g.x + col[j].y * g.y + col[j].z * g.z + g.w;
-                        Pend += Tj[j] * kal[j] * wj;
-                    }
-                }
-                float R = more && T > 0.0f ? (G - Pend) / T : 0.0f;
-#pragma unroll
-                for (int j = K - 1; j >= 0; --j) {
-                    if ((uint32_t)j < used) {
-                        const uint32_t id = kid[j];
-                        const float al = kal[j];
-                        const float wj = col[j].x * g.x + col[j].y * g.y + col[j].z * g.z + g.w;
-                        const float dal = Tj[j] * (wj - R);
-                        const float ta = Tj[j] * al;
-                        unsafeAtomicAdd(&a.d_rgb[3 * (size_t)id + 0], ta * g.x);
-                        unsafeAtomicAdd(&a.d_rgb[3 * (size_t)id + 1], ta * g.y);
-                        unsafeAtomicAdd(&a.d_rgb[3 * (size_t)id + 2], ta * g.z);
-                        if (!soft) {
-                            unsafeAtomicAdd(&a.d_alpha[id], dal);
-                        } else {
-                            const float4 c = a.centre_radius[id];
-                            const double oc0 = (double)c.x - eye.o[0], oc1 = (double)c.y - eye.o[1],
-                                         oc2 = (double)c.z - eye.o[2];
-                            const double b = oc0 * ray.d[0] + oc1 * ray.d[1] + oc2 * ray.d[2];
-                            const double v0 = oc0 - b * ray.d[0], v1 = oc1 - b * ray.d[1], v2 = oc2 - b * ray.d[2];
-                            const double q = v0 * v0 + v1 * v1 + v2 * v2;
-                            const double r = (double)c.w;
-                            const double u = q / (r * r);
-                            const double aa = (double)col[j].w;
-                            const double dd = (double)dal;
-                            unsafeAtomicAdd(&a.d_alpha[id], (float)(dd * (1.0 - u) * (1.0 - u)));
-                            unsafeAtomicAdd(&a.d_radius[id], (float)(dd * 4.0 * aa * (1.0 - u) * q / (r * r * r)));
-                            const double cc = -dd * 4.0 * aa * (1.0 - u) / (r * r);
-                            unsafeAtomicAdd(&a.d_centre[3 * (size_t)id + 0], (float)(cc * v0));
-                            unsafeAtomicAdd(&a.d_centre[3 * (size_t)id + 1], (float)(cc * v1));
-                            unsafeAtomicAdd(&a.d_centre[3 * (size_t)id + 2], (float)(cc * v2));
-                        }
-                        R = al * wj + (1.0f - al) * R;
-                    }
-                }
-                P = Pend;
+                L.t[j][lane] = T64;  // transmittance before hit j, for the gradients
+                T64 *= 1.0 - (double)al;
             }
-            if (more) {
-                lo_t = kt[K - 1];
-                lo_id = kid[K - 1];
+            ++n_hit;
+            ++used;
+            if (A >= stop) done = true;
+        }
+        const bool more = !done && m == K;
+        if (BWD) {
+            // sum over this pass of T_j alpha_j w_j, w_j = k_j . g_C + g_A
+            double Pc = 0.0;
+            for (uint32_t j = 0; j < used; ++j)
+                Pc += L.t[j][lane] * (double)L.al[j][lane] * wdot(load_colour(a.rgba, half, L.id[j][lane]), g);
+            if (phase == 0 && more) {
+                phase = 1;  // the total G is needed: sweep the rest first
+                G64 = Pc;
+            } else if (phase == 1) {
+                G64 += Pc;
+                if (!more) {
+                    // G known: start over from the first hit and emit gradients
+                    phase = 2;
+                    A = 0.0f; T = 1.0f; C[0] = C[1] = C[2] = 0.0f;
+                    n_hit = 0; T64 = 1.0; P64 = 0.0;
+                    lo_t = 0.0; lo_id = 0xffffffffu;
+                    continue;
+                }
             } else {
-                active = false;
+                // remainder behind this pass, composited from full transmittance
+                double R = (more && T64 > 0.0) ? (G64 - (P64 + Pc)) / T64 : 0.0;
+                for (uint32_t jj = used; jj > 0; --jj) {
+                    const uint32_t j = jj - 1;
+                    const uint32_t id = L.id[j][lane];
+                    const double al = (double)L.al[j][lane];
+                    const double Tj = L.t[j][lane];
+                    const float4 col = load_colour(a.rgba, half, id);
+                    const double wj = wdot(col, g);
+                    const double dal = Tj * (wj - R);
+                    const double ta = Tj * al;
+                    unsafeAtomicAdd(&a.d_rgb[3 * (size_t)id + 0], (float)(ta * g.x));
+                    unsafeAtomicAdd(&a.d_rgb[3 * (size_t)id + 1], (float)(ta * g.y));
+                    unsafeAtomicAdd(&a.d_rgb[3 * (size_t)id + 2], (float)(ta * g.z));
+                    if (!soft) {
+                        unsafeAtomicAdd(&a.d_alpha[id], (float)dal);
+                    } else {
+                        const float4 c = a.centre_radius[id];
+                        const double oc0 = (double)c.x - eye.o[0], oc1 = (double)c.y - eye.o[1],
+                                     oc2 = (double)c.z - eye.o[2];
+                        const double b = oc0 * ray.d[0] + oc1 * ray.d[1] + oc2 * ray.d[2];
+                        const double v0 = oc0 - b * ray.d[0], v1 = oc1 - b * ray.d[1], v2 = oc2 - b * ray.d[2];
+                        const double q = v0 * v0 + v1 * v1 + v2 * v2;
+                        const double r = (double)c.w;
+                        const double u = q / (r * r);
+                        const double aa = (double)col.w;
+                        unsafeAtomicAdd(&a.d_alpha[id], (float)(dal * (1.0 - u) * (1.0 - u)));
+                        unsafeAtomicAdd(&a.d_radius[id], (float)(dal * 4.0 * aa * (1.0 - u) * q / (r * r * r)));
+                        const double cc = -dal * 4.0 * aa * (1.0 - u) / (r * r);
+                        unsafeAtomicAdd(&a.d_centre[3 * (size_t)id + 0], (float)(cc * v0));
+                        unsafeAtomicAdd(&a.d_centre[3 * (size_t)id + 1], (float)(cc * v1));
+                        unsafeAtomicAdd(&a.d_centre[3 * (size_t)id + 2], (float)(cc * v2));
+                    }
+                    R = al * wj + (1.0 - al) * R;
+                }
+                P64 += Pc;
             }
+        }
+        if (more) {
+            lo_t = last_t;
+            lo_id = last_id;
+        } else {
+            active = false;
         }
     }
     if (!BWD && inside) {
@@ -343,20 +366,48 @@ __device__ void trace_tile(const TraceArgs &a, const Node *__restrict__ nodes, c
 
 // ---------------------------------------------------------------- kernels
 
-// One wave per block; block b -> XCD b % 8.  Each XCD gets a contiguous band
-// of tiles so that neighbouring tiles share that XCD's L2.
-template <int K, bool BWD>
-__global__ void __launch_bounds__(64) k_trace(TraceArgs a, int tiles_x, int tiles)
+// Tile of a block.  Consecutive blocks are dealt round robin to the 8 XCDs
+// (block b runs on XCD b % 8).  Schedule 0: the image is cut into
+// super-tiles of 8 x 8 tiles, dealt round robin to the XCDs; each XCD walks
+// its super-tiles tile by tile, so neighbouring tiles share an L2 while
+// every XCD gets a spread of the image (balanced load).  Schedule 1: each
+// XCD takes one contiguous band of tiles.
+__device__ inline bool tile_of_block(uint32_t b, int tiles_x, int tiles_y, int schedule, int &tx, int &ty)
 {
-    __shared__ uint32_t stack[64];
-    const int per_xcd = (tiles + 7) / 8;
-    const int tile = (int)(blockIdx.x % 8) * per_xcd + (int)(blockIdx.x / 8);
-    if (tile >= tiles) return;
+    const int xcd = (int)(b % 8), i = (int)(b / 8);
+    if (schedule == 1) {
+        const int tiles = tiles_x * tiles_y, per_xcd = (tiles + 7) / 8;
+        const int t = xcd * per_xcd + i;
+        tx = t % tiles_x;
+        ty = t / tiles_x;
+        return t < tiles;
+    }
+    const int sx_n = (tiles_x + 7) / 8, sy_n = (tiles_y + 7) / 8;
+    const int s = xcd + 8 * (i / 64), w = i % 64;
+    if (s >= sx_n * sy_n) return false;
+    tx = (s % sx_n) * 8 + w % 8;
+    ty = (s / sx_n) * 8 + w / 8;
+    return tx < tiles_x && ty < tiles_y;
+}
+
+__host__ inline uint32_t blocks_for(int tiles_x, int tiles_y, int schedule)
+{
+    if (schedule == 1) return (uint32_t)(((tiles_x * tiles_y + 7) / 8) * 8);
+    const int s = ((tiles_x + 7) / 8) * ((tiles_y + 7) / 8);
+    return (uint32_t)(((s + 7) / 8) * 8 * 64);
+}
+
+template <int K, bool BWD>
+__global__ void __launch_bounds__(64) k_trace(TraceArgs a, int tiles_x, int tiles_y)
+{
+    __shared__ WaveLds<K> lds;
+    int tx, ty;
+    if (!tile_of_block(blockIdx.x, tiles_x, tiles_y, a.schedule, tx, ty)) return;
     const char *mem = static_cast<const char *>(a.bvh_mem);
     const BvhLayout L(0);
     const BvhHeader *hdr = reinterpret_cast<const BvhHeader *>(mem);
     const Node *nodes = reinterpret_cast<const Node *>(mem + L.nodes);
-    trace_tile<K, BWD>(a, nodes, hdr, tile % tiles_x, tile / tiles_x, stack);
+    trace_tile<K, BWD>(a, nodes, hdr, tx, ty, lds);
 }
 
 // Persistent batched trace: waves pull tiles from one atomic counter until
@@ -367,7 +418,7 @@ k_trace_batched(const splat_batch_job *__restrict__ jobs, const uint32_t *__rest
                 uint32_t total_tiles, float alpha_stop, int mode, double t_max, int tile_w, int tile_h,
                 uint32_t *__restrict__ counter)
 {
-    __shared__ uint32_t stack[64];
+    __shared__ WaveLds<K> lds;
     __shared__ uint32_t item_s;
     const BvhLayout L(0);
     for (;;) {
@@ -405,9 +456,9 @@ k_trace_batched(const splat_batch_job *__restrict__ jobs, const uint32_t *__rest
         a.kbuf = K;
         a.tile_w = tile_w;
         a.tile_h = tile_h;
+        a.schedule = 0;
         a.out = reinterpret_cast<float4 *>(j.out_rgba);
         a.hits = j.out_hits;
-        a.fwd = nullptr;
         a.grad = nullptr;
         a.d_rgb = a.d_alpha = a.d_radius = a.d_centre = nullptr;
         const int tiles_x = (a.cam.w + tile_w - 1) / tile_w;
@@ -415,7 +466,7 @@ k_trace_batched(const splat_batch_job *__restrict__ jobs, const uint32_t *__rest
         const int t = t64 < 0 ? 0x7fffffff : (int)min(t64, (int64_t)0x7fffffff);
         const char *mem = static_cast<const char *>(j.bvh_mem);
         trace_tile<K, false>(a, reinterpret_cast<const Node *>(mem + L.nodes), reinterpret_cast<const BvhHeader *>(mem),
-                             t % tiles_x, t / tiles_x, stack);
+                             t % tiles_x, t / tiles_x, lds);
     }
 }
 
@@ -425,14 +476,14 @@ __global__ void k_zero_counter(uint32_t *c)
 }
 
 template <bool BWD>
-static hipError_t launch_k(const TraceArgs &a, int K, dim3 grid, int tiles_x, int tiles, hipStream_t s)
+static hipError_t launch_k(const TraceArgs &a, int K, dim3 grid, int tiles_x, int tiles_y, hipStream_t s)
 {
     switch (K) {
-    case 1: hipLaunchKernelGGL((k_trace<1, BWD>), grid, dim3(64), 0, s, a, tiles_x, tiles); break;
-    case 2: hipLaunchKernelGGL((k_trace<2, BWD>), grid, dim3(64), 0, s, a, tiles_x, tiles); break;
-    case 4: hipLaunchKernelGGL((k_trace<4, BWD>), grid, dim3(64), 0, s, a, tiles_x, tiles); break;
-    case 8: hipLaunchKernelGGL((k_trace<8, BWD>), grid, dim3(64), 0, s, a, tiles_x, tiles); break;
-    case 16: hipLaunchKernelGGL((k_trace<16, BWD>), grid, dim3(64), 0, s, a, tiles_x, tiles); break;
+    case 1: hipLaunchKernelGGL((k_trace<1, BWD>), grid, dim3(64), 0, s, a, tiles_x, tiles_y); break;
+    case 2: hipLaunchKernelGGL((k_trace<2, BWD>), grid, dim3(64), 0, s, a, tiles_x, tiles_y); break;
+    case 4: hipLaunchKernelGGL((k_trace<4, BWD>), grid, dim3(64), 0, s, a, tiles_x, tiles_y); break;
+    case 8: hipLaunchKernelGGL((k_trace<8, BWD>), grid, dim3(64), 0, s, a, tiles_x, tiles_y); break;
+    case 16: hipLaunchKernelGGL((k_trace<16, BWD>), grid, dim3(64), 0, s, a, tiles_x, tiles_y); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -442,11 +493,9 @@ hipError_t launch_trace(const TraceArgs &a, bool backward, hipStream_t s)
 {
     const int tiles_x = (a.cam.w + a.tile_w - 1) / a.tile_w;
     const int tiles_y = (a.cam.h + a.tile_h - 1) / a.tile_h;
-    const int tiles = tiles_x * tiles_y;
-    const int per_xcd = (tiles + 7) / 8;
-    const dim3 grid(per_xcd * 8);
-    return backward ? launch_k<true>(a, a.kbuf, grid, tiles_x, tiles, s)
-                    : launch_k<false>(a, a.kbuf, grid, tiles_x, tiles, s);
+    const dim3 grid(blocks_for(tiles_x, tiles_y, a.schedule));
+    return backward ? launch_k<true>(a, a.kbuf, grid, tiles_x, tiles_y, s)
+                    : launch_k<false>(a, a.kbuf, grid, tiles_x, tiles_y, s);
 }
 
 hipError_t launch_trace_batched(const splat_batch_job *jobs, const uint32_t *tile_offsets, int32_t n_jobs,

@@ -153,6 +153,7 @@ class TraceOptions:
     mode: int = _lib.SPLAT_ALPHA_CONSTANT
     kbuf: int = 8
     tile: tuple = field(default=(8, 8))
+    schedule: int = 0
 
     def struct(self) -> _lib.splat_trace_opts:
         o = _lib.splat_trace_opts()
@@ -161,6 +162,7 @@ class TraceOptions:
         o.mode = int(self.mode)
         o.kbuf = int(self.kbuf)
         o.tile_w, o.tile_h = int(self.tile[0]), int(self.tile[1])
+        o.schedule = int(self.schedule)
         return o
 
 

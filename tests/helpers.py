@@ -64,6 +64,20 @@ LEAF = 0x80000000
 EMPTY = 0xFFFFFFFF
 
 
+def bvh_core(mem, cap: int):
+    """The BVH bytes that define the hierarchy: everything except the refit's
+    scratch list of chunk-crossing arrivals (appended in arrival order) and its count."""
+    import torch
+    c = max(cap, 1)
+    lay = bvh_layout(cap)
+    ranges = _align(lay["leaf_ids"] + c * 4)       # flags
+    ranges = _align(ranges + c * 4)                # ranges
+    cross = _align(ranges + c * 8)
+    core = mem[:cross].clone() if isinstance(mem, torch.Tensor) else mem[:cross].copy()
+    core[4:8] = 0
+    return core
+
+
 def check_bvh(mem: np.ndarray, cap: int, cr: np.ndarray, alpha: np.ndarray) -> dict:
     """Structure of a built BVH: every sphere in exactly one leaf slot with its exact data,
     every internal node reached once, boxes containing their children, sphere boxes
