@@ -1,0 +1,141 @@
+"""Many client frames, each with several target views, in one persistent trace.
+
+Every frame is unprojected and its LBVH built with the plain entry points;
+then every (frame, view) job is traced by ONE splat_trace_batched launch,
+whose waves pull tiles from an atomic counter until the batch is drained.
+The whole sequence can be captured once in a HIP graph and replayed.
+Outputs equal the per-job splat_trace outputs bit for bit.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib
+from .render import (BVH, Spheres, TraceOptions, _ptr, _stream, alloc_bvh, alloc_spheres, build_bvh, trace,
+                     unproject, workspace)
+
+
+@dataclass
+class Frame:
+    rgba: torch.Tensor      # premultiplied float32 [H, W, 4] on the device
+    depth: torch.Tensor     # float32 [H, W]
+    src_cam: object
+    dst_cams: list
+
+
+class BatchedRenderer:
+    """Owns the device buffers of a batch; `run()` enqueues the whole batch."""
+
+    def __init__(self, frames: list[Frame], radius_scale: float = 1.0, half: bool = True,
+                 opts: TraceOptions | None = None, waves: int = 0):
+        self.frames = frames
+        self.radius_scale = float(radius_scale)
+        self.half = half
+        self.opts = opts or TraceOptions()
+        self.waves = int(waves)
+        dev = frames[0].rgba.device
+        self.device = dev
+        lib = _lib.load()
+        self.spheres: list[Spheres] = []
+        self.bvhs: list[BVH] = []
+        self.outputs: list[list[tuple[torch.Tensor, torch.Tensor]]] = []
+        for fr in frames:
+            cap = int(fr.src_cam.width) * int(fr.src_cam.height)
+            s = alloc_spheres(cap, dev, half)
+            self.spheres.append(s)
+            self.bvhs.append(alloc_bvh(cap, dev))
+            outs = []
+            for cam in fr.dst_cams:
+                outs.append((torch.zeros((cam.height, cam.width, 4), dtype=torch.float32, device=dev),
+                             torch.zeros((cam.height, cam.width), dtype=torch.int32, device=dev)))
+            self.outputs.append(outs)
+        self._build_jobs()
+        self.ws = torch.zeros(lib.splat_workspace_bytes(_lib.SPLAT_OP_BATCHED, self.n_jobs, 0, 0), dtype=torch.uint8,
+                              device=dev)
+        # grow the shared workspaces now so that nothing allocates during capture
+        for fr, s in zip(frames, self.spheres):
+            workspace(lib.splat_workspace_bytes(_lib.SPLAT_OP_UNPROJECT, 0, fr.src_cam.width, fr.src_cam.height),
+                      dev, "unproject")
+            workspace(lib.splat_workspace_bytes(_lib.SPLAT_OP_BUILD, s.capacity, 0, 0), dev, "build")
+        self.graph = None
+
+    def set_schedule(self, opts: TraceOptions, waves: int) -> None:
+        """Change hits per pass, tile shape or resident waves (rebuilds the tile prefix)."""
+        self.opts = opts
+        self.waves = int(waves)
+        self._build_jobs()
+        self.graph = None
+
+    def _build_jobs(self) -> None:
+        """Job table and exclusive tile prefix, built on the host and copied once."""
+        frames, half, dev = self.frames, self.half, self.device
+        tw, th = self.opts.tile
+        jobs, offsets, total = [], [0], 0
+        for fi, fr in enumerate(frames):
+            for vi, cam in enumerate(fr.dst_cams):
+                j = _lib.splat_batch_job()
+                j.bvh_mem = self.bvhs[fi].mem.data_ptr()
+                j.bvh_capacity = self.bvhs[fi].capacity
+                j.centre_radius = self.spheres[fi].centre_radius.data_ptr()
+                j.rgba = self.spheres[fi].rgba.data_ptr()
+                j.rgba_dtype = _lib.SPLAT_F16 if half else _lib.SPLAT_F32
+                j.camera = _lib.camera_struct(cam)
+                j.out_rgba = self.outputs[fi][vi][0].data_ptr()
+                j.out_hits = self.outputs[fi][vi][1].data_ptr()
+                jobs.append(j)
+                total += ((cam.width + tw - 1) // tw) * ((cam.height + th - 1) // th)
+                offsets.append(total)
+        self.n_jobs = len(jobs)
+        self.total_tiles = total
+        self.rays = sum(int(c.width) * int(c.height) for fr in frames for c in fr.dst_cams)
+        table = (_lib.splat_batch_job * self.n_jobs)(*jobs)
+        raw = np.frombuffer(bytes(table), dtype=np.uint8)
+        self.job_table = torch.from_numpy(raw.copy()).to(dev)
+        self.tile_offsets = torch.tensor(np.array(offsets[:-1], dtype=np.uint32).view(np.int32), device=dev)
+
+    def prepare(self):
+        """Unproject and build every frame (plain launches)."""
+        for fr, s, b in zip(self.frames, self.spheres, self.bvhs):
+            unproject(fr.src_cam, fr.rgba, fr.depth, self.radius_scale, self.half, out=s)
+            build_bvh(s, b)
+
+    def trace_batched(self):
+        """Every job in one persistent launch (splat_trace_batched)."""
+        o = self.opts.struct()
+        _lib.check(_lib.load().splat_trace_batched(_ptr(self.job_table), _ptr(self.tile_offsets), self.n_jobs,
+                                                   self.total_tiles, ctypes.byref(o), self.waves, _ptr(self.ws),
+                                                   self.ws.numel(), _stream()))
+
+    def run(self):
+        self.prepare()
+        self.trace_batched()
+
+    def run_sequential(self):
+        """Reference schedule: the same work as plain per-job launches."""
+        self.prepare()
+        for fi, fr in enumerate(self.frames):
+            for vi, cam in enumerate(fr.dst_cams):
+                out, hits = self.outputs[fi][vi]
+                trace(self.bvhs[fi], self.spheres[fi], cam, self.opts, out=out, hits=hits)
+
+    def capture(self):
+        """Capture run() into a HIP graph (torch.cuda.CUDAGraph over hipGraph)."""
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            self.run()  # warm-up on the capture stream
+        torch.cuda.current_stream().wait_stream(side)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.run()
+        self.graph = g
+        return g
+
+    def replay(self):
+        if self.graph is None:
+            self.capture()
+        self.graph.replay()

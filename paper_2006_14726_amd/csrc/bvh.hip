@@ -68,28 +68,42 @@ __device__ inline uint32_t expand_bits10(uint32_t v)
     return v;
 }
 
+// Fold the block partials into the centre box of the header (one block).
+__global__ void __launch_bounds__(256)
+k_bounds_final(const float *__restrict__ partial, BvhHeader *__restrict__ hdr)
+{
+    __shared__ float s[4][6];
+    float v[6];
+    for (int k = 0; k < 6; ++k) v[k] = partial[threadIdx.x * 8 + k];  // one partial per thread
+    for (int k = 0; k < 3; ++k) {
+        v[k] = wave_min(v[k]);
+        v[3 + k] = wave_max(v[3 + k]);
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0)
+        for (int k = 0; k < 6; ++k) s[w][k] = v[k];
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        float r = s[0][threadIdx.x];
+        for (int q = 1; q < 4; ++q) r = threadIdx.x < 3 ? fminf(r, s[q][threadIdx.x]) : fmaxf(r, s[q][threadIdx.x]);
+        if (threadIdx.x < 3) hdr->cen_lo[threadIdx.x] = r;
+        else hdr->cen_hi[threadIdx.x - 3] = r;
+    }
+}
+
 // Bit 3k+2 of a code is x, 3k+1 is y, 3k is z.
 __global__ void __launch_bounds__(256)
-k_morton(const float4 *__restrict__ cr, const uint32_t *__restrict__ count, uint32_t cap, const float *__restrict__ partial,
-         BvhHeader *__restrict__ hdr, uint32_t *__restrict__ keys, uint32_t *__restrict__ vals)
+k_morton(const float4 *__restrict__ cr, const uint32_t *__restrict__ count, uint32_t cap,
+         const BvhHeader *__restrict__ hdr, uint32_t *__restrict__ keys, uint32_t *__restrict__ vals)
 {
     __shared__ float box[6];
-    if (threadIdx.x < 6) {
-        float v = partial[threadIdx.x];
-        for (int b = 1; b < kBoundsBlocks; ++b) {
-            const float u = partial[b * 8 + threadIdx.x];
-            v = threadIdx.x < 3 ? fminf(v, u) : fmaxf(v, u);
-        }
-        box[threadIdx.x] = v;
+    if (threadIdx.x < 3) {
+        box[threadIdx.x] = hdr->cen_lo[threadIdx.x];
+        box[3 + threadIdx.x] = hdr->cen_hi[threadIdx.x];
     }
     __syncthreads();
     const uint32_t n = min(*count, cap);
     const uint32_t i = blockIdx.x * 256 + threadIdx.x;
-    if (blockIdx.x == 0 && threadIdx.x < 6) {
-        if (threadIdx.x < 3) hdr->cen_lo[threadIdx.x] = box[threadIdx.x];
-        else hdr->cen_hi[threadIdx.x - 3] = box[threadIdx.x];
-        if (threadIdx.x == 0) hdr->n = n;
-    }
     if (i >= n) return;
     const float4 c = cr[i];
     const float p[3] = {c.x, c.y, c.z};
@@ -392,24 +406,33 @@ __device__ inline uint32_t lift_box(Node *nodes, uint32_t p, const uint32_t *__r
 // node whose leaf range lies inside the chunk has both subtrees in this
 // workgroup, so the second-arrival handshake needs only workgroup scope.  A
 // thread that reaches a node whose range crosses the chunk records the
-// arrival for phase 2 and stops.
-__global__ void __launch_bounds__(256)
+// arrival for phase 2 and stops.  Inside the chunk, the child boxes and the
+// arrival counters live in LDS (an internal node's index lies in its own
+// leaf range, so the chunk's nodes are indices c_lo..c_hi); the node slots
+// are written to HBM for the traversal and for phase 2.
+constexpr int kRefitThreads = 512;
+
+__global__ void __launch_bounds__(kRefitThreads)
 k_refit_local(const float4 *__restrict__ cr, const void *__restrict__ rgba, int half,
               const uint32_t *__restrict__ count, uint32_t cap, Node *nodes, const uint32_t *__restrict__ leaf_parent,
-              const uint32_t *__restrict__ node_parent, const uint32_t *__restrict__ leaf_ids, uint32_t *flags,
+              const uint32_t *__restrict__ node_parent, const uint32_t *__restrict__ leaf_ids,
               const uint2 *__restrict__ ranges, uint32_t *__restrict__ cross, BvhHeader *hdr)
 {
+    __shared__ float lbox[kRefitChunk][2][6];  // child boxes of the chunk's nodes
+    __shared__ uint32_t lcnt[kRefitChunk];      // arrivals per node
     const uint32_t n = min(*count, cap);
     const uint32_t n_nodes = n > 1 ? n - 1 : 1;
     const uint32_t c_lo = blockIdx.x * kRefitChunk;
     if (c_lo >= n) return;
     const uint32_t c_hi = min(c_lo + kRefitChunk, n) - 1;
-    for (uint32_t j = c_lo + threadIdx.x; j <= c_hi; j += 256) {
+    for (uint32_t k = threadIdx.x; k < kRefitChunk; k += kRefitThreads) lcnt[k] = 0u;
+    __syncthreads();
+    for (uint32_t j = c_lo + threadIdx.x; j <= c_hi; j += kRefitThreads) {
         const uint32_t id = leaf_ids[j];
         if (id >= n) continue;  // only after a refit of a hierarchy that was never built
         const float4 c = cr[id];
         const float a = sphere_alpha_a(rgba, half, id);
-        const uint32_t pp = leaf_parent[j];
+        uint32_t pp = leaf_parent[j];
         uint32_t p = pp >> 1;
         if (p >= n_nodes) continue;
         {
@@ -422,23 +445,44 @@ k_refit_local(const float4 *__restrict__ cr, const void *__restrict__ rgba, int 
             lift_box(nodes, 0, node_parent, hdr);
             continue;
         }
+        const float ctr[3] = {c.x, c.y, c.z};
+        float lo[3], hi[3];
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = nextafterf(ctr[k] - c.w, -INFINITY);
+            hi[k] = nextafterf(ctr[k] + c.w, INFINITY);
+        }
+        // (lo, hi) is the box of the child in slot (pp & 1) of node p
         for (;;) {
             const uint2 r = ranges[p];
-            if (r.x < c_lo || r.y > c_hi) {
+            if (r.x < c_lo || r.y > c_hi || p < c_lo || p > c_hi) {
                 const uint32_t e = __hip_atomic_fetch_add(&hdr->n_cross, 1u, __ATOMIC_RELAXED,
                                                           __HIP_MEMORY_SCOPE_AGENT);
                 if (e < 2 * cap) cross[e] = p;
                 break;
             }
-            const uint32_t old = __hip_atomic_fetch_add(&flags[p], 1u, __ATOMIC_ACQ_REL,
+            const uint32_t lp = p - c_lo, side = pp & 1u;
+            for (int k = 0; k < 3; ++k) {
+                lbox[lp][side][k] = lo[k];
+                lbox[lp][side][3 + k] = hi[k];
+            }
+            const uint32_t old = __hip_atomic_fetch_add(&lcnt[lp], 1u, __ATOMIC_ACQ_REL,
                                                         __HIP_MEMORY_SCOPE_WORKGROUP);
             // first arrival: the sibling subtree is not finished and its thread
             // continues; a count above 1 only occurs in a corrupt hierarchy
             if (old != 1u) break;
-            const uint32_t up = lift_box(nodes, p, node_parent, hdr);
-            if (up == kEmpty) break;
-            p = up >> 1;
+            for (int k = 0; k < 3; ++k) {
+                lo[k] = fminf(lo[k], lbox[lp][side ^ 1u][k]);
+                hi[k] = fmaxf(hi[k], lbox[lp][side ^ 1u][3 + k]);
+            }
+            pp = node_parent[p];
+            if (pp == kEmpty) {
+                for (int k = 0; k < 3; ++k) { hdr->scene_lo[k] = lo[k]; hdr->scene_hi[k] = hi[k]; }
+                break;
+            }
+            p = pp >> 1;
             if (p >= n_nodes) break;
+            float *s = nodes[p].f + 6 * (pp & 1u);
+            s[0] = lo[0]; s[1] = lo[1]; s[2] = lo[2]; s[3] = hi[0]; s[4] = hi[1]; s[5] = hi[2];
         }
     }
 }
@@ -502,7 +546,8 @@ hipError_t launch_build(const splat_spheres &sph, const splat_bvh &bvh, bool ref
         uint32_t *totals = reinterpret_cast<uint32_t *>(w + B.totals);
         float *partial = reinterpret_cast<float *>(w + B.partial);
         hipLaunchKernelGGL(k_bounds_partial, dim3(kBoundsBlocks), dim3(256), 0, s, cr, sph.count, cap, partial);
-        hipLaunchKernelGGL(k_morton, dim3(blocks), dim3(256), 0, s, cr, sph.count, cap, partial, hdr, ka, va);
+        hipLaunchKernelGGL(k_bounds_final, dim3(1), dim3(kBoundsBlocks), 0, s, partial, hdr);
+        hipLaunchKernelGGL(k_morton, dim3(blocks), dim3(256), 0, s, cr, sph.count, cap, hdr, ka, va);
         for (int shift = 0; shift < kMortonBits; shift += kSortBits) {
             hipLaunchKernelGGL(k_sort_hist, dim3(B.tiles), dim3(kSortBlock), 0, s, ka, sph.count, cap, shift, hist,
                                B.tiles);
@@ -517,8 +562,8 @@ hipError_t launch_build(const splat_spheres &sph, const splat_bvh &bvh, bool ref
     } else {
         hipLaunchKernelGGL(k_zero_flags, dim3(blocks), dim3(256), 0, s, flags, sph.count, cap);
     }
-    hipLaunchKernelGGL(k_refit_local, dim3(chunks), dim3(256), 0, s, cr, sph.rgba, half, sph.count, cap, nodes,
-                       leaf_parent, node_parent, leaf_ids, flags, ranges, cross, hdr);
+    hipLaunchKernelGGL(k_refit_local, dim3(chunks), dim3(kRefitThreads), 0, s, cr, sph.rgba, half, sph.count, cap,
+                       nodes, leaf_parent, node_parent, leaf_ids, ranges, cross, hdr);
     hipLaunchKernelGGL(k_refit_top, dim3(1), dim3(1024), 0, s, sph.count, cap, nodes, node_parent, flags, cross, hdr);
     return hipGetLastError();
 }

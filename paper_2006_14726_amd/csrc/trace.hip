@@ -59,6 +59,8 @@ struct Ray {
     double d[3];     // unit direction, double
     float df[3];     // float copy of d
     float inv[3];    // 1 / df
+    float oPi[3];    // (eye + margin) / df
+    float oMi[3];    // (eye - margin) / df
 };
 
 // Wave-uniform ray state.
@@ -125,6 +127,8 @@ __device__ void trace_tile(const TraceArgs &a, const Node *__restrict__ nodes, c
         for (int k = 0; k < 3; ++k) {
             eye.oP[k] = eye.of[k] + m;
             eye.oM[k] = eye.of[k] - m;
+            ray.oPi[k] = eye.oP[k] * ray.inv[k];
+            ray.oMi[k] = eye.oM[k] * ray.inv[k];
         }
         eye.E = m;
     }
@@ -222,10 +226,11 @@ __device__ void trace_tile(const TraceArgs &a, const Node *__restrict__ nodes, c
                         pr_f = (float)(pr_t * (1.0 + 0x1p-20));
                     }
                 } else {
-                    // padded-box slab test in float
-                    const float t1x = (s[0] - eye.oP[0]) * ray.inv[0], t2x = (s[3] - eye.oM[0]) * ray.inv[0];
-                    const float t1y = (s[1] - eye.oP[1]) * ray.inv[1], t2y = (s[4] - eye.oM[1]) * ray.inv[1];
-                    const float t1z = (s[2] - eye.oP[2]) * ray.inv[2], t2z = (s[5] - eye.oM[2]) * ray.inv[2];
+                    // padded-box slab test in float, (x - o) / d as fma(x, 1/d, -o/d): the
+                    // rounding of o/d moves the eye by at most eps |o|, far inside the margin
+                    const float t1x = fmaf(s[0], ray.inv[0], -ray.oPi[0]), t2x = fmaf(s[3], ray.inv[0], -ray.oMi[0]);
+                    const float t1y = fmaf(s[1], ray.inv[1], -ray.oPi[1]), t2y = fmaf(s[4], ray.inv[1], -ray.oMi[1]);
+                    const float t1z = fmaf(s[2], ray.inv[2], -ray.oPi[2]), t2z = fmaf(s[5], ray.inv[2], -ray.oMi[2]);
                     const float tn = fmaxf(fmaxf(fminf(t1x, t2x), fminf(t1y, t2y)), fminf(t1z, t2z));
                     const float tf = fminf(fminf(fmaxf(t1x, t2x), fmaxf(t1y, t2y)), fmaxf(t1z, t2z)) * 1.0000005f;
                     hit[side] = tn <= tf && tf >= lo_f && tn <= pr_f && ref < n_nodes;

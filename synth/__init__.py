@@ -203,6 +203,44 @@ def volume_of(w: Workload) -> np.ndarray:
     return _cache[w][4]
 
 
+# ---------------------------------------------------------------- batched frames
+
+@dataclass(frozen=True)
+class BatchFrame:
+    index: int
+    seed: int
+    nblobs: int
+    src: int          # square source size
+    dst_w: int
+    dst_h: int
+    yaws: tuple       # one target pose per yaw (degrees)
+
+
+def batch_frames(n_frames: int = 64, meta_seed: int = 5, vol_n: int = 128,
+                 src_sizes=(256, 512, 1024, 2048), dst_sizes=((640, 480), (1280, 720), (1920, 1080))):
+    """Client frames of uneven sizes: per frame a source size, a target size, 16-128 blobs
+    (seed 5000 + frame) and 1-8 target poses at yaw U[0, 20) degrees, all drawn from `meta_seed`."""
+    rng = np.random.default_rng(meta_seed)
+    frames = []
+    for f in range(n_frames):
+        src = int(rng.choice(src_sizes))
+        dw, dh = dst_sizes[int(rng.integers(len(dst_sizes)))]
+        nblobs = int(rng.integers(16, 129))
+        poses = int(rng.integers(1, 9))
+        yaws = tuple(float(y) for y in rng.uniform(0.0, 20.0, poses))
+        frames.append(BatchFrame(f, 5000 + f, nblobs, src, int(dw), int(dh), yaws))
+    return frames
+
+
+def batch_frame_images(fr: BatchFrame, vol_n: int = 128):
+    """(rgba, depth, src_cam, [dst_cams]) of one batched frame."""
+    vol = make_volume(vol_n, fr.nblobs, fr.seed)
+    src = source_camera(fr.src, fr.src)
+    rgba, depth = raycast(vol, src)
+    dsts = [rotated_camera(src, y, 0.0, fr.dst_w, fr.dst_h) for y in fr.yaws]
+    return rgba, depth, src, dsts
+
+
 # ---------------------------------------------------------------- small scenes
 
 def random_spheres(n: int, seed: int, centre_lo=0.3, centre_hi=0.7, r_lo=0.01, r_hi=0.06,

@@ -1,0 +1,130 @@
+"""Batched persistent trace: bit-identical to per-job plain launches, stable
+under HIP-graph replay, sampled pixels against the oracle, and the
+autotuner."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from helpers import assert_parity, compare
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sp():
+    import paper_2006_14726_amd as sp
+    sp.load_library()
+    return sp
+
+
+def up(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def small_batch():
+    frames = synth.batch_frames(n_frames=7, meta_seed=9, src_sizes=(48, 64, 96),
+                                dst_sizes=((80, 60), (70, 45), (130, 66)))
+    out = []
+    for fr in frames:
+        rgba, depth, src, dsts = synth.batch_frame_images(fr, vol_n=32)
+        out.append((rgba, depth, src, dsts))
+    return out
+
+
+def make_renderer(sp, batch, **kw):
+    from paper_2006_14726_amd.batched import BatchedRenderer, Frame
+    frames = [Frame(up(r), up(d), s, dsts) for r, d, s, dsts in batch]
+    return BatchedRenderer(frames, **kw)
+
+
+def snapshot(r):
+    return [[(o.clone(), h.clone()) for o, h in views] for views in r.outputs]
+
+
+def assert_same(a, b):
+    for va, vb in zip(a, b):
+        for (oa, ha), (ob, hb) in zip(va, vb):
+            assert torch.equal(oa, ob) and torch.equal(ha, hb)
+
+
+@pytest.mark.parametrize("kbuf,tile,waves", [(8, (8, 8), 0), (4, (16, 4), 97), (1, (32, 2), 3)])
+def test_batched_equals_sequential(sp, small_batch, kbuf, tile, waves):
+    r = make_renderer(sp, small_batch, half=True, opts=sp.TraceOptions(kbuf=kbuf, tile=tile), waves=waves)
+    assert r.n_jobs >= 7
+    r.run_sequential()
+    ref = snapshot(r)
+    for views in r.outputs:
+        for o, h in views:
+            o.zero_()
+            h.zero_()
+    r.run()
+    torch.cuda.synchronize()
+    assert_same(snapshot(r), ref)
+    assert sum(int(h.sum()) for views in ref for _, h in views) > 100
+
+
+def test_graph_replay_matches_eager(sp, small_batch):
+    r = make_renderer(sp, small_batch, half=True)
+    r.run()
+    torch.cuda.synchronize()
+    ref = snapshot(r)
+    r.capture()
+    for it in range(3):
+        for views in r.outputs:
+            for o, h in views:
+                o.fill_(float(it + 1))
+                h.fill_(-1)
+        torch.cuda.synchronize()
+        r.replay()
+        torch.cuda.synchronize()
+        assert_same(snapshot(r), ref)
+        _ = torch.ones(1000, device="cuda:0").sum().item()  # eager work between replays
+
+
+def test_batched_output_against_oracle(sp, small_batch):
+    r = make_renderer(sp, small_batch, half=True)
+    r.run()
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(3)
+    for fi in (0, 3, 6):
+        s = r.spheres[fi]
+        n = s.n()
+        cr = s.centre_radius[:n].cpu().numpy()
+        col = s.rgba[:n].cpu().numpy()
+        # the oracle traces its own unprojection of the same source image
+        rgba, depth, src, dsts = small_batch[fi]
+        ocr, ocol, _ = oracle.unproject(src, rgba, depth, 1.0, True)
+        assert np.array_equal(ocol.view(np.uint16), col.view(np.uint16))
+        assert np.abs(ocr.view(np.int32).astype(np.int64) - cr.view(np.int32)).max() <= 1
+        for vi, cam in enumerate(dsts):
+            img, hits = r.outputs[fi][vi]
+            pix = rng.integers(0, cam.width * cam.height, 300)
+            g = img.cpu().numpy().reshape(-1, 4)[pix]
+            h = hits.cpu().numpy().reshape(-1)[pix]
+            assert_parity(compare(g, h, oracle.render(ocr, ocol, cam, pixels=pix)), exempt_frac=None)
+
+
+def test_autotuner_picks_a_valid_schedule(sp, small_batch, tmp_path, monkeypatch):
+    from paper_2006_14726_amd import autotune
+    monkeypatch.setenv("SPLAT_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
+    rgba, depth, src, dsts = small_batch[2]
+    s = sp.unproject(src, up(rgba), up(depth), 1.0, True)
+    bvh = sp.build_bvh(s)
+    opts, rec = autotune.tune_trace(bvh, s, dsts[0])
+    assert opts.kbuf in (4, 8) and len(rec["all_ms"]) == len(autotune.TRACE_CANDIDATES)
+    ref, _ = sp.trace(bvh, s, dsts[0])
+    got, _ = sp.trace(bvh, s, dsts[0], opts)
+    assert torch.equal(ref, got)
+    again, rec2 = autotune.tune_trace(bvh, s, dsts[0])  # from the cache
+    assert rec2["kbuf"] == rec["kbuf"]
+    r = make_renderer(sp, small_batch, half=True)
+    r.run_sequential()
+    ref_out = snapshot(r)
+    best = autotune.tune_batched(r)
+    assert best["waves"] > 0
+    r.run()
+    torch.cuda.synchronize()
+    assert_same(snapshot(r), ref_out)
