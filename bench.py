@@ -33,9 +33,32 @@ def parse():
     p.add_argument("--tile", type=str, default="8x8")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--no-bwd", action="store_true", help="skip the fwd+bwd measurement")
+    p.add_argument("--batch-frames", type=int, default=64,
+                   help="frames of the batched graph measurement (0 skips it)")
     p.add_argument("--calib-copy-mib", type=int, default=0,
                    help="run one plain device copy of this many MiB first (scales the HBM byte counters)")
     return p.parse_args()
+
+
+def measured_traffic(args):
+    """HBM bytes per trace launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None
+    when the trace kernel source or the launch configuration differs from the one profiled."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "trace_client_frame_hbm_traffic.txt")
+    if not os.path.exists(path) or (args.kbuf, args.tile, args.scale) != (8, "8x8", 1.0):
+        return None
+    rec = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            rec[k.strip()] = v.strip()
+    h = hashlib.sha256()
+    for f in ("trace.hip", "common.h", "kernels.h"):
+        with open(os.path.join(ROOT, "paper_2006_14726_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if rec.get("trace_source_sha256_16") != h.hexdigest()[:16]:
+        return None
+    return int(float(rec["traffic_bytes_per_dispatch"]))
 
 
 def trace_bytes(n: int, pixels: int, half: bool) -> int:
@@ -144,12 +167,14 @@ def main():
         "trace_only_mrays_s": round(P / (trace_ms * 1e-3) / 1e6, 2),
         "mean_hits_per_ray": round(float(hit_stats.mean()), 3),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": measured_traffic(args),
                      "kernel": "k_trace<8,false>", "algorithmic_bytes": tb, "avg_launch_ms": round(trace_ms, 4)},
     }
 
     if not args.no_bwd:
         result["fwd_bwd"] = fwd_bwd(sp, torch, synth, dev, args.steps)
+    if args.batch_frames > 0:
+        result["batched"] = batched(sp, torch, synth, dev, args.batch_frames)
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(sph, dst, n)
     print(json.dumps(result), flush=True)
@@ -182,6 +207,42 @@ def fwd_bwd(sp, torch, synth, dev, steps):
     fb = ev[1].elapsed_time(ev[2]) / reps
     return {"workload": f"{src.width}x{src.height} source ({s.n()} spheres) -> {dst.width}x{dst.height}, soft alpha",
             "fwd_ms": round(f, 4), "fwd_bwd_ms": round(fb, 4), "bwd_over_fwd": round((fb - f) / f, 3)}
+
+
+def batched(sp, torch, synth, dev, n_frames):
+    """Uneven client frames (source 256^2..2048^2, target 640x480..1920x1080, 1-8 views each):
+    one graph-captured persistent launch vs per-job plain launches, bit-identical outputs."""
+    from paper_2006_14726_amd import autotune
+    from paper_2006_14726_amd.batched import BatchedRenderer, Frame
+    t0 = time.perf_counter()
+    frames = []
+    for fr in synth.batch_frames(n_frames):
+        rgba, depth, src, dsts = synth.batch_frame_images(fr)
+        frames.append(Frame(torch.from_numpy(rgba).to(dev), torch.from_numpy(depth).to(dev), src, dsts))
+    gen_s = time.perf_counter() - t0
+    r = BatchedRenderer(frames, half=True)
+    tuned = autotune.tune_batched(r, use_cache=False)
+
+    def wall(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / reps
+
+    seq = wall(r.run_sequential)
+    ref = [[o.clone() for o, _ in views] for views in r.outputs]
+    r.capture()
+    graph = wall(r.replay)
+    same = all(torch.equal(o, q) for views, rv in zip(r.outputs, ref) for (o, _), q in zip(views, rv))
+    return {"workload": f"{n_frames} frames, {r.n_jobs} views, {r.rays} rays, "
+                        f"{sum(int(f.src_cam.width) * int(f.src_cam.height) for f in frames)} source pixels",
+            "graph_ms": round(graph * 1e3, 3), "sequential_ms": round(seq * 1e3, 3),
+            "graph_mrays_s": round(r.rays / graph / 1e6, 1), "sequential_mrays_s": round(r.rays / seq / 1e6, 1),
+            "bit_identical": bool(same), "tuned": {k: tuned[k] for k in ("kbuf", "tile", "waves")},
+            "input_generation_s": round(gen_s, 1)}
 
 
 def cpu_baseline(sph, dst, n):

@@ -420,12 +420,20 @@ k_refit_local(const float4 *__restrict__ cr, const void *__restrict__ rgba, int 
 {
     __shared__ float lbox[kRefitChunk][2][6];  // child boxes of the chunk's nodes
     __shared__ uint32_t lcnt[kRefitChunk];      // arrivals per node
+    __shared__ uint32_t lpar[kRefitChunk];      // parent references of the chunk's nodes
+    __shared__ uint2 lrng[kRefitChunk];         // leaf ranges of the chunk's nodes
     const uint32_t n = min(*count, cap);
     const uint32_t n_nodes = n > 1 ? n - 1 : 1;
     const uint32_t c_lo = blockIdx.x * kRefitChunk;
     if (c_lo >= n) return;
     const uint32_t c_hi = min(c_lo + kRefitChunk, n) - 1;
-    for (uint32_t k = threadIdx.x; k < kRefitChunk; k += kRefitThreads) lcnt[k] = 0u;
+    for (uint32_t k = threadIdx.x; k < kRefitChunk; k += kRefitThreads) {
+        const uint32_t i = c_lo + k;
+        const bool ok = i < n_nodes && n > 1;
+        lcnt[k] = 0u;
+        lpar[k] = ok ? node_parent[i] : kEmpty;
+        lrng[k] = ok ? ranges[i] : make_uint2(0xffffffffu, 0u);
+    }
     __syncthreads();
     for (uint32_t j = c_lo + threadIdx.x; j <= c_hi; j += kRefitThreads) {
         const uint32_t id = leaf_ids[j];
@@ -453,8 +461,8 @@ k_refit_local(const float4 *__restrict__ cr, const void *__restrict__ rgba, int 
         }
         // (lo, hi) is the box of the child in slot (pp & 1) of node p
         for (;;) {
-            const uint2 r = ranges[p];
-            if (r.x < c_lo || r.y > c_hi || p < c_lo || p > c_hi) {
+            const bool inside = p >= c_lo && p <= c_hi && lrng[p - c_lo].x >= c_lo && lrng[p - c_lo].y <= c_hi;
+            if (!inside) {
                 const uint32_t e = __hip_atomic_fetch_add(&hdr->n_cross, 1u, __ATOMIC_RELAXED,
                                                           __HIP_MEMORY_SCOPE_AGENT);
                 if (e < 2 * cap) cross[e] = p;
@@ -474,7 +482,7 @@ k_refit_local(const float4 *__restrict__ cr, const void *__restrict__ rgba, int 
                 lo[k] = fminf(lo[k], lbox[lp][side ^ 1u][k]);
                 hi[k] = fmaxf(hi[k], lbox[lp][side ^ 1u][3 + k]);
             }
-            pp = node_parent[p];
+            pp = lpar[lp];
             if (pp == kEmpty) {
                 for (int k = 0; k < 3; ++k) { hdr->scene_lo[k] = lo[k]; hdr->scene_hi[k] = hi[k]; }
                 break;
@@ -496,11 +504,12 @@ k_refit_top(const uint32_t *__restrict__ count, uint32_t cap, Node *nodes, const
     const uint32_t n = min(*count, cap);
     const uint32_t n_nodes = n > 1 ? n - 1 : 1;
     const uint32_t m = min(hdr->n_cross, 2 * cap);
-    for (uint32_t e = threadIdx.x; e < m; e += 1024) {
+    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < m; e += gridDim.x * blockDim.x) {
         uint32_t p = cross[e];
         while (p < n_nodes) {
+            // the two subtrees of a crossing node may finish on different XCDs
             const uint32_t old = __hip_atomic_fetch_add(&flags[p], 1u, __ATOMIC_ACQ_REL,
-                                                        __HIP_MEMORY_SCOPE_WORKGROUP);
+                                                        __HIP_MEMORY_SCOPE_AGENT);
             if (old != 1u) break;
             const uint32_t up = lift_box(nodes, p, node_parent, hdr);
             if (up == kEmpty) break;
@@ -564,7 +573,7 @@ hipError_t launch_build(const splat_spheres &sph, const splat_bvh &bvh, bool ref
     }
     hipLaunchKernelGGL(k_refit_local, dim3(chunks), dim3(kRefitThreads), 0, s, cr, sph.rgba, half, sph.count, cap,
                        nodes, leaf_parent, node_parent, leaf_ids, ranges, cross, hdr);
-    hipLaunchKernelGGL(k_refit_top, dim3(1), dim3(1024), 0, s, sph.count, cap, nodes, node_parent, flags, cross, hdr);
+    hipLaunchKernelGGL(k_refit_top, dim3(128), dim3(256), 0, s, sph.count, cap, nodes, node_parent, flags, cross, hdr);
     return hipGetLastError();
 }
 
