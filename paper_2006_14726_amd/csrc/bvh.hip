@@ -518,6 +518,41 @@ k_refit_top(const uint32_t *__restrict__ count, uint32_t cap, Node *nodes, const
     }
 }
 
+// Wide nodes: internal node X gathers the slots of its internal children (its
+// grandchildren) and keeps its leaf children, so that the traversal descends
+// two levels per node fetch.  Runs after every refit (it copies boxes).
+__global__ void __launch_bounds__(256)
+k_gather_wide(const uint32_t *__restrict__ count, uint32_t cap, const Node *__restrict__ nodes,
+              WideNode *__restrict__ wide)
+{
+    const uint32_t n = min(*count, cap);
+    const uint32_t n_nodes = n > 1 ? n - 1 : 1;
+    const uint32_t x = blockIdx.x * 256 + threadIdx.x;
+    if (n == 0 || x >= n_nodes) return;
+    const Node X = nodes[x];
+    float w[32];
+    w[28] = X.f[14];
+    for (int c = 0; c < 2; ++c) {
+        const uint32_t ref = __float_as_uint(X.f[12 + c]);
+        if (ref != kEmpty && !(ref & kLeafBit) && ref < n_nodes) {
+            const Node C = nodes[ref];
+            for (int k = 0; k < 12; ++k) w[12 * c + k] = C.f[k];
+            w[24 + 2 * c] = C.f[12];
+            w[25 + 2 * c] = C.f[13];
+            w[29 + c] = C.f[14];
+        } else {
+            for (int k = 0; k < 6; ++k) w[12 * c + k] = X.f[6 * c + k];
+            for (int k = 6; k < 12; ++k) w[12 * c + k] = 0.0f;
+            w[24 + 2 * c] = __uint_as_float(ref == kEmpty || (ref & kLeafBit) ? ref : kEmpty);
+            w[25 + 2 * c] = __uint_as_float(kEmpty);
+            w[29 + c] = __uint_as_float(3u);
+        }
+    }
+    w[31] = 0.0f;
+    float4 *dst = reinterpret_cast<float4 *>(wide + x);
+    for (int k = 0; k < 8; ++k) dst[k] = make_float4(w[4 * k], w[4 * k + 1], w[4 * k + 2], w[4 * k + 3]);
+}
+
 // Header count (an empty sphere set traces as background) and the refit list reset.
 __global__ void k_header_count(const uint32_t *__restrict__ count, uint32_t cap, BvhHeader *__restrict__ hdr)
 {
@@ -574,6 +609,8 @@ hipError_t launch_build(const splat_spheres &sph, const splat_bvh &bvh, bool ref
     hipLaunchKernelGGL(k_refit_local, dim3(chunks), dim3(kRefitThreads), 0, s, cr, sph.rgba, half, sph.count, cap,
                        nodes, leaf_parent, node_parent, leaf_ids, ranges, cross, hdr);
     hipLaunchKernelGGL(k_refit_top, dim3(128), dim3(256), 0, s, sph.count, cap, nodes, node_parent, flags, cross, hdr);
+    hipLaunchKernelGGL(k_gather_wide, dim3(blocks), dim3(256), 0, s, sph.count, cap, nodes,
+                       reinterpret_cast<WideNode *>(mem + L.wide));
     return hipGetLastError();
 }
 

@@ -112,6 +112,16 @@ struct __align__(64) Node {
     float f[16];
 };
 
+// Wide node of internal node X: the four grandchildren of X (two per internal
+// child of X; a leaf child of X takes one slot and leaves the next empty).
+//   f[0..23]:  four slots of 6 floats, as in Node
+//   f[24..27]: slot references (binary node index of an internal grandchild,
+//              whose own wide node is wide[index]; kLeafBit | sphere id; kEmpty)
+//   f[28..30]: split axes of X, of X's child 0 and of X's child 1 (3 = none)
+struct __align__(128) WideNode {
+    float f[32];
+};
+
 struct __align__(256) BvhHeader {
     uint32_t n;            // spheres at build time
     uint32_t n_cross;      // refit: entries in the list of chunk-crossing arrivals
@@ -127,7 +137,7 @@ __host__ __device__ inline size_t align256(size_t x) { return (x + 255) & ~(size
 
 // Offsets inside splat_bvh.mem.
 struct BvhLayout {
-    size_t header, nodes, leaf_parent, node_parent, leaf_ids, flags, ranges, cross, total;
+    size_t header, nodes, leaf_parent, node_parent, leaf_ids, flags, ranges, cross, wide, total;
     __host__ __device__ explicit BvhLayout(uint32_t cap)
     {
         const size_t c = cap < 1 ? 1 : cap;
@@ -139,7 +149,8 @@ struct BvhLayout {
         flags = align256(leaf_ids + c * 4);
         ranges = align256(flags + c * 4);       // first/last sorted leaf of each internal node
         cross = align256(ranges + c * 8);       // refit arrivals at chunk-crossing nodes
-        total = align256(cross + c * 8);
+        wide = align256(cross + c * 8);         // WideNode per internal node (what the trace reads)
+        total = align256(wide + c * sizeof(WideNode));
     }
 };
 

@@ -71,19 +71,21 @@ struct Eye {
     float E;             // bound on the float ray-to-centre distance error
 };
 
+constexpr int kStack = 128;  // wave traversal stack (entries)
+
 // LDS of one wave: hit buffers (column per lane) and the traversal stack.
 template <int K>
 struct WaveLds {
     double t[K][kWave];     // hit distance; in the backward, the transmittance before the hit
     uint32_t id[K][kWave];
     float al[K][kWave];
-    uint32_t stack[64];
+    uint32_t stack[kStack];
 };
 
 // ---------------------------------------------------------------- one tile
 
 template <int K, bool BWD>
-__device__ void trace_tile(const TraceArgs &a, const Node *__restrict__ nodes, const BvhHeader *__restrict__ hdr,
+__device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ nodes, const BvhHeader *__restrict__ hdr,
                            int tile_x, int tile_y, WaveLds<K> &L)
 {
     const int lane = threadIdx.x & (kWave - 1);
@@ -167,14 +169,14 @@ __device__ void trace_tile(const TraceArgs &a, const Node *__restrict__ nodes, c
         // a pass visits every node at most once; the cap only matters for a
         // corrupt hierarchy, where it turns a cycle into an early exit
         for (uint32_t visits = 0; visits <= n_nodes; ++visits) {
-            const Node *nd = nodes + node;
-            float f[16];
+            const WideNode *nd = nodes + node;
+            float f[32];
 #pragma unroll
-            for (int k = 0; k < 16; ++k) f[k] = nd->f[k];
-            bool hit[2] = {false, false};
+            for (int k = 0; k < 32; ++k) f[k] = nd->f[k];
+            bool hit[4] = {false, false, false, false};
 #pragma unroll
-            for (int side = 0; side < 2; ++side) {
-                const uint32_t ref = __float_as_uint(f[12 + side]);
+            for (int side = 0; side < 4; ++side) {
+                const uint32_t ref = __float_as_uint(f[24 + side]);
                 const float *s = f + 6 * side;
                 if (ref == kEmpty) continue;
                 if (ref & kLeafBit) {
@@ -236,21 +238,35 @@ __device__ void trace_tile(const TraceArgs &a, const Node *__restrict__ nodes, c
                     hit[side] = tn <= tf && tf >= lo_f && tn <= pr_f && ref < n_nodes;
                 }
             }
-            const uint64_t b0 = __ballot(hit[0]), b1 = __ballot(hit[1]);
-            const uint32_t r0 = __float_as_uint(f[12]), r1 = __float_as_uint(f[13]);
-            if (b0 && b1) {
-                const uint32_t axis = __float_as_uint(f[14]);
-                const bool second_first = axis < 3 && ((neg_mask >> axis) & 1u);
-                // depth <= 63 for 62-bit (code, position) keys, so 64 slots never overflow
-                if (sp < 64) {
-                    if (lane == 0) L.stack[sp] = second_first ? r0 : r1;
-                    ++sp;
+            uint32_t any = 0;  // slots whose box some lane's ray meets
+#pragma unroll
+            for (int side = 0; side < 4; ++side)
+                if (__ballot(hit[side])) any |= 1u << side;
+            if (any) {
+                // near-first order: the near child of the node, within it the near grandchild
+                const uint32_t ax = __float_as_uint(f[28]);
+                const uint32_t cn = (ax < 3 && ((neg_mask >> ax) & 1u)) ? 1u : 0u;
+                const uint32_t axn = __float_as_uint(f[29 + cn]), axf = __float_as_uint(f[30 - cn]);
+                const uint32_t gn = (axn < 3 && ((neg_mask >> axn) & 1u)) ? 1u : 0u;
+                const uint32_t gf = (axf < 3 && ((neg_mask >> axf) & 1u)) ? 1u : 0u;
+                const uint32_t order[4] = {2 * cn + gn, 2 * cn + (1u - gn), 2 * (1u - cn) + gf,
+                                           2 * (1u - cn) + (1u - gf)};
+                // descend into the nearest slot hit; push the others, farthest first
+                int first = -1;
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (first < 0 && ((any >> order[i]) & 1u)) first = i;
+#pragma unroll
+                for (int i = 3; i >= 0; --i) {
+                    if (i <= first || !((any >> order[i]) & 1u)) continue;
+                    // a wide level pushes at most 3 entries and the wide depth is
+                    // at most 32 for 62-bit (code, position) keys: 128 slots suffice
+                    if (sp < kStack) {
+                        if (lane == 0) L.stack[sp] = __float_as_uint(f[24 + order[i]]);
+                        ++sp;
+                    }
                 }
-                node = second_first ? r1 : r0;
-            } else if (b0) {
-                node = r0;
-            } else if (b1) {
-                node = r1;
+                node = __float_as_uint(f[24 + order[first]]);
             } else {
                 if (sp == 0) break;
                 --sp;
@@ -411,7 +427,7 @@ __global__ void __launch_bounds__(64) k_trace(TraceArgs a, int tiles_x, int tile
     const char *mem = static_cast<const char *>(a.bvh_mem);
     const BvhLayout L(0);
     const BvhHeader *hdr = reinterpret_cast<const BvhHeader *>(mem);
-    const Node *nodes = reinterpret_cast<const Node *>(mem + L.nodes);
+    const WideNode *nodes = reinterpret_cast<const WideNode *>(mem + L.wide);
     trace_tile<K, BWD>(a, nodes, hdr, tx, ty, lds);
 }
 
@@ -470,7 +486,7 @@ k_trace_batched(const splat_batch_job *__restrict__ jobs, const uint32_t *__rest
         const int64_t t64 = (int64_t)item - (int64_t)tile_offsets[lo];
         const int t = t64 < 0 ? 0x7fffffff : (int)min(t64, (int64_t)0x7fffffff);
         const char *mem = static_cast<const char *>(j.bvh_mem);
-        trace_tile<K, false>(a, reinterpret_cast<const Node *>(mem + L.nodes), reinterpret_cast<const BvhHeader *>(mem),
+        trace_tile<K, false>(a, reinterpret_cast<const WideNode *>(mem + L.wide), reinterpret_cast<const BvhHeader *>(mem),
                              t % tiles_x, t / tiles_x, lds);
     }
 }

@@ -1,0 +1,97 @@
+"""The pins catch plausible mistakes: each mutant below plants one mistake in
+a copy of oracle.c (on the CPU), and at least one pin must fail against it.
+The unmutated oracle passes the same pins (test_oracle_pins*)."""
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+import test_oracle_grad_pins as G
+import test_oracle_pins as P
+
+SRC = open(os.path.join(os.path.dirname(oracle.__file__), "oracle.c")).read()
+
+# (name, original text, mutated text): one mistake each
+MUTANTS = [
+    ("drop transmittance in colour", "C[k] += T * al * SPH(h->id, 4 + k);", "C[k] += al * SPH(h->id, 4 + k);"),
+    ("transmittance keeps alpha", "T *= (1.0 - al);", "T *= al;"),
+    ("tangent is a miss", "return disc >= 0.0 && t0 > 0.0 && t0 < t_max;", "return disc > 0.0 && t0 > 0.0 && t0 < t_max;"),
+    ("exit instead of entry", "double t0 = disc >= 0.0 ? b - sqrt(disc) : NAN;", "double t0 = disc >= 0.0 ? b + sqrt(disc) : NAN;"),
+    ("back to front order", "if (a->t0 < b->t0) return -1;\n    if (a->t0 > b->t0) return 1;",
+     "if (a->t0 > b->t0) return -1;\n    if (a->t0 < b->t0) return 1;"),
+    ("tie broken by larger id", "return (a->id > b->id) - (a->id < b->id);", "return (a->id < b->id) - (a->id > b->id);"),
+    ("stop only above the threshold", "int stop = A >= alpha_stop;", "int stop = A > alpha_stop;"),
+    ("footprint without factor 2", "double footprint = 2.0 * t * cam->tan_half_fov_y / (double)H;",
+     "double footprint = t * cam->tan_half_fov_y / (double)H;"),
+    ("rows counted from the bottom", "double sy = (1.0 - (2.0 * (double)y + 1.0) / c->height) * c->tan_half_fov_y;",
+     "double sy = ((2.0 * (double)y + 1.0) / c->height - 1.0) * c->tan_half_fov_y;"),
+    ("no aspect ratio", "double sx = ((2.0 * (double)x + 1.0) / c->width - 1.0) * c->tan_half_fov_y * aspect;",
+     "double sx = ((2.0 * (double)x + 1.0) / c->width - 1.0) * c->tan_half_fov_y;"),
+    ("perpendicular offset sign", "double v[3] = {oc[0] - b * d[0], oc[1] - b * d[1], oc[2] - b * d[2]};",
+     "double v[3] = {oc[0] + b * d[0], oc[1] + b * d[1], oc[2] + b * d[2]};"),
+    ("soft alpha linear falloff", "return a * (1.0 - u) * (1.0 - u);", "return a * (1.0 - u);"),
+    ("alpha gradient chain", "acc[8 * j + 7] += dal * (1.0 - u) * (1.0 - u);", "acc[8 * j + 7] += dal * (1.0 - u);"),
+    ("remainder ignores transmittance", "R = al * w + (1.0 - al) * R;", "R = al * w + R;"),
+    ("radius gradient power", "acc[8 * j + 3] += dal * 4.0 * a * (1.0 - u) * h->q / (r * r * r);",
+     "acc[8 * j + 3] += dal * 4.0 * a * (1.0 - u) * h->q / (r * r);"),
+    ("half truncates", "double q = rint(ldexp(a, 10 - E));", "double q = floor(ldexp(a, 10 - E));"),
+    ("no colour clamp", "col[k] = kc < 0.0 ? 0.0 : (kc > 1.0 ? 1.0 : kc);", "col[k] = kc;"),
+    ("premultiplied colour kept", "double kc = (double)rgba[4 * i + k] / A;", "double kc = (double)rgba[4 * i + k];"),
+]
+
+# pins run against each mutant (parametrised pins with their cases)
+PINS = [
+    lambda: [P.test_sphere_closed_form(*c) for c in [((0, 0, 5), 1.0, True, 4.0, 0.0),
+                                                     ((0.6, 0, 5), 1.0, True, 4.2, 0.36),
+                                                     ((1, 0, 5), 1.0, True, 5.0, 1.0)]],
+    P.test_sphere_matches_quadratic_roots,
+    P.test_two_spheres_hand_computed,
+    P.test_stop_at_alpha_hand_computed,
+    P.test_first_hit_special_case,
+    P.test_equal_depth_tie_breaks_by_id,
+    P.test_stop_knife_edge_reports_both_branches,
+    P.test_hit_sets_against_quadratic_roots_on_tiny_scene,
+    P.test_unproject_eq1_closed_form,
+    P.test_unproject_colour_is_straight_and_clamped,
+    P.test_unproject_footprint_values,
+    P.test_half_rounding_matches_numpy,
+    P.test_identity_reprojection_reproduces_source,
+    G.test_soft_alpha_closed_form,
+    G.test_two_sphere_constant_alpha_derivatives,
+    lambda: G.test_analytic_gradient_matches_central_differences(oracle.MODE_SOFT, 0.99),
+]
+
+
+def caught(lib_path: str) -> list[int]:
+    """Indices of the pins that fail against the library at lib_path."""
+    saved = oracle._LIB_PATH, oracle._lib
+    oracle._LIB_PATH, oracle._lib = lib_path, None
+    failed = []
+    try:
+        for i, pin in enumerate(PINS):
+            try:
+                pin()
+            except (AssertionError, RuntimeError, ValueError, FloatingPointError):
+                failed.append(i)
+    finally:
+        oracle._LIB_PATH, oracle._lib = saved
+    return failed
+
+
+@pytest.mark.parametrize("name,orig,mut", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_pins_catch_mutant(tmp_path, name, orig, mut):
+    assert SRC.count(orig) >= 1, f"mutation site not found: {name}"
+    src = tmp_path / "mutant.c"
+    src.write_text(SRC.replace(orig, mut, 1))  # the first occurrence: the hot-path copy
+    lib = tmp_path / "libmutant.so"
+    subprocess.check_call(["gcc", "-O1", "-fopenmp", "-fPIC", "-shared", "-std=c99", "-ffp-contract=off",
+                           "-o", str(lib), str(src), "-lm"])
+    with np.errstate(all="ignore"):
+        failed = caught(str(lib))
+    assert failed, f"no pin catches the mutant '{name}'"
+
+
+def test_unmutated_oracle_passes_every_pin():
+    assert caught(oracle._LIB_PATH) == []

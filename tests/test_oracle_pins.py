@@ -192,6 +192,15 @@ def test_unproject_eq1_closed_form():
     assert np.array_equal(colour[0], np.array([0.5, 1.0, 0.25, 0.5], dtype=np.float32))
 
 
+def test_unproject_colour_is_straight_and_clamped():
+    """k = clamp(C / A, 0, 1): a premultiplied value above A clamps to 1, a negative one to 0."""
+    cam = Cam((0.0, 0.0, 3.0), (0, 0, -1), (1, 0, 0), (0, 1, 0), 1.0, 1, 1)
+    rgba = np.array([[[0.75, -0.25, 0.2, 0.5]]], dtype=np.float32)
+    depth = np.array([[2.0]], dtype=np.float32)
+    _, colour, _ = oracle.unproject(cam, rgba, depth, 1.0, half=False)
+    assert np.array_equal(colour[0], np.array([1.0, 0.0, np.float32(0.2 / 0.5), 0.5], dtype=np.float32))
+
+
 def test_unproject_footprint_values():
     """At t = 2 with fov 45 deg: footprint 2 t tan(22.5 deg) / H."""
     for H, expect in [(64, 0.0258883476), (512, 0.00323604345), (1024, 0.00161802172)]:
