@@ -183,6 +183,7 @@ static int trace_common(const splat_bvh *bvh, const splat_spheres *sph, const sp
     std::memset(&a, 0, sizeof a);
     a.bvh_mem = bvh->mem;
     a.bvh_capacity = bvh->capacity < sph->capacity ? bvh->capacity : sph->capacity;
+    a.layout_cap = bvh->capacity;
     a.centre_radius = reinterpret_cast<const float4 *>(sph->centre_radius);
     a.rgba = sph->rgba;
     a.half = sph->rgba_dtype == SPLAT_F16;

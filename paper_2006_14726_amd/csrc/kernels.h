@@ -7,7 +7,8 @@ namespace splat {
 
 struct TraceArgs {
     const void *bvh_mem;
-    uint32_t bvh_capacity;
+    uint32_t bvh_capacity;      // spheres that may be referenced: min(BVH, sphere-array capacity)
+    uint32_t layout_cap;        // capacity the BVH allocation was laid out for
     const float4 *centre_radius;
     const void *rgba;
     int32_t half;               // colour dtype is half4

@@ -49,6 +49,12 @@ __device__ inline float4 load_colour(const void *rgba, int half, uint32_t id)
     return reinterpret_cast<const float4 *>(rgba)[id];
 }
 
+__device__ inline float load_alpha(const void *rgba, int half, uint32_t id)
+{
+    if (half) return half_to_float(reinterpret_cast<const ushort4 *>(rgba)[id].w);
+    return reinterpret_cast<const float4 *>(rgba)[id].w;
+}
+
 __device__ inline double wdot(const float4 &k, const float4 &g)
 {
     return (double)k.x * g.x + (double)k.y * g.y + (double)k.z * g.z + (double)g.w;
@@ -72,6 +78,7 @@ struct Eye {
 };
 
 constexpr int kStack = 128;  // wave traversal stack (entries)
+constexpr int kCand = 16;    // queued candidate spheres per lane (>= 4 slots per wide node)
 
 // LDS of one wave: hit buffers (column per lane) and the traversal stack.
 template <int K>
@@ -79,6 +86,7 @@ struct WaveLds {
     double t[K][kWave];     // hit distance; in the backward, the transmittance before the hit
     uint32_t id[K][kWave];
     float al[K][kWave];
+    uint32_t cand[kCand][kWave];  // queued sphere ids awaiting the exact test
     uint32_t stack[kStack];
 };
 
@@ -164,6 +172,55 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
         if (active && !(pr_f < INFINITY)) pr_f = INFINITY;
         const float lo_f = (float)(lo_t * (1.0 - 0x1p-20));
 
+        // Spheres that passed the float prefilter wait in the lane's queue;
+        // flush() settles them with the exact double test and files the hits
+        // (append, or replace the largest key once the buffer is full).
+        uint32_t nc = 0;
+        auto flush = [&]() {
+            for (uint32_t j = 0; __ballot(j < nc); ++j) {
+                if (j >= nc) continue;
+                const uint32_t id = L.cand[j][lane];
+                const float4 c = a.centre_radius[id];
+                const double oc0 = (double)c.x - eye.o[0], oc1 = (double)c.y - eye.o[1],
+                             oc2 = (double)c.z - eye.o[2];
+                const double b = oc0 * ray.d[0] + oc1 * ray.d[1] + oc2 * ray.d[2];
+                const double v0 = oc0 - b * ray.d[0], v1 = oc1 - b * ray.d[1], v2 = oc2 - b * ray.d[2];
+                const double q = v0 * v0 + v1 * v1 + v2 * v2;
+                const double r = (double)c.w;
+                const double disc = r * r - q;
+                if (disc < 0.0) continue;
+                const double t0 = b - sqrt(disc);
+                if (!(t0 > 0.0)) continue;
+                if (!key_less(lo_t, lo_id, t0, id)) continue;
+                if (!key_less(t0, id, pr_t, pr_id)) continue;
+                float al = load_alpha(a.rgba, half, id);
+                if (soft) {
+                    const double u = q / (r * r);
+                    al = (float)((double)al * (1.0 - u) * (1.0 - u));
+                }
+                const uint32_t slot = m < K ? m : mx;
+                L.t[slot][lane] = t0;
+                L.id[slot][lane] = id;
+                L.al[slot][lane] = al;
+                if (m < K) ++m;
+                if (m == K) {
+                    // the largest buffered key becomes the prune key
+                    double bt = -1.0;
+                    uint32_t bi = 0, bj = 0;
+                    for (int k = 0; k < K; ++k) {
+                        const double tk = L.t[k][lane];
+                        const uint32_t ik = L.id[k][lane];
+                        if (key_less(bt, bi, tk, ik)) { bt = tk; bi = ik; bj = (uint32_t)k; }
+                    }
+                    mx = bj;
+                    pr_t = bt;
+                    pr_id = bi;
+                    pr_f = (float)(pr_t * (1.0 + 0x1p-20));
+                }
+            }
+            nc = 0;
+        };
+
         int sp = 0;
         uint32_t node = 0;
         // a pass visits every node at most once; the cap only matters for a
@@ -181,52 +238,16 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
                 if (ref == kEmpty) continue;
                 if (ref & kLeafBit) {
                     if (!active || (ref & ~kLeafBit) >= n_spheres) continue;
-                    // float prefilter: certain miss if the ray passes farther than r + E
+                    // float prefilter: certain miss if the ray passes farther than
+                    // r + E; a survivor is only queued here (postponed leaf)
                     const float ox = s[0] - eye.of[0], oy = s[1] - eye.of[1], oz = s[2] - eye.of[2];
                     const float bf = ox * ray.df[0] + oy * ray.df[1] + oz * ray.df[2];
                     const float vx = ox - bf * ray.df[0], vy = oy - bf * ray.df[1], vz = oz - bf * ray.df[2];
                     const float qf = vx * vx + vy * vy + vz * vz;
                     const float rE = s[3] + eye.E;
                     if (qf > rE * rE) continue;
-                    // exact test in double
-                    const double oc0 = (double)s[0] - eye.o[0], oc1 = (double)s[1] - eye.o[1],
-                                 oc2 = (double)s[2] - eye.o[2];
-                    const double b = oc0 * ray.d[0] + oc1 * ray.d[1] + oc2 * ray.d[2];
-                    const double v0 = oc0 - b * ray.d[0], v1 = oc1 - b * ray.d[1], v2 = oc2 - b * ray.d[2];
-                    const double q = v0 * v0 + v1 * v1 + v2 * v2;
-                    const double r = (double)s[3];
-                    const double disc = r * r - q;
-                    if (disc < 0.0) continue;
-                    const double t0 = b - sqrt(disc);
-                    const uint32_t id = ref & ~kLeafBit;
-                    if (!(t0 > 0.0)) continue;
-                    if (!key_less(lo_t, lo_id, t0, id)) continue;
-                    if (!key_less(t0, id, pr_t, pr_id)) continue;
-                    float al = s[4];
-                    if (soft) {
-                        const double u = q / (r * r);
-                        al = (float)((double)s[4] * (1.0 - u) * (1.0 - u));
-                    }
-                    // append, or replace the largest key of a full buffer
-                    const uint32_t slot = m < K ? m : mx;
-                    L.t[slot][lane] = t0;
-                    L.id[slot][lane] = id;
-                    L.al[slot][lane] = al;
-                    if (m < K) ++m;
-                    if (m == K) {
-                        // the largest buffered key becomes the prune key
-                        double bt = -1.0;
-                        uint32_t bi = 0, bj = 0;
-                        for (int j = 0; j < K; ++j) {
-                            const double tj = L.t[j][lane];
-                            const uint32_t ij = L.id[j][lane];
-                            if (key_less(bt, bi, tj, ij)) { bt = tj; bi = ij; bj = (uint32_t)j; }
-                        }
-                        mx = bj;
-                        pr_t = bt;
-                        pr_id = bi;
-                        pr_f = (float)(pr_t * (1.0 + 0x1p-20));
-                    }
+                    L.cand[nc][lane] = ref & ~kLeafBit;
+                    ++nc;
                 } else {
                     // padded-box slab test in float, (x - o) / d as fma(x, 1/d, -o/d): the
                     // rounding of o/d moves the eye by at most eps |o|, far inside the margin
@@ -238,6 +259,8 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
                     hit[side] = tn <= tf && tf >= lo_f && tn <= pr_f && ref < n_nodes;
                 }
             }
+            // a lane's queue could overflow at the next node: test the queued spheres now
+            if (__ballot(nc > kCand - 4)) flush();
             uint32_t any = 0;  // slots whose box some lane's ray meets
 #pragma unroll
             for (int side = 0; side < 4; ++side)
@@ -274,6 +297,7 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
             }
         }
 
+        flush();
         if (!active) continue;
         // ---- sort this pass's hits by key (insertion sort of the lane's column)
         for (uint32_t i = 1; i < m; ++i) {
@@ -425,7 +449,7 @@ __global__ void __launch_bounds__(64) k_trace(TraceArgs a, int tiles_x, int tile
     int tx, ty;
     if (!tile_of_block(blockIdx.x, tiles_x, tiles_y, a.schedule, tx, ty)) return;
     const char *mem = static_cast<const char *>(a.bvh_mem);
-    const BvhLayout L(0);
+    const BvhLayout L(a.layout_cap);
     const BvhHeader *hdr = reinterpret_cast<const BvhHeader *>(mem);
     const WideNode *nodes = reinterpret_cast<const WideNode *>(mem + L.wide);
     trace_tile<K, BWD>(a, nodes, hdr, tx, ty, lds);
@@ -441,7 +465,6 @@ k_trace_batched(const splat_batch_job *__restrict__ jobs, const uint32_t *__rest
 {
     __shared__ WaveLds<K> lds;
     __shared__ uint32_t item_s;
-    const BvhLayout L(0);
     for (;;) {
         if (threadIdx.x == 0) item_s = atomicAdd(counter, 1u);
         __syncthreads();
@@ -459,6 +482,8 @@ k_trace_batched(const splat_batch_job *__restrict__ jobs, const uint32_t *__rest
         TraceArgs a;
         a.bvh_mem = j.bvh_mem;
         a.bvh_capacity = j.bvh_capacity;
+        a.layout_cap = j.bvh_capacity;
+        const BvhLayout L(a.layout_cap);
         a.centre_radius = reinterpret_cast<const float4 *>(j.centre_radius);
         a.rgba = j.rgba;
         a.half = j.rgba_dtype == SPLAT_F16;
