@@ -169,7 +169,10 @@ int splat_unproject(const splat_camera *src, const float *rgba_premul, const flo
  * stable LDS radix sort of (code, id), Karras radix-tree hierarchy, and a
  * bottom-up refit of boxes rounded outward to float.  refit_only != 0 keeps
  * the hierarchy of the previous build over the same centres and recomputes
- * the boxes and the per-leaf data (radius or colour changes).
+ * the boxes and the per-leaf data (radius or colour changes).  The BVH keeps
+ * its own copy of each sphere's centre, radius and alpha a, as read by the
+ * last build or refit: after any change to those arrays, refit (or build)
+ * before tracing.
  *   ws  device, >= splat_workspace_bytes(SPLAT_OP_BUILD, bvh->capacity, 0, 0)
  *   sph->capacity <= bvh->capacity (SPLAT_ENOSPC otherwise)
  */
@@ -182,6 +185,8 @@ int splat_build_bvh(const splat_spheres *sph, const splat_bvh *bvh, int32_t refi
  * (t0, sphere id), composited front to back, C += T alpha k, A += T alpha,
  * T *= 1 - alpha, stopping after the hit at which A >= alpha_stop.  Ray,
  * sphere test and ordering are double precision; compositing is float.
+ * Centres, radii and alphas come from the BVH's copy (see splat_build_bvh),
+ * colours from sph->rgba.
  *   out_rgba  device float4 [height][width] (C, A), background 0
  *   out_hits  device uint32 [height][width] composited hit count, or NULL
  */

@@ -548,7 +548,14 @@ k_gather_wide(const uint32_t *__restrict__ count, uint32_t cap, const Node *__re
             w[29 + c] = __uint_as_float(3u);
         }
     }
-    w[31] = 0.0f;
+    uint32_t kinds = 0;
+    for (int s = 0; s < 4; ++s) {
+        const uint32_t ref = __float_as_uint(w[24 + s]);
+        if (ref == kEmpty) continue;
+        if (ref & kLeafBit) kinds |= ((ref & ~kLeafBit) < n ? 1u : 0u) << s;
+        else kinds |= (ref < n_nodes ? 1u : 0u) << (4 + s);
+    }
+    w[31] = __uint_as_float(kinds);
     float4 *dst = reinterpret_cast<float4 *>(wide + x);
     for (int k = 0; k < 8; ++k) dst[k] = make_float4(w[4 * k], w[4 * k + 1], w[4 * k + 2], w[4 * k + 3]);
 }

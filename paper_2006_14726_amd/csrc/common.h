@@ -118,6 +118,10 @@ struct __align__(64) Node {
 //   f[24..27]: slot references (binary node index of an internal grandchild,
 //              whose own wide node is wide[index]; kLeafBit | sphere id; kEmpty)
 //   f[28..30]: split axes of X, of X's child 0 and of X's child 1 (3 = none)
+//   f[31]:     slot kinds (uint32): bit s marks slot s as a sphere of the
+//              set, bit 4 + s as an internal node of the hierarchy
+//   A sphere slot holds the centre, radius and opacity of the sphere (as
+//   read at the last build or refit) and 0.
 struct __align__(128) WideNode {
     float f[32];
 };

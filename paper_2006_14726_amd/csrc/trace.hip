@@ -5,14 +5,20 @@
 // One 64-lane wavefront traces one tile of pixels as a packet: the BVH walk
 // is wave-uniform (node fetched once per wave with scalar loads, stack of
 // node indices in LDS, a child is visited if any lane's ray meets its box),
-// while each lane gathers its own hits.  Per traversal pass a lane keeps the
-// K hits with the smallest keys (t0, sphere id) greater than the last key it
-// composited, in an unsorted LDS buffer of its own; once the buffer is full,
-// nodes beyond its largest key are pruned.  The buffer is sorted once at the
-// end of the pass and composited; if it was full and the alpha stop was not
-// reached, the lane runs another pass from its last key.  So there is no cap
-// on hits, and the result depends neither on K, nor on the tile shape, nor
-// on the other lanes of the wave.
+// while each lane gathers its own hits.  A visit costs the wave its whole
+// instruction stream whatever the number of lanes that need it, so the walk
+// keeps it short: slot kinds come precomputed with the node, child order is
+// chosen with scalar selects, and the spheres that pass a lane's float
+// prefilter are queued and settled by the exact test in batches.
+//
+// Per traversal pass a lane keeps the K hits with the smallest keys
+// (t0, sphere id) greater than the last key it composited, sorted in
+// registers.  Nodes beyond the hit at which the alpha stop is already
+// certain, or beyond the largest key of a full buffer, are pruned.  At the
+// end of the pass the buffer is composited; if it was full and the alpha
+// stop was not reached, the lane runs another pass from its last key.  So
+// there is no cap on hits, and the result depends neither on K, nor on the
+// tile shape, nor on the other lanes of the wave.
 //
 // Precision: ray and sphere test in double (hits are settled far below a
 // relative discriminant of 1e-6), keys in double, boxes in float with a
@@ -78,23 +84,30 @@ struct Eye {
 };
 
 constexpr int kStack = 128;  // wave traversal stack (entries)
-constexpr int kCand = 16;    // queued candidate spheres per lane (>= 4 slots per wide node)
+constexpr int kQueue = 8;    // leaf candidates queued per lane (at least the 4 slots of one node)
 
-// LDS of one wave: hit buffers (column per lane) and the traversal stack.
-template <int K>
+// LDS of one wave: the leaf candidates awaiting the exact test (a column per
+// lane) and the traversal stack.
 struct WaveLds {
-    double t[K][kWave];     // hit distance; in the backward, the transmittance before the hit
-    uint32_t id[K][kWave];
-    float al[K][kWave];
-    uint32_t cand[kCand][kWave];  // queued sphere ids awaiting the exact test
+    uint32_t cand[kQueue][kWave];  // (wide node index << 2) | slot
     uint32_t stack[kStack];
+};
+
+// A lane's hits of one pass, sorted by key, in registers (every index is a
+// compile-time constant).  Empty entries hold the key (+inf, ~0), which is
+// above every hit.
+template <int K>
+struct HitBuf {
+    double t[K];  // hit distance; in the backward, the transmittance before the hit
+    uint32_t id[K];
+    float al[K];
 };
 
 // ---------------------------------------------------------------- one tile
 
 template <int K, bool BWD>
 __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ nodes, const BvhHeader *__restrict__ hdr,
-                           int tile_x, int tile_y, WaveLds<K> &L)
+                           int tile_x, int tile_y, WaveLds &L)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int px = tile_x * a.tile_w + (lane % a.tile_w);
@@ -163,62 +176,103 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
     double G64 = 0.0, P64 = 0.0, T64 = 1.0;
     if (BWD && inside) g = a.grad[(size_t)py * a.cam.w + px];
 
+    HitBuf<K> B;
     while (__ballot(active)) {
         // ---- one traversal pass
-        uint32_t m = 0, mx = 0;                  // buffered hits; slot of the largest once full
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            B.t[k] = INFINITY;
+            B.id[k] = 0xffffffffu;
+            B.al[k] = 0.0f;
+        }
+        uint32_t m = 0;                          // buffered hits
         double pr_t = active ? a.t_max : -1.0;   // prune key: hits must be below it
         uint32_t pr_id = 0;
         float pr_f = active ? (float)(pr_t * (1.0 + 0x1p-20)) : -INFINITY;
         if (active && !(pr_f < INFINITY)) pr_f = INFINITY;
         const float lo_f = (float)(lo_t * (1.0 - 0x1p-20));
+        uint32_t nc = 0;                         // queued leaf candidates
 
-        // Spheres that passed the float prefilter wait in the lane's queue;
-        // flush() settles them with the exact double test and files the hits
-        // (append, or replace the largest key once the buffer is full).
-        uint32_t nc = 0;
+        // The exact test of the queued candidates.  A leaf slot holds the
+        // sphere's centre, radius and opacity as stored by the last build or
+        // refit; the node was fetched moments ago, so the slot is read from
+        // cache.  A hit below the prune key is filed in key order; a full
+        // buffer drops its largest key, and its new largest key becomes the
+        // prune key.  Afterwards the prune key moves down to the hit at which
+        // the alpha stop is already certain (the same float steps as the
+        // compositing below).
         auto flush = [&]() {
-            for (uint32_t j = 0; __ballot(j < nc); ++j) {
+            bool changed = false;
+            for (uint32_t j = 0; j < (uint32_t)kQueue; ++j) {
+                if (!__ballot(j < nc)) break;
                 if (j >= nc) continue;
-                const uint32_t id = L.cand[j][lane];
-                const float4 c = a.centre_radius[id];
-                const double oc0 = (double)c.x - eye.o[0], oc1 = (double)c.y - eye.o[1],
-                             oc2 = (double)c.z - eye.o[2];
+                const uint32_t e = L.cand[j][lane];
+                const float *s = nodes[e >> 2].f + 6 * (e & 3u);
+                const float2 s01 = *reinterpret_cast<const float2 *>(s);
+                const float2 s23 = *reinterpret_cast<const float2 *>(s + 2);
+                const float ca = s[4];
+                const uint32_t id = __float_as_uint(nodes[e >> 2].f[24 + (e & 3u)]) & ~kLeafBit;
+                if (id >= n_spheres) continue;
+                const double oc0 = (double)s01.x - eye.o[0], oc1 = (double)s01.y - eye.o[1],
+                             oc2 = (double)s23.x - eye.o[2];
                 const double b = oc0 * ray.d[0] + oc1 * ray.d[1] + oc2 * ray.d[2];
                 const double v0 = oc0 - b * ray.d[0], v1 = oc1 - b * ray.d[1], v2 = oc2 - b * ray.d[2];
                 const double q = v0 * v0 + v1 * v1 + v2 * v2;
-                const double r = (double)c.w;
+                const double r = (double)s23.y;
                 const double disc = r * r - q;
                 if (disc < 0.0) continue;
                 const double t0 = b - sqrt(disc);
                 if (!(t0 > 0.0)) continue;
                 if (!key_less(lo_t, lo_id, t0, id)) continue;
                 if (!key_less(t0, id, pr_t, pr_id)) continue;
-                float al = load_alpha(a.rgba, half, id);
+                float al = ca;
                 if (soft) {
                     const double u = q / (r * r);
                     al = (float)((double)al * (1.0 - u) * (1.0 - u));
                 }
-                const uint32_t slot = m < K ? m : mx;
-                L.t[slot][lane] = t0;
-                L.id[slot][lane] = id;
-                L.al[slot][lane] = al;
-                if (m < K) ++m;
-                if (m == K) {
-                    // the largest buffered key becomes the prune key
-                    double bt = -1.0;
-                    uint32_t bi = 0, bj = 0;
-                    for (int k = 0; k < K; ++k) {
-                        const double tk = L.t[k][lane];
-                        const uint32_t ik = L.id[k][lane];
-                        if (key_less(bt, bi, tk, ik)) { bt = tk; bi = ik; bj = (uint32_t)k; }
-                    }
-                    mx = bj;
-                    pr_t = bt;
-                    pr_id = bi;
+                // insertion network: entry k takes entry k - 1 when the new key is
+                // below that, the new hit when it lands at k, else stays
+                bool lt[K];
+#pragma unroll
+                for (int k = 0; k < K; ++k) lt[k] = key_less(t0, id, B.t[k], B.id[k]);
+#pragma unroll
+                for (int k = K - 1; k > 0; --k) {
+                    const bool here = lt[k] && !lt[k - 1];
+                    B.t[k] = lt[k - 1] ? B.t[k - 1] : (here ? t0 : B.t[k]);
+                    B.id[k] = lt[k - 1] ? B.id[k - 1] : (here ? id : B.id[k]);
+                    B.al[k] = lt[k - 1] ? B.al[k - 1] : (here ? al : B.al[k]);
+                }
+                if (lt[0]) {
+                    B.t[0] = t0;
+                    B.id[0] = id;
+                    B.al[0] = al;
+                }
+                m = m < K ? m + 1 : K;
+                changed = true;
+                if (key_less(B.t[K - 1], B.id[K - 1], pr_t, pr_id)) {
+                    // full: later candidates must beat the new largest key
+                    pr_t = B.t[K - 1];
+                    pr_id = B.id[K - 1];
                     pr_f = (float)(pr_t * (1.0 + 0x1p-20));
                 }
             }
             nc = 0;
+            if (changed) {
+                float As = A, Ts = T, w;
+                bool found = false;
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    if (!found && (uint32_t)k < m) {
+                        alpha_step(B.al[k], As, Ts, w);
+                        if (As >= stop) {
+                            found = true;
+                            pr_t = B.t[k];
+                            pr_id = B.id[k];
+                            pr_f = (float)(pr_t * (1.0 + 0x1p-20));
+                        }
+                    }
+                }
+            }
         };
 
         int sp = 0;
@@ -230,120 +284,116 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
             float f[32];
 #pragma unroll
             for (int k = 0; k < 32; ++k) f[k] = nd->f[k];
-            bool hit[4] = {false, false, false, false};
+            const uint32_t kinds = __float_as_uint(f[31]);  // bits 0-3 leaf slots, 4-7 internal slots
+            if (kinds & 0xfu) {
+                // leaf slots: float prefilter, certain misses only (the ray passes
+                // farther than r + E from the centre, or the sphere lies wholly
+                // beyond the prune key or before the last composited key: t0 lies
+                // in [b - r, b], and E bounds the error of the float b).  A
+                // survivor is queued for the exact test.
 #pragma unroll
-            for (int side = 0; side < 4; ++side) {
-                const uint32_t ref = __float_as_uint(f[24 + side]);
-                const float *s = f + 6 * side;
-                if (ref == kEmpty) continue;
-                if (ref & kLeafBit) {
-                    if (!active || (ref & ~kLeafBit) >= n_spheres) continue;
-                    // float prefilter: certain miss if the ray passes farther than
-                    // r + E; a survivor is only queued here (postponed leaf)
+                for (int side = 0; side < 4; ++side) {
+                    if (!((kinds >> side) & 1u)) continue;
+                    const float *s = f + 6 * side;
                     const float ox = s[0] - eye.of[0], oy = s[1] - eye.of[1], oz = s[2] - eye.of[2];
                     const float bf = ox * ray.df[0] + oy * ray.df[1] + oz * ray.df[2];
                     const float vx = ox - bf * ray.df[0], vy = oy - bf * ray.df[1], vz = oz - bf * ray.df[2];
                     const float qf = vx * vx + vy * vy + vz * vz;
                     const float rE = s[3] + eye.E;
-                    if (qf > rE * rE) continue;
-                    L.cand[nc][lane] = ref & ~kLeafBit;
-                    ++nc;
-                } else {
-                    // padded-box slab test in float, (x - o) / d as fma(x, 1/d, -o/d): the
-                    // rounding of o/d moves the eye by at most eps |o|, far inside the margin
-                    const float t1x = fmaf(s[0], ray.inv[0], -ray.oPi[0]), t2x = fmaf(s[3], ray.inv[0], -ray.oMi[0]);
-                    const float t1y = fmaf(s[1], ray.inv[1], -ray.oPi[1]), t2y = fmaf(s[4], ray.inv[1], -ray.oMi[1]);
-                    const float t1z = fmaf(s[2], ray.inv[2], -ray.oPi[2]), t2z = fmaf(s[5], ray.inv[2], -ray.oMi[2]);
-                    const float tn = fmaxf(fmaxf(fminf(t1x, t2x), fminf(t1y, t2y)), fminf(t1z, t2z));
-                    const float tf = fminf(fminf(fmaxf(t1x, t2x), fmaxf(t1y, t2y)), fmaxf(t1z, t2z)) * 1.0000005f;
-                    hit[side] = tn <= tf && tf >= lo_f && tn <= pr_f && ref < n_nodes;
+                    const bool may = (qf <= rE * rE) & (bf - rE <= pr_f) & (bf + eye.E >= lo_f);
+                    // nc < kQueue here: the queue is flushed once a lane could overflow
+                    L.cand[nc][lane] = (node << 2) | (uint32_t)side;
+                    nc += may ? 1u : 0u;
                 }
+                if (__ballot(nc > (uint32_t)kQueue - 4u)) flush();
             }
-            // a lane's queue could overflow at the next node: test the queued spheres now
-            if (__ballot(nc > kCand - 4)) flush();
-            uint32_t any = 0;  // slots whose box some lane's ray meets
+            // internal slots: padded-box slab test in float, (x - o) / d as
+            // fma(x, 1/d, -o/d): the rounding of o/d moves the eye by at most
+            // eps |o|, far inside the margin
+            uint32_t boxes = 0;  // slots whose box some lane's ray meets
 #pragma unroll
-            for (int side = 0; side < 4; ++side)
-                if (__ballot(hit[side])) any |= 1u << side;
-            if (any) {
-                // near-first order: the near child of the node, within it the near grandchild
-                const uint32_t ax = __float_as_uint(f[28]);
-                const uint32_t cn = (ax < 3 && ((neg_mask >> ax) & 1u)) ? 1u : 0u;
-                const uint32_t axn = __float_as_uint(f[29 + cn]), axf = __float_as_uint(f[30 - cn]);
-                const uint32_t gn = (axn < 3 && ((neg_mask >> axn) & 1u)) ? 1u : 0u;
-                const uint32_t gf = (axf < 3 && ((neg_mask >> axf) & 1u)) ? 1u : 0u;
-                const uint32_t order[4] = {2 * cn + gn, 2 * cn + (1u - gn), 2 * (1u - cn) + gf,
-                                           2 * (1u - cn) + (1u - gf)};
+            for (int side = 0; side < 4; ++side) {
+                if (!((kinds >> (4 + side)) & 1u)) continue;
+                const float *s = f + 6 * side;
+                const float t1x = fmaf(s[0], ray.inv[0], -ray.oPi[0]), t2x = fmaf(s[3], ray.inv[0], -ray.oMi[0]);
+                const float t1y = fmaf(s[1], ray.inv[1], -ray.oPi[1]), t2y = fmaf(s[4], ray.inv[1], -ray.oMi[1]);
+                const float t1z = fmaf(s[2], ray.inv[2], -ray.oPi[2]), t2z = fmaf(s[5], ray.inv[2], -ray.oMi[2]);
+                const float tn = fmaxf(fmaxf(fminf(t1x, t2x), fminf(t1y, t2y)), fminf(t1z, t2z));
+                const float tf = fminf(fminf(fmaxf(t1x, t2x), fmaxf(t1y, t2y)), fmaxf(t1z, t2z)) * 1.0000005f;
+                if (__ballot((tn <= tf) & (tf >= lo_f) & (tn <= pr_f))) boxes |= 1u << side;
+            }
+            if (boxes) {
+                // near-first order: the near child of the node, within it the
+                // near grandchild (split axes against the first lane's ray)
+                const uint32_t ax = __float_as_uint(f[28]), a0 = __float_as_uint(f[29]), a1 = __float_as_uint(f[30]);
+                const uint32_t cn = ax < 3u ? (neg_mask >> ax) & 1u : 0u;
+                const uint32_t axn = cn ? a1 : a0, axf = cn ? a0 : a1;
+                const uint32_t gn = axn < 3u ? (neg_mask >> axn) & 1u : 0u;
+                const uint32_t gf = axf < 3u ? (neg_mask >> axf) & 1u : 0u;
+                const uint32_t o0 = 2u * cn + gn, o2 = 2u * (1u - cn) + gf;
+                const uint32_t order = o0 | ((o0 ^ 1u) << 2) | (o2 << 4) | ((o2 ^ 1u) << 6);
                 // descend into the nearest slot hit; push the others, farthest first
-                int first = -1;
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    if (first < 0 && ((any >> order[i]) & 1u)) first = i;
+                uint32_t next = kEmpty;
 #pragma unroll
                 for (int i = 3; i >= 0; --i) {
-                    if (i <= first || !((any >> order[i]) & 1u)) continue;
-                    // a wide level pushes at most 3 entries and the wide depth is
-                    // at most 32 for 62-bit (code, position) keys: 128 slots suffice
-                    if (sp < kStack) {
-                        if (lane == 0) L.stack[sp] = __float_as_uint(f[24 + order[i]]);
-                        ++sp;
+                    const uint32_t o = (order >> (2 * i)) & 3u;
+                    if (!((boxes >> o) & 1u)) continue;
+                    if (next != kEmpty) {
+                        // a wide level pushes at most 3 entries and the wide depth is
+                        // at most 32 for 62-bit (code, position) keys: 128 slots suffice
+                        if (sp < kStack) {
+                            if (lane == 0) L.stack[sp] = next;
+                            ++sp;
+                        }
                     }
+                    next = o == 0 ? __float_as_uint(f[24]) : o == 1 ? __float_as_uint(f[25])
+                         : o == 2 ? __float_as_uint(f[26]) : __float_as_uint(f[27]);
                 }
-                node = __float_as_uint(f[24 + order[first]]);
+                node = next;
             } else {
                 if (sp == 0) break;
                 --sp;
                 node = ufirst(L.stack[sp]);
             }
+            // only a corrupt hierarchy can name a node outside the array
+            node = min(node, n_nodes - 1);
         }
-
-        flush();
+        if (__ballot(nc > 0)) flush();
         if (!active) continue;
-        // ---- sort this pass's hits by key (insertion sort of the lane's column)
-        for (uint32_t i = 1; i < m; ++i) {
-            const double ti = L.t[i][lane];
-            const uint32_t ii = L.id[i][lane];
-            const float ai = L.al[i][lane];
-            uint32_t j = i;
-            while (j > 0 && key_less(ti, ii, L.t[j - 1][lane], L.id[j - 1][lane])) {
-                L.t[j][lane] = L.t[j - 1][lane];
-                L.id[j][lane] = L.id[j - 1][lane];
-                L.al[j][lane] = L.al[j - 1][lane];
-                --j;
-            }
-            L.t[j][lane] = ti;
-            L.id[j][lane] = ii;
-            L.al[j][lane] = ai;
-        }
-        const double last_t = m ? L.t[m - 1][lane] : 0.0;
-        const uint32_t last_id = m ? L.id[m - 1][lane] : 0u;
+        // the last key, where a further pass starts
+        const double last_t = B.t[K - 1];
+        const uint32_t last_id = B.id[K - 1];
 
         // ---- composite this pass
         bool done = false;
         uint32_t used = 0;
-        for (uint32_t j = 0; j < m && !done; ++j) {
-            const uint32_t id = L.id[j][lane];
-            const float al = L.al[j][lane];
-            const float4 col = load_colour(a.rgba, half, id);
-            float w;
-            alpha_step(al, A, T, w);
-            C[0] = __fadd_rn(C[0], __fmul_rn(w, col.x));
-            C[1] = __fadd_rn(C[1], __fmul_rn(w, col.y));
-            C[2] = __fadd_rn(C[2], __fmul_rn(w, col.z));
-            if (BWD) {
-                L.t[j][lane] = T64;  // transmittance before hit j, for the gradients
-                T64 *= 1.0 - (double)al;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if ((uint32_t)k < m && !done) {
+                const float al = B.al[k];
+                const float4 col = load_colour(a.rgba, half, B.id[k]);
+                float w;
+                alpha_step(al, A, T, w);
+                C[0] = __fadd_rn(C[0], __fmul_rn(w, col.x));
+                C[1] = __fadd_rn(C[1], __fmul_rn(w, col.y));
+                C[2] = __fadd_rn(C[2], __fmul_rn(w, col.z));
+                if (BWD) {
+                    B.t[k] = T64;  // transmittance before hit k, for the gradients
+                    T64 *= 1.0 - (double)al;
+                }
+                ++n_hit;
+                ++used;
+                if (A >= stop) done = true;
             }
-            ++n_hit;
-            ++used;
-            if (A >= stop) done = true;
         }
         const bool more = !done && m == K;
         if (BWD) {
             // sum over this pass of T_j alpha_j w_j, w_j = k_j . g_C + g_A
             double Pc = 0.0;
-            for (uint32_t j = 0; j < used; ++j)
-                Pc += L.t[j][lane] * (double)L.al[j][lane] * wdot(load_colour(a.rgba, half, L.id[j][lane]), g);
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                if ((uint32_t)k < used)
+                    Pc += B.t[k] * (double)B.al[k] * wdot(load_colour(a.rgba, half, B.id[k]), g);
             if (phase == 0 && more) {
                 phase = 1;  // the total G is needed: sweep the rest first
                 G64 = Pc;
@@ -360,11 +410,12 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
             } else {
                 // remainder behind this pass, composited from full transmittance
                 double R = (more && T64 > 0.0) ? (G64 - (P64 + Pc)) / T64 : 0.0;
-                for (uint32_t jj = used; jj > 0; --jj) {
-                    const uint32_t j = jj - 1;
-                    const uint32_t id = L.id[j][lane];
-                    const double al = (double)L.al[j][lane];
-                    const double Tj = L.t[j][lane];
+#pragma unroll
+                for (int k = K - 1; k >= 0; --k) {
+                    if ((uint32_t)k >= used) continue;
+                    const uint32_t id = B.id[k];
+                    const double al = (double)B.al[k];
+                    const double Tj = B.t[k];
                     const float4 col = load_colour(a.rgba, half, id);
                     const double wj = wdot(col, g);
                     const double dal = Tj * (wj - R);
@@ -445,7 +496,7 @@ __host__ inline uint32_t blocks_for(int tiles_x, int tiles_y, int schedule)
 template <int K, bool BWD>
 __global__ void __launch_bounds__(64) k_trace(TraceArgs a, int tiles_x, int tiles_y)
 {
-    __shared__ WaveLds<K> lds;
+    __shared__ WaveLds lds;
     int tx, ty;
     if (!tile_of_block(blockIdx.x, tiles_x, tiles_y, a.schedule, tx, ty)) return;
     const char *mem = static_cast<const char *>(a.bvh_mem);
@@ -463,7 +514,7 @@ k_trace_batched(const splat_batch_job *__restrict__ jobs, const uint32_t *__rest
                 uint32_t total_tiles, float alpha_stop, int mode, double t_max, int tile_w, int tile_h,
                 uint32_t *__restrict__ counter)
 {
-    __shared__ WaveLds<K> lds;
+    __shared__ WaveLds lds;
     __shared__ uint32_t item_s;
     for (;;) {
         if (threadIdx.x == 0) item_s = atomicAdd(counter, 1u);
