@@ -41,6 +41,9 @@ extern "C" {
 #define SPLAT_ALPHA_CONSTANT 0 /* alpha = a: the paper's constant sample colour */
 #define SPLAT_ALPHA_SOFT 1     /* alpha = a (1 - q/r^2)^2, q = squared ray-centre distance */
 
+#define SPLAT_WALK_LANE 0      /* every lane walks the BVH on its own path */
+#define SPLAT_WALK_PACKET 1    /* the 64 lanes of a wavefront walk it together */
+
 #define SPLAT_OP_UNPROJECT 0
 #define SPLAT_OP_BUILD 1
 #define SPLAT_OP_TRACE 2
@@ -101,12 +104,15 @@ typedef struct splat_bvh {
  *               (0.99 by default; 0 = the paper's first-hit query; > 1 never)
  *   t_max       hits must satisfy 0 < t0 < t_max (INFINITY for none)
  *   mode        SPLAT_ALPHA_CONSTANT or SPLAT_ALPHA_SOFT
- *   kbuf        hits gathered per traversal pass: 1, 2, 4, 8 or 16 (0 = 8);
+ *   kbuf        hits gathered per traversal pass: 1, 2, 4, 6, 8 or 16 (0 = 6);
  *               the result does not depend on it
  *   tile_w/h    pixels per 64-lane wavefront: 8x8, 16x4, 32x2, 64x1 or 4x16
  *               (0x0 = 8x8); the result does not depend on it
  *   schedule    tile -> XCD assignment: 0 super-tiles of 8x8 tiles dealt
  *               round robin to the XCDs, 1 one contiguous band per XCD; the
+ *               result does not depend on it
+ *   walk        SPLAT_WALK_LANE (each ray on its own path; default) or
+ *               SPLAT_WALK_PACKET (a wavefront's rays as one packet); the
  *               result does not depend on it
  */
 typedef struct splat_trace_opts {
@@ -117,6 +123,7 @@ typedef struct splat_trace_opts {
     int32_t tile_w;
     int32_t tile_h;
     int32_t schedule;
+    int32_t walk;
 } splat_trace_opts;
 
 /* Per-sphere gradients, device float arrays indexed by sphere id; accumulated into (+=). */

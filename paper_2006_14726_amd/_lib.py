@@ -10,6 +10,7 @@ LIB_PATH = os.path.join(HERE, "libsplat.so")
 SPLAT_OK, SPLAT_EINVAL, SPLAT_ENOSPC, SPLAT_ENODEV, SPLAT_EHIP, SPLAT_EUNSUPPORTED = range(6)
 SPLAT_F32, SPLAT_F16 = 0, 1
 SPLAT_ALPHA_CONSTANT, SPLAT_ALPHA_SOFT = 0, 1
+SPLAT_WALK_LANE, SPLAT_WALK_PACKET = 0, 1
 SPLAT_OP_UNPROJECT, SPLAT_OP_BUILD, SPLAT_OP_TRACE, SPLAT_OP_BACKWARD, SPLAT_OP_BATCHED = range(5)
 
 # every symbol include/splat.h declares
@@ -37,7 +38,7 @@ class splat_bvh(ctypes.Structure):
 class splat_trace_opts(ctypes.Structure):
     _fields_ = [("alpha_stop", ctypes.c_float), ("mode", ctypes.c_int32), ("t_max", ctypes.c_double),
                 ("kbuf", ctypes.c_int32), ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
-                ("schedule", ctypes.c_int32)]
+                ("schedule", ctypes.c_int32), ("walk", ctypes.c_int32)]
 
 
 class splat_grads(ctypes.Structure):

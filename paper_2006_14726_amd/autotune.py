@@ -1,5 +1,6 @@
 """Autotuner for the trace schedule: hits per pass (kbuf), tile shape, the
-tile -> XCD schedule and, for the batched launch, resident waves.
+tile -> XCD schedule, the walk (per lane or per packet) and, for the batched
+launch, resident waves.
 
 Every candidate produces the same image (the traversal result does not
 depend on these knobs), so the tuner only times them, with events on the
@@ -17,7 +18,8 @@ import torch
 
 from .render import BVH, Spheres, TraceOptions, trace
 
-TRACE_CANDIDATES = [(k, tile, sched) for k in (4, 8) for tile in ((8, 8), (16, 4)) for sched in (0, 1)]
+TRACE_CANDIDATES = [(k, tile, sched, walk) for k in (6, 8) for tile in ((8, 8), (16, 4)) for sched in (0, 1)
+                    for walk in (0, 1)]
 WAVES_PER_CU = (8, 16, 32)
 
 
@@ -66,30 +68,31 @@ def _time(fn, reps: int) -> float:
 
 def tune_trace(bvh: BVH, sph: Spheres, cam, base: TraceOptions | None = None, reps: int = 5,
                use_cache: bool = True) -> tuple[TraceOptions, dict]:
-    """Fastest (kbuf, tile, schedule) for tracing this sphere set from this camera size."""
+    """Fastest (kbuf, tile, schedule, walk) for tracing this sphere set from this camera size."""
     base = base or TraceOptions()
     dev = sph.centre_radius.device
     key = f"{_arch(dev)}|trace|rays{_bucket(cam.width * cam.height)}|sph{_bucket(sph.capacity)}|mode{base.mode}"
     if use_cache:
         hit = _load_cache().get(key)
         if hit:
-            return replace(base, kbuf=hit["kbuf"], tile=tuple(hit["tile"]), schedule=hit["schedule"]), hit
+            return replace(base, kbuf=hit["kbuf"], tile=tuple(hit["tile"]), schedule=hit["schedule"],
+                           walk=hit.get("walk", 0)), hit
     out = torch.empty((cam.height, cam.width, 4), dtype=torch.float32, device=dev)
     hits = torch.empty((cam.height, cam.width), dtype=torch.int32, device=dev)
     timings = {}
-    for k, tile, sched in TRACE_CANDIDATES:
-        o = replace(base, kbuf=k, tile=tile, schedule=sched)
-        timings[f"k{k}_{tile[0]}x{tile[1]}_s{sched}"] = _time(lambda: trace(bvh, sph, cam, o, out=out, hits=hits),
-                                                              reps)
+    for k, tile, sched, walk in TRACE_CANDIDATES:
+        o = replace(base, kbuf=k, tile=tile, schedule=sched, walk=walk)
+        timings[f"k{k}_{tile[0]}x{tile[1]}_s{sched}_w{walk}"] = _time(
+            lambda: trace(bvh, sph, cam, o, out=out, hits=hits), reps)
     best = min(timings, key=timings.get)
-    k, tile, sched = TRACE_CANDIDATES[list(timings).index(best)]
-    rec = {"kbuf": k, "tile": list(tile), "schedule": sched, "ms": timings[best], "all_ms": timings}
+    k, tile, sched, walk = TRACE_CANDIDATES[list(timings).index(best)]
+    rec = {"kbuf": k, "tile": list(tile), "schedule": sched, "walk": walk, "ms": timings[best], "all_ms": timings}
     _store(key, rec)
-    return replace(base, kbuf=k, tile=tile, schedule=sched), rec
+    return replace(base, kbuf=k, tile=tile, schedule=sched, walk=walk), rec
 
 
 def tune_batched(renderer, reps: int = 3, use_cache: bool = True) -> dict:
-    """Fastest (kbuf, tile, resident waves) for a batched renderer; applies it to the renderer."""
+    """Fastest (kbuf, tile, walk, resident waves) for a batched renderer; applies it to the renderer."""
     dev = renderer.device
     cus = torch.cuda.get_device_properties(dev).multi_processor_count
     key = f"{_arch(dev)}|batched|jobs{_bucket(renderer.n_jobs)}|rays{_bucket(renderer.rays)}"
@@ -100,12 +103,13 @@ def tune_batched(renderer, reps: int = 3, use_cache: bool = True) -> dict:
             return hit
     renderer.prepare()
     timings = {}
-    for k in (4, 8):
+    for k in (6, 8):
         for tile in ((8, 8), (16, 4)):
-            for wpc in WAVES_PER_CU:
-                rec = {"kbuf": k, "tile": list(tile), "waves": wpc * cus}
-                _apply(renderer, rec)
-                timings[json.dumps(rec)] = _time(renderer.trace_batched, reps)
+            for walk in (0, 1):
+                for wpc in WAVES_PER_CU:
+                    rec = {"kbuf": k, "tile": list(tile), "walk": walk, "waves": wpc * cus}
+                    _apply(renderer, rec)
+                    timings[json.dumps(rec)] = _time(renderer.trace_batched, reps)
     best = min(timings, key=timings.get)
     rec = json.loads(best)
     rec["ms"] = timings[best]
@@ -115,4 +119,5 @@ def tune_batched(renderer, reps: int = 3, use_cache: bool = True) -> dict:
 
 
 def _apply(renderer, rec: dict) -> None:
-    renderer.set_schedule(replace(renderer.opts, kbuf=rec["kbuf"], tile=tuple(rec["tile"])), rec["waves"])
+    renderer.set_schedule(replace(renderer.opts, kbuf=rec["kbuf"], tile=tuple(rec["tile"]), walk=rec.get("walk", 0)),
+                          rec["waves"])

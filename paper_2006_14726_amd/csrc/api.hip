@@ -86,9 +86,9 @@ int resolve_opts(const splat_trace_opts *o, splat_trace_opts *out)
 {
     if (!o) return fail(SPLAT_EINVAL, "opts is NULL");
     *out = *o;
-    if (out->kbuf == 0) out->kbuf = 8;
-    if (out->kbuf != 1 && out->kbuf != 2 && out->kbuf != 4 && out->kbuf != 8 && out->kbuf != 16)
-        return fail(SPLAT_EUNSUPPORTED, "kbuf %d not in {1,2,4,8,16}", out->kbuf);
+    if (out->kbuf == 0) out->kbuf = 6;
+    if (out->kbuf != 1 && out->kbuf != 2 && out->kbuf != 4 && out->kbuf != 6 && out->kbuf != 8 && out->kbuf != 16)
+        return fail(SPLAT_EUNSUPPORTED, "kbuf %d not in {1,2,4,6,8,16}", out->kbuf);
     if (out->tile_w == 0 && out->tile_h == 0) {
         out->tile_w = 8;
         out->tile_h = 8;
@@ -101,6 +101,8 @@ int resolve_opts(const splat_trace_opts *o, splat_trace_opts *out)
         return fail(SPLAT_EUNSUPPORTED, "unknown alpha mode %d", out->mode);
     if (out->schedule != 0 && out->schedule != 1)
         return fail(SPLAT_EUNSUPPORTED, "unknown schedule %d", out->schedule);
+    if (out->walk != SPLAT_WALK_LANE && out->walk != SPLAT_WALK_PACKET)
+        return fail(SPLAT_EUNSUPPORTED, "unknown walk %d", out->walk);
     if (std::isnan(out->alpha_stop)) return fail(SPLAT_EINVAL, "alpha_stop is NaN");
     if (!(out->t_max > 0)) return fail(SPLAT_EINVAL, "t_max must be positive");
     return SPLAT_OK;
@@ -116,7 +118,7 @@ int hip_status(hipError_t e, const char *what)
 
 extern "C" {
 
-int splat_version(void) { return 100; }
+int splat_version(void) { return 101; }
 
 const char *splat_last_error(void) { return g_err; }
 
@@ -195,6 +197,7 @@ static int trace_common(const splat_bvh *bvh, const splat_spheres *sph, const sp
     a.tile_w = o.tile_w;
     a.tile_h = o.tile_h;
     a.schedule = o.schedule;
+    a.walk = o.walk;
     return SPLAT_OK;
 }
 

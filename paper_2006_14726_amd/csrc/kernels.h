@@ -19,6 +19,7 @@ struct TraceArgs {
     int32_t kbuf;
     int32_t tile_w, tile_h;
     int32_t schedule;           // tile -> XCD assignment (0 super-tiles, 1 bands)
+    int32_t walk;               // SPLAT_WALK_LANE or SPLAT_WALK_PACKET
     float4 *out;                // forward output
     uint32_t *hits;             // nullable
     // backward only

@@ -85,12 +85,14 @@ struct Eye {
 
 constexpr int kStack = 128;  // wave traversal stack (entries)
 constexpr int kQueue = 8;    // leaf candidates queued per lane (at least the 4 slots of one node)
+constexpr uint32_t kLaneStack = 16;  // per-lane walk: stack entries per lane (a power of 2)
 
 // LDS of one wave: the leaf candidates awaiting the exact test (a column per
 // lane) and the traversal stack.
 struct WaveLds {
-    uint32_t cand[kQueue][kWave];  // (wide node index << 2) | slot
-    uint32_t stack[kStack];
+    uint32_t cand[kQueue][kWave];        // (wide node index << 2) | slot
+    uint32_t lstack[kLaneStack][kWave];  // per-lane walk: a stack per lane
+    uint32_t stack[kStack];              // packet walk: one stack per wave
 };
 
 // A lane's hits of one pass, sorted by key, in registers (every index is a
@@ -105,7 +107,7 @@ struct HitBuf {
 
 // ---------------------------------------------------------------- one tile
 
-template <int K, bool BWD>
+template <int K, bool BWD, bool LANE>
 __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ nodes, const BvhHeader *__restrict__ hdr,
                            int tile_x, int tile_y, WaveLds &L)
 {
@@ -192,6 +194,7 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
         if (active && !(pr_f < INFINITY)) pr_f = INFINITY;
         const float lo_f = (float)(lo_t * (1.0 - 0x1p-20));
         uint32_t nc = 0;                         // queued leaf candidates
+        bool redo = false;                       // spheres may be tested a second time
 
         // The exact test of the queued candidates.  A leaf slot holds the
         // sphere's centre, radius and opacity as stored by the last build or
@@ -225,6 +228,14 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
                 if (!(t0 > 0.0)) continue;
                 if (!key_less(lo_t, lo_id, t0, id)) continue;
                 if (!key_less(t0, id, pr_t, pr_id)) continue;
+                if (redo) {
+                    // a second walk over the same nodes: keys are unique, so an
+                    // equal key is this sphere already filed
+                    bool dup = false;
+#pragma unroll
+                    for (int k = 0; k < K; ++k) dup |= B.t[k] == t0 && B.id[k] == id;
+                    if (dup) continue;
+                }
                 float al = ca;
                 if (soft) {
                     const double u = q / (r * r);
@@ -275,42 +286,34 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
             }
         };
 
-        int sp = 0;
-        uint32_t node = 0;
-        // a pass visits every node at most once; the cap only matters for a
-        // corrupt hierarchy, where it turns a cycle into an early exit
-        for (uint32_t visits = 0; visits <= n_nodes; ++visits) {
-            const WideNode *nd = nodes + node;
-            float f[32];
+        // Leaf slots of a node: float prefilter, certain misses only (the ray
+        // passes farther than r + E from the centre, or the sphere lies wholly
+        // beyond the prune key or before the last composited key: t0 lies in
+        // [b - r, b], and E bounds the error of the float b).  A survivor is
+        // queued for the exact test.  `pf` is the lane's prune bound (-inf for
+        // a lane that takes no part).
+        auto queue_leaves = [&](const float *f, uint32_t node, uint32_t kinds, float pf) {
 #pragma unroll
-            for (int k = 0; k < 32; ++k) f[k] = nd->f[k];
-            const uint32_t kinds = __float_as_uint(f[31]);  // bits 0-3 leaf slots, 4-7 internal slots
-            if (kinds & 0xfu) {
-                // leaf slots: float prefilter, certain misses only (the ray passes
-                // farther than r + E from the centre, or the sphere lies wholly
-                // beyond the prune key or before the last composited key: t0 lies
-                // in [b - r, b], and E bounds the error of the float b).  A
-                // survivor is queued for the exact test.
-#pragma unroll
-                for (int side = 0; side < 4; ++side) {
-                    if (!((kinds >> side) & 1u)) continue;
-                    const float *s = f + 6 * side;
-                    const float ox = s[0] - eye.of[0], oy = s[1] - eye.of[1], oz = s[2] - eye.of[2];
-                    const float bf = ox * ray.df[0] + oy * ray.df[1] + oz * ray.df[2];
-                    const float vx = ox - bf * ray.df[0], vy = oy - bf * ray.df[1], vz = oz - bf * ray.df[2];
-                    const float qf = vx * vx + vy * vy + vz * vz;
-                    const float rE = s[3] + eye.E;
-                    const bool may = (qf <= rE * rE) & (bf - rE <= pr_f) & (bf + eye.E >= lo_f);
-                    // nc < kQueue here: the queue is flushed once a lane could overflow
-                    L.cand[nc][lane] = (node << 2) | (uint32_t)side;
-                    nc += may ? 1u : 0u;
-                }
-                if (__ballot(nc > (uint32_t)kQueue - 4u)) flush();
+            for (int side = 0; side < 4; ++side) {
+                if (!((kinds >> side) & 1u)) continue;
+                const float *s = f + 6 * side;
+                const float ox = s[0] - eye.of[0], oy = s[1] - eye.of[1], oz = s[2] - eye.of[2];
+                const float bf = ox * ray.df[0] + oy * ray.df[1] + oz * ray.df[2];
+                const float vx = ox - bf * ray.df[0], vy = oy - bf * ray.df[1], vz = oz - bf * ray.df[2];
+                const float qf = vx * vx + vy * vy + vz * vz;
+                const float rE = s[3] + eye.E;
+                const bool may = (qf <= rE * rE) & (bf - rE <= pf) & (bf + eye.E >= lo_f);
+                // nc < kQueue here: the queue is flushed once a lane could overflow
+                L.cand[nc][lane] = (node << 2) | (uint32_t)side;
+                nc += may ? 1u : 0u;
             }
-            // internal slots: padded-box slab test in float, (x - o) / d as
-            // fma(x, 1/d, -o/d): the rounding of o/d moves the eye by at most
-            // eps |o|, far inside the margin
-            uint32_t boxes = 0;  // slots whose box some lane's ray meets
+        };
+        // Internal slots: padded-box slab test in float, (x - o) / d as
+        // fma(x, 1/d, -o/d): the rounding of o/d moves the eye by at most
+        // eps |o|, far inside the margin.  Bit s of the result: this lane's
+        // ray meets the box of slot s before its prune bound.
+        auto box_hits = [&](const float *f, uint32_t kinds, float pf) -> uint32_t {
+            uint32_t hits = 0;
 #pragma unroll
             for (int side = 0; side < 4; ++side) {
                 if (!((kinds >> (4 + side)) & 1u)) continue;
@@ -320,43 +323,137 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
                 const float t1z = fmaf(s[2], ray.inv[2], -ray.oPi[2]), t2z = fmaf(s[5], ray.inv[2], -ray.oMi[2]);
                 const float tn = fmaxf(fmaxf(fminf(t1x, t2x), fminf(t1y, t2y)), fminf(t1z, t2z));
                 const float tf = fminf(fminf(fmaxf(t1x, t2x), fmaxf(t1y, t2y)), fmaxf(t1z, t2z)) * 1.0000005f;
-                if (__ballot((tn <= tf) & (tf >= lo_f) & (tn <= pr_f))) boxes |= 1u << side;
+                hits |= ((tn <= tf) & (tf >= lo_f) & (tn <= pf)) ? 1u << side : 0u;
             }
-            if (boxes) {
-                // near-first order: the near child of the node, within it the
-                // near grandchild (split axes against the first lane's ray)
-                const uint32_t ax = __float_as_uint(f[28]), a0 = __float_as_uint(f[29]), a1 = __float_as_uint(f[30]);
-                const uint32_t cn = ax < 3u ? (neg_mask >> ax) & 1u : 0u;
-                const uint32_t axn = cn ? a1 : a0, axf = cn ? a0 : a1;
-                const uint32_t gn = axn < 3u ? (neg_mask >> axn) & 1u : 0u;
-                const uint32_t gf = axf < 3u ? (neg_mask >> axf) & 1u : 0u;
-                const uint32_t o0 = 2u * cn + gn, o2 = 2u * (1u - cn) + gf;
-                const uint32_t order = o0 | ((o0 ^ 1u) << 2) | (o2 << 4) | ((o2 ^ 1u) << 6);
-                // descend into the nearest slot hit; push the others, farthest first
-                uint32_t next = kEmpty;
+            return hits;
+        };
+        // Near-first order of the four slots: the near child of the node, within
+        // it the near grandchild (split axes against the ray signs in `neg`),
+        // as four 2-bit slot numbers.
+        auto slot_order = [](const float *f, uint32_t neg) -> uint32_t {
+            const uint32_t ax = __float_as_uint(f[28]), a0 = __float_as_uint(f[29]), a1 = __float_as_uint(f[30]);
+            const uint32_t cn = ax < 3u ? (neg >> ax) & 1u : 0u;
+            const uint32_t axn = cn ? a1 : a0, axf = cn ? a0 : a1;
+            const uint32_t gn = axn < 3u ? (neg >> axn) & 1u : 0u;
+            const uint32_t gf = axf < 3u ? (neg >> axf) & 1u : 0u;
+            const uint32_t o0 = 2u * cn + gn, o2 = 2u * (1u - cn) + gf;
+            return o0 | ((o0 ^ 1u) << 2) | (o2 << 4) | ((o2 ^ 1u) << 6);
+        };
+        auto slot_ref = [](const float *f, uint32_t o) -> uint32_t {
+            return o == 0 ? __float_as_uint(f[24]) : o == 1 ? __float_as_uint(f[25])
+                 : o == 2 ? __float_as_uint(f[26]) : __float_as_uint(f[27]);
+        };
+
+        bool overflow = false;  // the lane's own stack dropped entries
+        if (LANE) {
+            // Per-lane walk: every lane follows its own ray through the tree
+            // (vector loads of its node; stack in its own LDS column, a ring
+            // of kLaneStack entries).  A wave costs the longest path of its
+            // lanes rather than the union of their paths.
+            const uint32_t neg = (ray.d[0] < 0.0 ? 1u : 0u) | (ray.d[1] < 0.0 ? 2u : 0u) | (ray.d[2] < 0.0 ? 4u : 0u);
+            uint32_t node = 0, top = 0, depth = 0, steps = 0;
+            bool walking = active;
+            while (__ballot(walking)) {
+                if (walking) {
+                    const float4 *np = reinterpret_cast<const float4 *>(nodes + node);
+                    float f[32];
 #pragma unroll
-                for (int i = 3; i >= 0; --i) {
-                    const uint32_t o = (order >> (2 * i)) & 3u;
-                    if (!((boxes >> o) & 1u)) continue;
-                    if (next != kEmpty) {
-                        // a wide level pushes at most 3 entries and the wide depth is
-                        // at most 32 for 62-bit (code, position) keys: 128 slots suffice
-                        if (sp < kStack) {
-                            if (lane == 0) L.stack[sp] = next;
-                            ++sp;
-                        }
+                    for (int k = 0; k < 8; ++k) {
+                        const float4 v = np[k];
+                        f[4 * k] = v.x;
+                        f[4 * k + 1] = v.y;
+                        f[4 * k + 2] = v.z;
+                        f[4 * k + 3] = v.w;
                     }
-                    next = o == 0 ? __float_as_uint(f[24]) : o == 1 ? __float_as_uint(f[25])
-                         : o == 2 ? __float_as_uint(f[26]) : __float_as_uint(f[27]);
+                    const uint32_t kinds = __float_as_uint(f[31]);
+                    queue_leaves(f, node, kinds, pr_f);
+                    const uint32_t boxes = box_hits(f, kinds, pr_f);
+                    if (boxes) {
+                        const uint32_t order = slot_order(f, neg);
+                        uint32_t next = kEmpty;
+#pragma unroll
+                        for (int i = 3; i >= 0; --i) {
+                            const uint32_t o = (order >> (2 * i)) & 3u;
+                            if (!((boxes >> o) & 1u)) continue;
+                            if (next != kEmpty) {
+                                // a full ring drops its oldest entry; the packet walk
+                                // below then settles this lane
+                                L.lstack[top][lane] = next;
+                                top = (top + 1u) & (kLaneStack - 1u);
+                                if (depth < kLaneStack) ++depth;
+                                else overflow = true;
+                            }
+                            next = slot_ref(f, o);
+                        }
+                        node = next;
+                    } else if (depth > 0) {
+                        top = (top - 1u) & (kLaneStack - 1u);
+                        node = L.lstack[top][lane];
+                        --depth;
+                    } else {
+                        walking = false;
+                    }
+                    // only a corrupt hierarchy can name a node outside the array
+                    // or take more steps than there are nodes
+                    node = min(node, n_nodes - 1);
+                    if (++steps > n_nodes) walking = false;
                 }
-                node = next;
-            } else {
-                if (sp == 0) break;
-                --sp;
-                node = ufirst(L.stack[sp]);
+                if (__ballot(nc > (uint32_t)kQueue - 4u)) flush();
             }
-            // only a corrupt hierarchy can name a node outside the array
-            node = min(node, n_nodes - 1);
+            redo = overflow;
+        }
+        if (!LANE || __ballot(overflow)) {
+            // Packet walk (all lanes, or the lanes whose stack overflowed): the
+            // node is fetched once per wave with scalar loads and visited when
+            // any taking part lane's ray meets its box.
+            int sp = 0;
+            uint32_t node = 0;
+            // a pass visits every node at most once; the cap only matters for a
+            // corrupt hierarchy, where it turns a cycle into an early exit
+            for (uint32_t visits = 0; visits <= n_nodes; ++visits) {
+                const WideNode *nd = nodes + node;
+                float f[32];
+#pragma unroll
+                for (int k = 0; k < 32; ++k) f[k] = nd->f[k];
+                const uint32_t kinds = __float_as_uint(f[31]);  // bits 0-3 leaf slots, 4-7 internal slots
+                if (kinds & 0xfu) {
+                    queue_leaves(f, node, kinds, (!LANE || overflow) ? pr_f : -INFINITY);
+                    if (__ballot(nc > (uint32_t)kQueue - 4u)) flush();
+                }
+                uint32_t boxes = 0;  // slots whose box some lane's ray meets
+                {
+                    const uint32_t mine = box_hits(f, kinds, (!LANE || overflow) ? pr_f : -INFINITY);
+#pragma unroll
+                    for (int side = 0; side < 4; ++side)
+                        if (__ballot((mine >> side) & 1u)) boxes |= 1u << side;
+                }
+                if (boxes) {
+                    const uint32_t order = slot_order(f, neg_mask);
+                    // descend into the nearest slot hit; push the others, farthest first
+                    uint32_t next = kEmpty;
+#pragma unroll
+                    for (int i = 3; i >= 0; --i) {
+                        const uint32_t o = (order >> (2 * i)) & 3u;
+                        if (!((boxes >> o) & 1u)) continue;
+                        if (next != kEmpty) {
+                            // a wide level pushes at most 3 entries and the wide depth is
+                            // at most 32 for 62-bit (code, position) keys: 128 slots suffice
+                            if (sp < kStack) {
+                                if (lane == 0) L.stack[sp] = next;
+                                ++sp;
+                            }
+                        }
+                        next = slot_ref(f, o);
+                    }
+                    node = next;
+                } else {
+                    if (sp == 0) break;
+                    --sp;
+                    node = ufirst(L.stack[sp]);
+                }
+                // only a corrupt hierarchy can name a node outside the array
+                node = min(node, n_nodes - 1);
+            }
         }
         if (__ballot(nc > 0)) flush();
         if (!active) continue;
@@ -493,7 +590,7 @@ __host__ inline uint32_t blocks_for(int tiles_x, int tiles_y, int schedule)
     return (uint32_t)(((s + 7) / 8) * 8 * 64);
 }
 
-template <int K, bool BWD>
+template <int K, bool BWD, bool LANE>
 __global__ void __launch_bounds__(64) k_trace(TraceArgs a, int tiles_x, int tiles_y)
 {
     __shared__ WaveLds lds;
@@ -503,12 +600,12 @@ __global__ void __launch_bounds__(64) k_trace(TraceArgs a, int tiles_x, int tile
     const BvhLayout L(a.layout_cap);
     const BvhHeader *hdr = reinterpret_cast<const BvhHeader *>(mem);
     const WideNode *nodes = reinterpret_cast<const WideNode *>(mem + L.wide);
-    trace_tile<K, BWD>(a, nodes, hdr, tx, ty, lds);
+    trace_tile<K, BWD, LANE>(a, nodes, hdr, tx, ty, lds);
 }
 
 // Persistent batched trace: waves pull tiles from one atomic counter until
 // the batch is drained; every wave reaches the exit test.
-template <int K>
+template <int K, bool LANE>
 __global__ void __launch_bounds__(64)
 k_trace_batched(const splat_batch_job *__restrict__ jobs, const uint32_t *__restrict__ tile_offsets, int n_jobs,
                 uint32_t total_tiles, float alpha_stop, int mode, double t_max, int tile_w, int tile_h,
@@ -554,6 +651,7 @@ k_trace_batched(const splat_batch_job *__restrict__ jobs, const uint32_t *__rest
         a.tile_w = tile_w;
         a.tile_h = tile_h;
         a.schedule = 0;
+        a.walk = LANE ? SPLAT_WALK_LANE : SPLAT_WALK_PACKET;
         a.out = reinterpret_cast<float4 *>(j.out_rgba);
         a.hits = j.out_hits;
         a.grad = nullptr;
@@ -562,7 +660,7 @@ k_trace_batched(const splat_batch_job *__restrict__ jobs, const uint32_t *__rest
         const int64_t t64 = (int64_t)item - (int64_t)tile_offsets[lo];
         const int t = t64 < 0 ? 0x7fffffff : (int)min(t64, (int64_t)0x7fffffff);
         const char *mem = static_cast<const char *>(j.bvh_mem);
-        trace_tile<K, false>(a, reinterpret_cast<const WideNode *>(mem + L.wide), reinterpret_cast<const BvhHeader *>(mem),
+        trace_tile<K, false, LANE>(a, reinterpret_cast<const WideNode *>(mem + L.wide), reinterpret_cast<const BvhHeader *>(mem),
                              t % tiles_x, t / tiles_x, lds);
     }
 }
@@ -572,15 +670,16 @@ __global__ void k_zero_counter(uint32_t *c)
     if (threadIdx.x == 0) *c = 0u;
 }
 
-template <bool BWD>
+template <bool BWD, bool LANE>
 static hipError_t launch_k(const TraceArgs &a, int K, dim3 grid, int tiles_x, int tiles_y, hipStream_t s)
 {
     switch (K) {
-    case 1: hipLaunchKernelGGL((k_trace<1, BWD>), grid, dim3(64), 0, s, a, tiles_x, tiles_y); break;
-    case 2: hipLaunchKernelGGL((k_trace<2, BWD>), grid, dim3(64), 0, s, a, tiles_x, tiles_y); break;
-    case 4: hipLaunchKernelGGL((k_trace<4, BWD>), grid, dim3(64), 0, s, a, tiles_x, tiles_y); break;
-    case 8: hipLaunchKernelGGL((k_trace<8, BWD>), grid, dim3(64), 0, s, a, tiles_x, tiles_y); break;
-    case 16: hipLaunchKernelGGL((k_trace<16, BWD>), grid, dim3(64), 0, s, a, tiles_x, tiles_y); break;
+    case 1: hipLaunchKernelGGL((k_trace<1, BWD, LANE>), grid, dim3(64), 0, s, a, tiles_x, tiles_y); break;
+    case 2: hipLaunchKernelGGL((k_trace<2, BWD, LANE>), grid, dim3(64), 0, s, a, tiles_x, tiles_y); break;
+    case 4: hipLaunchKernelGGL((k_trace<4, BWD, LANE>), grid, dim3(64), 0, s, a, tiles_x, tiles_y); break;
+    case 6: hipLaunchKernelGGL((k_trace<6, BWD, LANE>), grid, dim3(64), 0, s, a, tiles_x, tiles_y); break;
+    case 8: hipLaunchKernelGGL((k_trace<8, BWD, LANE>), grid, dim3(64), 0, s, a, tiles_x, tiles_y); break;
+    case 16: hipLaunchKernelGGL((k_trace<16, BWD, LANE>), grid, dim3(64), 0, s, a, tiles_x, tiles_y); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -591,8 +690,11 @@ hipError_t launch_trace(const TraceArgs &a, bool backward, hipStream_t s)
     const int tiles_x = (a.cam.w + a.tile_w - 1) / a.tile_w;
     const int tiles_y = (a.cam.h + a.tile_h - 1) / a.tile_h;
     const dim3 grid(blocks_for(tiles_x, tiles_y, a.schedule));
-    return backward ? launch_k<true>(a, a.kbuf, grid, tiles_x, tiles_y, s)
-                    : launch_k<false>(a, a.kbuf, grid, tiles_x, tiles_y, s);
+    if (a.walk == SPLAT_WALK_PACKET)
+        return backward ? launch_k<true, false>(a, a.kbuf, grid, tiles_x, tiles_y, s)
+                        : launch_k<false, false>(a, a.kbuf, grid, tiles_x, tiles_y, s);
+    return backward ? launch_k<true, true>(a, a.kbuf, grid, tiles_x, tiles_y, s)
+                    : launch_k<false, true>(a, a.kbuf, grid, tiles_x, tiles_y, s);
 }
 
 hipError_t launch_trace_batched(const splat_batch_job *jobs, const uint32_t *tile_offsets, int32_t n_jobs,
@@ -602,19 +704,24 @@ hipError_t launch_trace_batched(const splat_batch_job *jobs, const uint32_t *til
     uint32_t *counter = static_cast<uint32_t *>(ws);
     hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, s, counter);
     const dim3 grid(waves), block(64);
+    const bool lane = o.walk != SPLAT_WALK_PACKET;
+#define SPLAT_BATCHED(KK)                                                                                        \
+    if (lane)                                                                                                    \
+        hipLaunchKernelGGL((k_trace_batched<KK, true>), grid, block, 0, s, jobs, tile_offsets, n_jobs,            \
+                           total_tiles, o.alpha_stop, o.mode, o.t_max, o.tile_w, o.tile_h, counter);              \
+    else                                                                                                         \
+        hipLaunchKernelGGL((k_trace_batched<KK, false>), grid, block, 0, s, jobs, tile_offsets, n_jobs,           \
+                           total_tiles, o.alpha_stop, o.mode, o.t_max, o.tile_w, o.tile_h, counter);
     switch (o.kbuf) {
-    case 1: hipLaunchKernelGGL(k_trace_batched<1>, grid, block, 0, s, jobs, tile_offsets, n_jobs, total_tiles,
-                               o.alpha_stop, o.mode, o.t_max, o.tile_w, o.tile_h, counter); break;
-    case 2: hipLaunchKernelGGL(k_trace_batched<2>, grid, block, 0, s, jobs, tile_offsets, n_jobs, total_tiles,
-                               o.alpha_stop, o.mode, o.t_max, o.tile_w, o.tile_h, counter); break;
-    case 4: hipLaunchKernelGGL(k_trace_batched<4>, grid, block, 0, s, jobs, tile_offsets, n_jobs, total_tiles,
-                               o.alpha_stop, o.mode, o.t_max, o.tile_w, o.tile_h, counter); break;
-    case 8: hipLaunchKernelGGL(k_trace_batched<8>, grid, block, 0, s, jobs, tile_offsets, n_jobs, total_tiles,
-                               o.alpha_stop, o.mode, o.t_max, o.tile_w, o.tile_h, counter); break;
-    case 16: hipLaunchKernelGGL(k_trace_batched<16>, grid, block, 0, s, jobs, tile_offsets, n_jobs, total_tiles,
-                                o.alpha_stop, o.mode, o.t_max, o.tile_w, o.tile_h, counter); break;
+    case 1: SPLAT_BATCHED(1) break;
+    case 2: SPLAT_BATCHED(2) break;
+    case 4: SPLAT_BATCHED(4) break;
+    case 6: SPLAT_BATCHED(6) break;
+    case 8: SPLAT_BATCHED(8) break;
+    case 16: SPLAT_BATCHED(16) break;
     default: return hipErrorInvalidValue;
     }
+#undef SPLAT_BATCHED
     return hipGetLastError();
 }
 

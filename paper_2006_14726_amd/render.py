@@ -151,9 +151,10 @@ class TraceOptions:
     alpha_stop: float = 0.99
     t_max: float = math.inf
     mode: int = _lib.SPLAT_ALPHA_CONSTANT
-    kbuf: int = 8
+    kbuf: int = 6
     tile: tuple = field(default=(8, 8))
     schedule: int = 0
+    walk: int = 0  # SPLAT_WALK_LANE (0) or SPLAT_WALK_PACKET (1)
 
     def struct(self) -> _lib.splat_trace_opts:
         o = _lib.splat_trace_opts()
@@ -163,6 +164,7 @@ class TraceOptions:
         o.kbuf = int(self.kbuf)
         o.tile_w, o.tile_h = int(self.tile[0]), int(self.tile[1])
         o.schedule = int(self.schedule)
+        o.walk = int(self.walk)
         return o
 
 

@@ -50,9 +50,10 @@ def assert_same(a, b):
             assert torch.equal(oa, ob) and torch.equal(ha, hb)
 
 
-@pytest.mark.parametrize("kbuf,tile,waves", [(8, (8, 8), 0), (4, (16, 4), 97), (1, (32, 2), 3)])
-def test_batched_equals_sequential(sp, small_batch, kbuf, tile, waves):
-    r = make_renderer(sp, small_batch, half=True, opts=sp.TraceOptions(kbuf=kbuf, tile=tile), waves=waves)
+@pytest.mark.parametrize("kbuf,tile,waves,walk", [(6, (8, 8), 0, 0), (8, (8, 8), 0, 1), (4, (16, 4), 97, 0),
+                                                  (1, (32, 2), 3, 1)])
+def test_batched_equals_sequential(sp, small_batch, kbuf, tile, waves, walk):
+    r = make_renderer(sp, small_batch, half=True, opts=sp.TraceOptions(kbuf=kbuf, tile=tile, walk=walk), waves=waves)
     assert r.n_jobs >= 7
     r.run_sequential()
     ref = snapshot(r)
@@ -114,7 +115,7 @@ def test_autotuner_picks_a_valid_schedule(sp, small_batch, tmp_path, monkeypatch
     s = sp.unproject(src, up(rgba), up(depth), 1.0, True)
     bvh = sp.build_bvh(s)
     opts, rec = autotune.tune_trace(bvh, s, dsts[0])
-    assert opts.kbuf in (4, 8) and len(rec["all_ms"]) == len(autotune.TRACE_CANDIDATES)
+    assert opts.kbuf in (6, 8) and opts.walk in (0, 1) and len(rec["all_ms"]) == len(autotune.TRACE_CANDIDATES)
     ref, _ = sp.trace(bvh, s, dsts[0])
     got, _ = sp.trace(bvh, s, dsts[0], opts)
     assert torch.equal(ref, got)

@@ -42,13 +42,13 @@ def test_large_unprojection(sp, large):
     assert np.array_equal(s.rgba[:n].cpu().numpy().view(np.uint16), col.view(np.uint16))
 
 
-@pytest.mark.parametrize("frame", [0, 14, 29])
-def test_large_orbit_sampled(sp, large, frame):
+@pytest.mark.parametrize("frame,walk", [(0, 0), (14, 0), (29, 0), (0, 1)])
+def test_large_orbit_sampled(sp, large, frame, walk):
     rgba, depth, src, cr, col, _ = large
     dst = synth.rotated_camera(src, 15.0 + frame, 0.0)
     sph = sp.spheres_from_tensors(up(cr), up(col))
     bvh = sp.build_bvh(sph)
-    img, hits = sp.trace(bvh, sph, dst)
+    img, hits = sp.trace(bvh, sph, dst, sp.TraceOptions(walk=walk))
     torch.cuda.synchronize()
     rng = np.random.default_rng(frame)
     W, H = dst.width, dst.height

@@ -132,13 +132,14 @@ def test_refit_matches_full_build(sp):
 
 # ---------------------------------------------------------------- trace
 
+@pytest.mark.parametrize("walk", [0, 1])
 @pytest.mark.parametrize("seed", [0, 1, 2])
 @pytest.mark.parametrize("mode,stop", [(0, 0.99), (0, NEVER), (0, 0.0), (1, 0.99), (1, NEVER)])
-def test_trace_random_scenes(sp, seed, mode, stop):
+def test_trace_random_scenes(sp, seed, mode, stop, walk):
     cr, col = synth.random_spheres(200, seed=seed, r_lo=0.02, r_hi=0.12)
     cam = synth.rotated_camera(synth.source_camera(45, 37), 8.0 * seed, 3.0)
-    print(f"random seed={seed} mode={mode} stop={stop}", flush=True)
-    g, n, _, _ = gpu_trace(sp, cr, col, cam, alpha_stop=stop, mode=mode)
+    print(f"random seed={seed} mode={mode} stop={stop} walk={walk}", flush=True)
+    g, n, _, _ = gpu_trace(sp, cr, col, cam, alpha_stop=stop, mode=mode, walk=walk)
     orc = oracle.render(cr, col, cam, alpha_stop=stop, mode=mode)
     st = compare(g, n, orc)
     assert_parity(st, exempt_frac=None, context=f"seed {seed}")
@@ -146,16 +147,43 @@ def test_trace_random_scenes(sp, seed, mode, stop):
     assert st["hits_checked"] > (100 if stop == 0.0 else 200)
 
 
+@pytest.mark.parametrize("walk", [0, 1])
 @pytest.mark.parametrize("half", [False, True])
-def test_trace_adversarial_scene(sp, half):
+def test_trace_adversarial_scene(sp, half, walk):
     cr, col = synth.adversarial_spheres(5)
     if half:
         col = synth.to_half_rgba(col)
     cam = synth.rotated_camera(synth.source_camera(64, 48), 12.0, -4.0)
     for stop in (0.99, NEVER):
-        g, n, _, _ = gpu_trace(sp, cr, col, cam, alpha_stop=stop)
+        g, n, _, _ = gpu_trace(sp, cr, col, cam, alpha_stop=stop, walk=walk)
         st = compare(g, n, oracle.render(cr, col, cam, alpha_stop=stop))
         assert_parity(st, exempt_frac=None, context=f"adversarial stop={stop}")
+
+
+@pytest.mark.parametrize("stop", [0.99, NEVER])
+def test_column_along_the_view_ray(sp, stop):
+    """16384 spheres strung along the central ray of a 15x15 view: every box on
+    the way is hit, so the near-first walk pushes three siblings per wide level
+    and a lane's own stack (16 entries) overflows; those lanes are then settled
+    by the packet walk.  Both walks must match the oracle, and each other."""
+    rng = np.random.default_rng(21)
+    cam = synth.source_camera(15, 15)
+    n = 16384
+    t = rng.uniform(1.0, 3.0, n)
+    e, f = np.array(cam.eye), np.array(cam.forward)
+    r_, u_ = np.array(cam.right), np.array(cam.up)
+    c = e + t[:, None] * f + rng.normal(0, 0.002, (n, 1)) * r_ + rng.normal(0, 0.002, (n, 1)) * u_
+    cr = np.concatenate([c, rng.uniform(0.01, 0.03, (n, 1))], axis=1).astype(np.float32)
+    col = np.concatenate([rng.uniform(0, 1, (n, 3)), np.full((n, 1), 0.05)], axis=1).astype(np.float32)
+    orc = oracle.render(cr, col, cam, alpha_stop=stop)
+    out = {}
+    for walk in (0, 1):
+        print(f"column stop={stop} walk={walk}", flush=True)
+        g, h, _, _ = gpu_trace(sp, cr, col, cam, alpha_stop=stop, walk=walk)
+        assert_parity(compare(g, h, orc), exempt_frac=None, context=f"column walk={walk}")
+        out[walk] = (g, h)
+    assert int(out[0][1].max()) > (1000 if stop == NEVER else 50)
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
 
 
 def test_result_independent_of_kbuf_and_tile(sp):
@@ -167,15 +195,16 @@ def test_result_independent_of_kbuf_and_tile(sp):
     ref = None
     for stop in (0.99, NEVER):
         ref = None
-        for k in (1, 2, 4, 8, 16):
+        for k in (1, 2, 4, 6, 8, 16):
             for tile in ((8, 8), (16, 4), (32, 2)):
-                img, hits = sp.trace(bvh, sph, cam, sp.TraceOptions(alpha_stop=stop, kbuf=k, tile=tile))
-                if ref is None:
-                    ref = (img.clone(), hits.clone())
-                    if stop == NEVER:
-                        assert int(hits.max()) > 16  # several restarts at k = 1, 2, 4, 8
-                else:
-                    assert torch.equal(img, ref[0]) and torch.equal(hits, ref[1]), (k, tile)
+                for walk in (0, 1):
+                    img, hits = sp.trace(bvh, sph, cam, sp.TraceOptions(alpha_stop=stop, kbuf=k, tile=tile, walk=walk))
+                    if ref is None:
+                        ref = (img.clone(), hits.clone())
+                        if stop == NEVER:
+                            assert int(hits.max()) > 16  # several restarts at k = 1, 2, 4, 6, 8
+                    else:
+                        assert torch.equal(img, ref[0]) and torch.equal(hits, ref[1]), (k, tile, walk)
 
 
 def test_tiny_config_full_frame(sp):
@@ -188,14 +217,14 @@ def test_tiny_config_full_frame(sp):
     assert st["hits_checked"] > 100
 
 
-@pytest.mark.parametrize("scale", [0.5, 1.0, 2.0])
-def test_client_frame_sampled(sp, scale):
+@pytest.mark.parametrize("scale,walk", [(0.5, 0), (1.0, 0), (2.0, 0), (1.0, 1), (2.0, 1)])
+def test_client_frame_sampled(sp, scale, walk):
     """1024^2 source -> 1920x1080 after 10 deg yaw + 3 deg pitch, half colours, full-size launch;
     the oracle checks one random pixel per 32x32 tile plus 512 random pixels."""
     rgba, depth, src, dst = synth.source_image(synth.CLIENT_FRAME)
     cr, col, _ = oracle.unproject(src, rgba, depth, scale, True)
-    print(f"client frame s={scale}: {len(cr)} spheres", flush=True)
-    g, n, _, _ = gpu_trace(sp, cr, col, dst)
+    print(f"client frame s={scale} walk={walk}: {len(cr)} spheres", flush=True)
+    g, n, _, _ = gpu_trace(sp, cr, col, dst, walk=walk)
     rng = np.random.default_rng(int(scale * 10))
     W, H = dst.width, dst.height
     tx, ty = np.meshgrid(np.arange(0, W, 32), np.arange(0, H, 32))
