@@ -29,8 +29,9 @@ def parse():
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=5)
     p.add_argument("--scale", type=float, default=1.0)
-    p.add_argument("--kbuf", type=int, default=8)
+    p.add_argument("--kbuf", type=int, default=6)
     p.add_argument("--tile", type=str, default="8x8")
+    p.add_argument("--walk", type=int, default=0, help="0 per-lane BVH walk, 1 packet walk")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--no-bwd", action="store_true", help="skip the fwd+bwd measurement")
     p.add_argument("--batch-frames", type=int, default=64,
@@ -45,7 +46,7 @@ def measured_traffic(args):
     when the trace kernel source or the launch configuration differs from the one profiled."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "trace_client_frame_hbm_traffic.txt")
-    if not os.path.exists(path) or (args.kbuf, args.tile, args.scale) != (8, "8x8", 1.0):
+    if not os.path.exists(path) or (args.kbuf, args.tile, args.scale, args.walk) != (6, "8x8", 1.0, 0):
         return None
     rec = {}
     for line in open(path):
@@ -94,7 +95,7 @@ def main():
     rgba = torch.from_numpy(rgba_np).to(dev)
     depth = torch.from_numpy(depth_np).to(dev)
     tw, th = (int(v) for v in args.tile.split("x"))
-    opts = sp.TraceOptions(alpha_stop=0.99, kbuf=args.kbuf, tile=(tw, th))
+    opts = sp.TraceOptions(alpha_stop=0.99, kbuf=args.kbuf, tile=(tw, th), walk=args.walk)
     P = dst.width * dst.height
 
     sph = sp.alloc_spheres(src.width * src.height, dev, half=True)
@@ -160,7 +161,8 @@ def main():
         "data": "synthetic seeded blob volume, CPU ray-cast 2.5D source image",
         "config": {"workload": f"client frame: {src.width}x{src.height} source ({n} spheres, radius scale "
                                f"{args.scale}) -> {dst.width}x{dst.height} target, yaw {work.yaw} pitch {work.pitch}",
-                   "rays": P, "spheres": n, "kbuf": args.kbuf, "tile": args.tile, "alpha_stop": 0.99},
+                   "rays": P, "spheres": n, "kbuf": args.kbuf, "tile": args.tile,
+                   "walk": "per-lane" if args.walk == 0 else "packet", "alpha_stop": 0.99},
         "stages_ms": {"unproject": round(float(np.median(stage[:, 0])), 4),
                       "build": round(float(np.median(stage[:, 1])), 4),
                       "trace": round(float(np.median(stage[:, 2])), 4)},
@@ -168,7 +170,8 @@ def main():
         "mean_hits_per_ray": round(float(hit_stats.mean()), 3),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": measured_traffic(args),
-                     "kernel": "k_trace<8,false>", "algorithmic_bytes": tb, "avg_launch_ms": round(trace_ms, 4)},
+                     "kernel": f"k_trace<{args.kbuf}, false, {'true' if args.walk == 0 else 'false'}>",
+                     "algorithmic_bytes": tb, "avg_launch_ms": round(trace_ms, 4)},
     }
 
     if not args.no_bwd:
@@ -241,7 +244,7 @@ def batched(sp, torch, synth, dev, n_frames):
                         f"{sum(int(f.src_cam.width) * int(f.src_cam.height) for f in frames)} source pixels",
             "graph_ms": round(graph * 1e3, 3), "sequential_ms": round(seq * 1e3, 3),
             "graph_mrays_s": round(r.rays / graph / 1e6, 1), "sequential_mrays_s": round(r.rays / seq / 1e6, 1),
-            "bit_identical": bool(same), "tuned": {k: tuned[k] for k in ("kbuf", "tile", "waves")},
+            "bit_identical": bool(same), "tuned": {k: tuned[k] for k in ("kbuf", "tile", "walk", "waves")},
             "input_generation_s": round(gen_s, 1)}
 
 
