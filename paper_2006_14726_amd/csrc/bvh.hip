@@ -9,8 +9,10 @@
 //            key range and split from common-prefix lengths of the sorted
 //            codes (ties broken by the sorted position)
 //   refit    bottom-up: each leaf writes its sphere into its parent; the
-//            second thread to reach a node (agent-scope acq_rel counter)
-//            unions the two child boxes and climbs on
+//            second thread to reach a node unions the two child boxes and
+//            climbs on.  The hierarchy is cut into treelets (subtrees of at
+//            most kTreelet leaves, refit by one workgroup each in LDS) and
+//            the top tree above them (finished by one workgroup)
 //
 // All sizes are read from device memory (the sphere count), so the sequence
 // can be captured in a HIP graph.
@@ -301,7 +303,8 @@ __global__ void __launch_bounds__(256)
 k_karras(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ vals, const uint32_t *__restrict__ count,
          uint32_t cap,
          Node *__restrict__ nodes, uint32_t *__restrict__ leaf_parent, uint32_t *__restrict__ node_parent,
-         uint32_t *__restrict__ leaf_ids, uint32_t *__restrict__ flags, uint2 *__restrict__ ranges)
+         uint32_t *__restrict__ leaf_ids, uint32_t *__restrict__ flags, uint2 *__restrict__ ranges,
+         uint32_t *__restrict__ entries, BvhHeader *__restrict__ hdr)
 {
     const int n = (int)min(*count, cap);
     const int i = blockIdx.x * 256 + threadIdx.x;
@@ -315,6 +318,7 @@ k_karras(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ vals, c
         node_parent[0] = kEmpty;
         flags[0] = 0u;
         ranges[0] = make_uint2(0u, 0u);
+        entries[atomicAdd(&hdr->n_entry, 1u)] = 0u;  // the root is the one treelet
         return;
     }
     if (i >= n - 1) return;
@@ -347,6 +351,20 @@ k_karras(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ vals, c
     if (right_leaf) leaf_parent[gamma + 1] = ((uint32_t)i << 1) | 1u;
     else node_parent[gamma + 1] = ((uint32_t)i << 1) | 1u;
     if (i == 0) node_parent[0] = kEmpty;
+    // Refit entries.  A node of more than kTreelet leaves belongs to the top
+    // tree; each of its children that is a treelet root (an internal node of
+    // at most kTreelet leaves) or a leaf is an entry of the top tree.  A root
+    // of at most kTreelet leaves is itself the one treelet.
+    const int size = hi - lo + 1;
+    if (size > kTreelet) {
+        const int lsize = gamma - lo + 1, rsize = hi - gamma;
+        if (left_leaf) entries[atomicAdd(&hdr->n_entry, 1u)] = kLeafBit | (uint32_t)gamma;
+        else if (lsize <= kTreelet) entries[atomicAdd(&hdr->n_entry, 1u)] = (uint32_t)gamma;
+        if (right_leaf) entries[atomicAdd(&hdr->n_entry, 1u)] = kLeafBit | (uint32_t)(gamma + 1);
+        else if (rsize <= kTreelet) entries[atomicAdd(&hdr->n_entry, 1u)] = (uint32_t)(gamma + 1);
+    } else if (i == 0) {
+        entries[atomicAdd(&hdr->n_entry, 1u)] = 0u;
+    }
 }
 
 __global__ void __launch_bounds__(256) k_zero_flags(uint32_t *__restrict__ flags, const uint32_t *__restrict__ count,
@@ -402,114 +420,135 @@ __device__ inline uint32_t lift_box(Node *nodes, uint32_t p, const uint32_t *__r
     return pp;
 }
 
-// Refit, phase 1: one workgroup per chunk of kRefitChunk sorted leaves.  A
-// node whose leaf range lies inside the chunk has both subtrees in this
-// workgroup, so the second-arrival handshake needs only workgroup scope.  A
-// thread that reaches a node whose range crosses the chunk records the
-// arrival for phase 2 and stops.  Inside the chunk, the child boxes and the
-// arrival counters live in LDS (an internal node's index lies in its own
-// leaf range, so the chunk's nodes are indices c_lo..c_hi); the node slots
-// are written to HBM for the traversal and for phase 2.
-constexpr int kRefitThreads = 512;
+// Refit, phase 1: one workgroup per treelet.  The internal nodes of a
+// subtree whose leaves are the sorted positions lo..hi have indices in
+// [lo, hi], so the treelet's arrival counters, the box of each node's first
+// arrival and the parent references live in LDS, indexed from lo; the
+// second-arrival handshake needs only workgroup scope.  Node slots are
+// written to HBM for the wide-node gather and for phase 2.  The thread that
+// finishes the treelet root writes its box into the root's parent (a node of
+// the top tree) or, for a root of the whole hierarchy, into the header.
+constexpr int kRefitThreads = 1024;
 
 __global__ void __launch_bounds__(kRefitThreads)
 k_refit_local(const float4 *__restrict__ cr, const void *__restrict__ rgba, int half,
               const uint32_t *__restrict__ count, uint32_t cap, Node *nodes, const uint32_t *__restrict__ leaf_parent,
               const uint32_t *__restrict__ node_parent, const uint32_t *__restrict__ leaf_ids,
-              const uint2 *__restrict__ ranges, uint32_t *__restrict__ cross, BvhHeader *hdr)
+              const uint2 *__restrict__ ranges, const uint32_t *__restrict__ entries, BvhHeader *hdr)
 {
-    __shared__ float lbox[kRefitChunk][2][6];  // child boxes of the chunk's nodes
-    __shared__ uint32_t lcnt[kRefitChunk];      // arrivals per node
-    __shared__ uint32_t lpar[kRefitChunk];      // parent references of the chunk's nodes
-    __shared__ uint2 lrng[kRefitChunk];         // leaf ranges of the chunk's nodes
+    __shared__ float lbox[kTreelet][2][6];  // child boxes of each node
+    __shared__ uint32_t lcnt[kTreelet];   // arrivals per node
+    __shared__ uint32_t lpar[kTreelet];   // parent references
     const uint32_t n = min(*count, cap);
     const uint32_t n_nodes = n > 1 ? n - 1 : 1;
-    const uint32_t c_lo = blockIdx.x * kRefitChunk;
-    if (c_lo >= n) return;
-    const uint32_t c_hi = min(c_lo + kRefitChunk, n) - 1;
-    for (uint32_t k = threadIdx.x; k < kRefitChunk; k += kRefitThreads) {
-        const uint32_t i = c_lo + k;
-        const bool ok = i < n_nodes && n > 1;
-        lcnt[k] = 0u;
-        lpar[k] = ok ? node_parent[i] : kEmpty;
-        lrng[k] = ok ? ranges[i] : make_uint2(0xffffffffu, 0u);
-    }
-    __syncthreads();
-    for (uint32_t j = c_lo + threadIdx.x; j <= c_hi; j += kRefitThreads) {
-        const uint32_t id = leaf_ids[j];
-        if (id >= n) continue;  // only after a refit of a hierarchy that was never built
-        const float4 c = cr[id];
-        const float a = sphere_alpha_a(rgba, half, id);
-        uint32_t pp = leaf_parent[j];
-        uint32_t p = pp >> 1;
-        if (p >= n_nodes) continue;
-        {
-            float *s = nodes[p].f + 6 * (pp & 1u);
-            s[0] = c.x; s[1] = c.y; s[2] = c.z; s[3] = c.w; s[4] = a; s[5] = 0.0f;
+    const uint32_t m = min(hdr->n_entry, 2 * cap);
+    for (uint32_t e_i = blockIdx.x; e_i < m; e_i += gridDim.x) {
+        const uint32_t r = entries[e_i];
+        if ((r & kLeafBit) || r >= n_nodes) continue;  // a leaf entry of the top tree
+        const uint2 rng = ranges[r];
+        const uint32_t lo = rng.x, hi = min(rng.y, n - 1);
+        if (lo > hi || hi - lo + 1 > (uint32_t)kTreelet) continue;  // only a corrupt hierarchy
+        __syncthreads();  // the previous treelet's LDS is no longer read
+        for (uint32_t k = threadIdx.x; k <= hi - lo; k += kRefitThreads) {
+            const uint32_t i = lo + k;
+            lcnt[k] = 0u;
+            lpar[k] = (i < n_nodes && n > 1) ? node_parent[i] : kEmpty;
         }
-        if (n == 1) {
-            float *s = nodes[0].f + 6;
-            for (int k = 0; k < 3; ++k) { s[k] = INFINITY; s[3 + k] = -INFINITY; }
-            lift_box(nodes, 0, node_parent, hdr);
-            continue;
-        }
-        const float ctr[3] = {c.x, c.y, c.z};
-        float lo[3], hi[3];
-        for (int k = 0; k < 3; ++k) {
-            lo[k] = nextafterf(ctr[k] - c.w, -INFINITY);
-            hi[k] = nextafterf(ctr[k] + c.w, INFINITY);
-        }
-        // (lo, hi) is the box of the child in slot (pp & 1) of node p
-        for (;;) {
-            const bool inside = p >= c_lo && p <= c_hi && lrng[p - c_lo].x >= c_lo && lrng[p - c_lo].y <= c_hi;
-            if (!inside) {
-                const uint32_t e = __hip_atomic_fetch_add(&hdr->n_cross, 1u, __ATOMIC_RELAXED,
-                                                          __HIP_MEMORY_SCOPE_AGENT);
-                if (e < 2 * cap) cross[e] = p;
-                break;
+        __syncthreads();
+        for (uint32_t j = lo + threadIdx.x; j <= hi; j += kRefitThreads) {
+            const uint32_t id = leaf_ids[j];
+            if (id >= n) continue;  // only after a refit of a hierarchy that was never built
+            const float4 c = cr[id];
+            const float a = sphere_alpha_a(rgba, half, id);
+            uint32_t pp = leaf_parent[j];
+            uint32_t p = pp >> 1;
+            if (p >= n_nodes) continue;
+            {
+                float *sl = nodes[p].f + 6 * (pp & 1u);
+                sl[0] = c.x; sl[1] = c.y; sl[2] = c.z; sl[3] = c.w; sl[4] = a; sl[5] = 0.0f;
             }
-            const uint32_t lp = p - c_lo, side = pp & 1u;
+            if (n == 1) {
+                float *sl = nodes[0].f + 6;
+                for (int k = 0; k < 3; ++k) { sl[k] = INFINITY; sl[3 + k] = -INFINITY; }
+                lift_box(nodes, 0, node_parent, hdr);
+                continue;
+            }
+            const float ctr[3] = {c.x, c.y, c.z};
+            float bl[3], bh[3];
             for (int k = 0; k < 3; ++k) {
-                lbox[lp][side][k] = lo[k];
-                lbox[lp][side][3 + k] = hi[k];
+                bl[k] = nextafterf(ctr[k] - c.w, -INFINITY);
+                bh[k] = nextafterf(ctr[k] + c.w, INFINITY);
             }
-            const uint32_t old = __hip_atomic_fetch_add(&lcnt[lp], 1u, __ATOMIC_ACQ_REL,
-                                                        __HIP_MEMORY_SCOPE_WORKGROUP);
-            // first arrival: the sibling subtree is not finished and its thread
-            // continues; a count above 1 only occurs in a corrupt hierarchy
-            if (old != 1u) break;
-            for (int k = 0; k < 3; ++k) {
-                lo[k] = fminf(lo[k], lbox[lp][side ^ 1u][k]);
-                hi[k] = fmaxf(hi[k], lbox[lp][side ^ 1u][3 + k]);
+            // (bl, bh) is the box of the child in slot (pp & 1) of node p
+            for (;;) {
+                if (p < lo || p > hi) break;  // only a corrupt hierarchy leaves the treelet
+                const uint32_t lp = p - lo, side = pp & 1u;
+                for (int k = 0; k < 3; ++k) {
+                    lbox[lp][side][k] = bl[k];
+                    lbox[lp][side][3 + k] = bh[k];
+                }
+                const uint32_t old = __hip_atomic_fetch_add(&lcnt[lp], 1u, __ATOMIC_ACQ_REL,
+                                                            __HIP_MEMORY_SCOPE_WORKGROUP);
+                // first arrival: the sibling subtree is not finished and its thread
+                // continues; a count above 1 only occurs in a corrupt hierarchy
+                if (old != 1u) break;
+                for (int k = 0; k < 3; ++k) {
+                    bl[k] = fminf(bl[k], lbox[lp][side ^ 1u][k]);
+                    bh[k] = fmaxf(bh[k], lbox[lp][side ^ 1u][3 + k]);
+                }
+                pp = lpar[lp];
+                if (pp == kEmpty) {
+                    for (int k = 0; k < 3; ++k) { hdr->scene_lo[k] = bl[k]; hdr->scene_hi[k] = bh[k]; }
+                    break;
+                }
+                const uint32_t up = pp >> 1;
+                if (up >= n_nodes) break;
+                float *sl = nodes[up].f + 6 * (pp & 1u);
+                sl[0] = bl[0]; sl[1] = bl[1]; sl[2] = bl[2]; sl[3] = bh[0]; sl[4] = bh[1]; sl[5] = bh[2];
+                if (p == r) break;  // the treelet is done; its parent is a node of the top tree
+                p = up;
             }
-            pp = lpar[lp];
-            if (pp == kEmpty) {
-                for (int k = 0; k < 3; ++k) { hdr->scene_lo[k] = lo[k]; hdr->scene_hi[k] = hi[k]; }
-                break;
-            }
-            p = pp >> 1;
-            if (p >= n_nodes) break;
-            float *s = nodes[p].f + 6 * (pp & 1u);
-            s[0] = lo[0]; s[1] = lo[1]; s[2] = lo[2]; s[3] = hi[0]; s[4] = hi[1]; s[5] = hi[2];
         }
     }
 }
 
-// Refit, phase 2: one workgroup finishes the nodes whose range crosses a
-// chunk, starting from the arrivals recorded in phase 1.
-__global__ void __launch_bounds__(1024)
-k_refit_top(const uint32_t *__restrict__ count, uint32_t cap, Node *nodes, const uint32_t *__restrict__ node_parent,
-            uint32_t *flags, const uint32_t *__restrict__ cross, BvhHeader *hdr)
+// Refit, phase 2: one workgroup finishes the top tree.  Its entries are the
+// treelet roots (boxes already written by phase 1) and the leaves hanging
+// directly from top nodes.  Every top node is reached only by threads of this
+// workgroup, so workgroup-scope ordering suffices; the boxes written by phase
+// 1 are visible across the kernel boundary.
+constexpr int kTopThreads = 1024;
+
+__global__ void __launch_bounds__(kTopThreads)
+k_refit_top(const float4 *__restrict__ cr, const void *__restrict__ rgba, int half,
+            const uint32_t *__restrict__ count, uint32_t cap, Node *nodes, const uint32_t *__restrict__ leaf_parent,
+            const uint32_t *__restrict__ node_parent, const uint32_t *__restrict__ leaf_ids, uint32_t *flags,
+            const uint32_t *__restrict__ entries, BvhHeader *hdr)
 {
     const uint32_t n = min(*count, cap);
     const uint32_t n_nodes = n > 1 ? n - 1 : 1;
-    const uint32_t m = min(hdr->n_cross, 2 * cap);
-    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < m; e += gridDim.x * blockDim.x) {
-        uint32_t p = cross[e];
+    const uint32_t m = min(hdr->n_entry, 2 * cap);
+    for (uint32_t e_i = threadIdx.x; e_i < m; e_i += kTopThreads) {
+        const uint32_t e = entries[e_i];
+        uint32_t pp;
+        if (e & kLeafBit) {
+            const uint32_t j = e & ~kLeafBit;
+            if (j >= n) continue;
+            const uint32_t id = leaf_ids[j];
+            if (id >= n) continue;
+            const float4 c = cr[id];
+            pp = leaf_parent[j];
+            if ((pp >> 1) >= n_nodes) continue;
+            float *sl = nodes[pp >> 1].f + 6 * (pp & 1u);
+            sl[0] = c.x; sl[1] = c.y; sl[2] = c.z; sl[3] = c.w; sl[4] = sphere_alpha_a(rgba, half, id); sl[5] = 0.0f;
+        } else {
+            if (e >= n_nodes) continue;
+            pp = node_parent[e];
+            if (pp == kEmpty) continue;  // the root treelet: phase 1 wrote the header
+        }
+        uint32_t p = pp >> 1;
         while (p < n_nodes) {
-            // the two subtrees of a crossing node may finish on different XCDs
-            const uint32_t old = __hip_atomic_fetch_add(&flags[p], 1u, __ATOMIC_ACQ_REL,
-                                                        __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t old = __hip_atomic_fetch_add(&flags[p], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
             if (old != 1u) break;
             const uint32_t up = lift_box(nodes, p, node_parent, hdr);
             if (up == kEmpty) break;
@@ -561,11 +600,12 @@ k_gather_wide(const uint32_t *__restrict__ count, uint32_t cap, const Node *__re
 }
 
 // Header count (an empty sphere set traces as background) and the refit list reset.
-__global__ void k_header_count(const uint32_t *__restrict__ count, uint32_t cap, BvhHeader *__restrict__ hdr)
+__global__ void k_header_count(const uint32_t *__restrict__ count, uint32_t cap, int new_hierarchy,
+                               BvhHeader *__restrict__ hdr)
 {
     if (threadIdx.x == 0) {
         hdr->n = min(*count, cap);
-        hdr->n_cross = 0u;
+        if (new_hierarchy) hdr->n_entry = 0u;
     }
 }
 
@@ -581,13 +621,14 @@ hipError_t launch_build(const splat_spheres &sph, const splat_bvh &bvh, bool ref
     uint32_t *leaf_ids = reinterpret_cast<uint32_t *>(mem + L.leaf_ids);
     uint32_t *flags = reinterpret_cast<uint32_t *>(mem + L.flags);
     uint2 *ranges = reinterpret_cast<uint2 *>(mem + L.ranges);
-    uint32_t *cross = reinterpret_cast<uint32_t *>(mem + L.cross);
+    uint32_t *entries = reinterpret_cast<uint32_t *>(mem + L.entries);
     const float4 *cr = reinterpret_cast<const float4 *>(sph.centre_radius);
     const int half = sph.rgba_dtype == SPLAT_F16;
     const uint32_t blocks = (cap + 255) / 256 > 0 ? (cap + 255) / 256 : 1;
-    const uint32_t chunks = (cap + kRefitChunk - 1) / kRefitChunk > 0 ? (cap + kRefitChunk - 1) / kRefitChunk : 1;
+    // one refit workgroup per CU (its LDS takes most of the CU's); they share out the treelets
+    const uint32_t refit_blocks = 256;
 
-    hipLaunchKernelGGL(k_header_count, dim3(1), dim3(64), 0, s, sph.count, cap, hdr);
+    hipLaunchKernelGGL(k_header_count, dim3(1), dim3(64), 0, s, sph.count, cap, refit_only ? 0 : 1, hdr);
     if (!refit_only) {
         const BuildLayout B(cap);
         char *w = static_cast<char *>(ws);
@@ -609,13 +650,14 @@ hipError_t launch_build(const splat_spheres &sph, const splat_bvh &bvh, bool ref
             t = va; va = vb; vb = t;
         }
         hipLaunchKernelGGL(k_karras, dim3(blocks), dim3(256), 0, s, ka, va, sph.count, cap, nodes, leaf_parent,
-                           node_parent, leaf_ids, flags, ranges);
+                           node_parent, leaf_ids, flags, ranges, entries, hdr);
     } else {
         hipLaunchKernelGGL(k_zero_flags, dim3(blocks), dim3(256), 0, s, flags, sph.count, cap);
     }
-    hipLaunchKernelGGL(k_refit_local, dim3(chunks), dim3(kRefitThreads), 0, s, cr, sph.rgba, half, sph.count, cap,
-                       nodes, leaf_parent, node_parent, leaf_ids, ranges, cross, hdr);
-    hipLaunchKernelGGL(k_refit_top, dim3(128), dim3(256), 0, s, sph.count, cap, nodes, node_parent, flags, cross, hdr);
+    hipLaunchKernelGGL(k_refit_local, dim3(refit_blocks), dim3(kRefitThreads), 0, s, cr, sph.rgba, half, sph.count,
+                       cap, nodes, leaf_parent, node_parent, leaf_ids, ranges, entries, hdr);
+    hipLaunchKernelGGL(k_refit_top, dim3(1), dim3(kTopThreads), 0, s, cr, sph.rgba, half, sph.count, cap, nodes,
+                       leaf_parent, node_parent, leaf_ids, flags, entries, hdr);
     hipLaunchKernelGGL(k_gather_wide, dim3(blocks), dim3(256), 0, s, sph.count, cap, nodes,
                        reinterpret_cast<WideNode *>(mem + L.wide));
     return hipGetLastError();

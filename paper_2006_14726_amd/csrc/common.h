@@ -128,7 +128,7 @@ struct __align__(128) WideNode {
 
 struct __align__(256) BvhHeader {
     uint32_t n;            // spheres at build time
-    uint32_t n_cross;      // refit: entries in the list of chunk-crossing arrivals
+    uint32_t n_entry;      // refit: entries of the top tree (treelet roots and leaves under top nodes)
     float scene_lo[3];     // box of all leaves (root box)
     float scene_hi[3];
     float cen_lo[3];       // bounds of the centres (Morton quantisation)
@@ -141,7 +141,7 @@ __host__ __device__ inline size_t align256(size_t x) { return (x + 255) & ~(size
 
 // Offsets inside splat_bvh.mem.
 struct BvhLayout {
-    size_t header, nodes, leaf_parent, node_parent, leaf_ids, flags, ranges, cross, wide, total;
+    size_t header, nodes, leaf_parent, node_parent, leaf_ids, flags, ranges, entries, wide, total;
     __host__ __device__ explicit BvhLayout(uint32_t cap)
     {
         const size_t c = cap < 1 ? 1 : cap;
@@ -152,8 +152,8 @@ struct BvhLayout {
         leaf_ids = align256(node_parent + c * 4);
         flags = align256(leaf_ids + c * 4);
         ranges = align256(flags + c * 4);       // first/last sorted leaf of each internal node
-        cross = align256(ranges + c * 8);       // refit arrivals at chunk-crossing nodes
-        wide = align256(cross + c * 8);         // WideNode per internal node (what the trace reads)
+        entries = align256(ranges + c * 8);     // refit entries of the top tree (at most 2 per top node)
+        wide = align256(entries + c * 8);       // WideNode per internal node (what the trace reads)
         total = align256(wide + c * sizeof(WideNode));
     }
 };
@@ -166,7 +166,7 @@ constexpr int kSortItems = 8;                    // keys per thread
 constexpr int kSortTile = kSortBlock * kSortItems;
 constexpr int kMortonBits = 30;
 
-constexpr int kRefitChunk = 2048;                // leaves refit by one workgroup
+constexpr int kTreelet = 2048;                   // most leaves of a treelet (refit by one workgroup)
 
 struct BuildLayout {
     size_t keys_a, vals_a, keys_b, vals_b, hist, partial, totals, total;

@@ -66,14 +66,14 @@ EMPTY = 0xFFFFFFFF
 
 def bvh_core(mem, cap: int):
     """The BVH bytes that define the hierarchy: everything except the refit's
-    scratch list of chunk-crossing arrivals (appended in arrival order) and its count."""
+    list of top-tree entries (appended in a nondeterministic order) and its count."""
     import torch
     c = max(cap, 1)
     lay = bvh_layout(cap)
     ranges = _align(lay["leaf_ids"] + c * 4)       # flags
     ranges = _align(ranges + c * 4)                # ranges
-    cross = _align(ranges + c * 8)
-    core = mem[:cross].clone() if isinstance(mem, torch.Tensor) else mem[:cross].copy()
+    entries = _align(ranges + c * 8)
+    core = mem[:entries].clone() if isinstance(mem, torch.Tensor) else mem[:entries].copy()
     core[4:8] = 0
     return core
 
