@@ -108,9 +108,12 @@ typedef struct splat_bvh {
  *               the result does not depend on it
  *   tile_w/h    pixels per 64-lane wavefront: 8x8, 16x4, 32x2, 64x1 or 4x16
  *               (0x0 = 8x8); the result does not depend on it
- *   schedule    tile -> XCD assignment: 0 super-tiles of 8x8 tiles dealt
- *               round robin to the XCDs, 1 one contiguous band per XCD; the
- *               result does not depend on it
+ *   schedule    order of the tiles: 0 super-tiles of 8x8 tiles dealt round
+ *               robin to the XCDs, 1 one contiguous band per XCD, 2 heaviest
+ *               first (tiles ranked by the sphere centres that project near
+ *               them; needs the trace workspace); the result does not
+ *               depend on it.  The batched launch ignores it (it has its own
+ *               work queue)
  *   walk        SPLAT_WALK_LANE (each ray on its own path; default) or
  *               SPLAT_WALK_PACKET (a wavefront's rays as one packet); the
  *               result does not depend on it
@@ -196,9 +199,13 @@ int splat_build_bvh(const splat_spheres *sph, const splat_bvh *bvh, int32_t refi
  * colours from sph->rgba.
  *   out_rgba  device float4 [height][width] (C, A), background 0
  *   out_hits  device uint32 [height][width] composited hit count, or NULL
+ *   ws        device, >= splat_workspace_bytes(SPLAT_OP_TRACE, 0, width, height)
+ *             with schedule 2 (SPLAT_ENOSPC otherwise); unused, and may be
+ *             NULL, with schedules 0 and 1.  Calls that overlap on one
+ *             workspace race.
  */
 int splat_trace(const splat_bvh *bvh, const splat_spheres *sph, const splat_camera *cam, const splat_trace_opts *opts,
-                float *out_rgba, uint32_t *out_hits, void *stream);
+                float *out_rgba, uint32_t *out_hits, void *ws, size_t ws_bytes, void *stream);
 
 /*
  * Backward of splat_trace: given dL/d(out_rgba), accumulates dL/dk, dL/da,
@@ -208,10 +215,11 @@ int splat_trace(const splat_bvh *bvh, const splat_spheres *sph, const splat_came
  *   out_rgba   device float4 [height][width]: the forward output of the same
  *              call (checked for NULL; the hits are recomputed, not read from it)
  *   grad_rgba  device float4 [height][width]
+ *   ws         as for splat_trace (SPLAT_OP_BACKWARD gives the same size)
  */
 int splat_trace_backward(const splat_bvh *bvh, const splat_spheres *sph, const splat_camera *cam,
                          const splat_trace_opts *opts, const float *out_rgba, const float *grad_rgba,
-                         const splat_grads *grads, void *stream);
+                         const splat_grads *grads, void *ws, size_t ws_bytes, void *stream);
 
 /*
  * Batched trace: every job of `jobs` (device array of n_jobs splat_batch_job)

@@ -75,10 +75,11 @@ def load() -> ctypes.CDLL:
         lib.splat_build_bvh.argtypes = [ctypes.POINTER(splat_spheres), ctypes.POINTER(splat_bvh), ctypes.c_int32, _P,
                                         ctypes.c_size_t, _P]
         lib.splat_trace.argtypes = [ctypes.POINTER(splat_bvh), ctypes.POINTER(splat_spheres),
-                                    ctypes.POINTER(splat_camera), ctypes.POINTER(splat_trace_opts), _P, _P, _P]
+                                    ctypes.POINTER(splat_camera), ctypes.POINTER(splat_trace_opts), _P, _P, _P,
+                                    ctypes.c_size_t, _P]
         lib.splat_trace_backward.argtypes = [ctypes.POINTER(splat_bvh), ctypes.POINTER(splat_spheres),
                                              ctypes.POINTER(splat_camera), ctypes.POINTER(splat_trace_opts), _P, _P,
-                                             ctypes.POINTER(splat_grads), _P]
+                                             ctypes.POINTER(splat_grads), _P, ctypes.c_size_t, _P]
         lib.splat_trace_batched.argtypes = [_P, _P, ctypes.c_int32, ctypes.c_uint32, ctypes.POINTER(splat_trace_opts),
                                             ctypes.c_int32, _P, ctypes.c_size_t, _P]
         lib.splat_last_error.argtypes = []

@@ -18,7 +18,7 @@ import torch
 
 from .render import BVH, Spheres, TraceOptions, trace
 
-TRACE_CANDIDATES = [(k, tile, sched, walk) for k in (6, 8) for tile in ((8, 8), (16, 4)) for sched in (0, 1)
+TRACE_CANDIDATES = [(k, tile, sched, walk) for k in (6, 8) for tile in ((8, 8), (16, 4)) for sched in (0, 2)
                     for walk in (0, 1)]
 WAVES_PER_CU = (8, 16, 32)
 

@@ -99,7 +99,7 @@ int resolve_opts(const splat_trace_opts *o, splat_trace_opts *out)
     if (!shape_ok) return fail(SPLAT_EUNSUPPORTED, "tile %dx%d is not a 64-pixel shape", out->tile_w, out->tile_h);
     if (out->mode != SPLAT_ALPHA_CONSTANT && out->mode != SPLAT_ALPHA_SOFT)
         return fail(SPLAT_EUNSUPPORTED, "unknown alpha mode %d", out->mode);
-    if (out->schedule != 0 && out->schedule != 1)
+    if (out->schedule != 0 && out->schedule != 1 && out->schedule != 2)
         return fail(SPLAT_EUNSUPPORTED, "unknown schedule %d", out->schedule);
     if (out->walk != SPLAT_WALK_LANE && out->walk != SPLAT_WALK_PACKET)
         return fail(SPLAT_EUNSUPPORTED, "unknown walk %d", out->walk);
@@ -118,11 +118,24 @@ int hip_status(hipError_t e, const char *what)
 
 extern "C" {
 
-int splat_version(void) { return 101; }
+int splat_version(void) { return 102; }
 
 const char *splat_last_error(void) { return g_err; }
 
 size_t splat_bvh_bytes(uint32_t capacity) { return BvhLayout(capacity).total; }
+
+// Workspace of the schedule-2 tile order: enough for any 64-pixel tile shape.
+static size_t trace_ws_bytes(int32_t width, int32_t height)
+{
+    static const int shapes[5][2] = {{8, 8}, {16, 4}, {32, 2}, {64, 1}, {4, 16}};
+    size_t best = 0;
+    for (const auto &sh : shapes) {
+        const uint64_t t = (uint64_t)((width + sh[0] - 1) / sh[0]) * (uint64_t)((height + sh[1] - 1) / sh[1]);
+        const size_t b = TileOrderLayout((uint32_t)(t < 0xffffffffu ? t : 0xffffffffu)).total;
+        if (b > best) best = b;
+    }
+    return best;
+}
 
 size_t splat_workspace_bytes(int32_t op, uint32_t capacity, int32_t width, int32_t height)
 {
@@ -131,7 +144,7 @@ size_t splat_workspace_bytes(int32_t op, uint32_t capacity, int32_t width, int32
         return (width > 0 && height > 0) ? unproject_ws_bytes((int64_t)width * height) : 0;
     case SPLAT_OP_BUILD: return BuildLayout(capacity).total;
     case SPLAT_OP_TRACE:
-    case SPLAT_OP_BACKWARD: return 0;
+    case SPLAT_OP_BACKWARD: return (width > 0 && height > 0) ? trace_ws_bytes(width, height) : 0;
     case SPLAT_OP_BATCHED: return 256;
     default: return 0;
     }
@@ -201,27 +214,39 @@ static int trace_common(const splat_bvh *bvh, const splat_spheres *sph, const sp
     return SPLAT_OK;
 }
 
+// Schedule 2 orders the tiles in the workspace, which must then be large enough.
+static int check_trace_ws(const TraceArgs &a, void *ws, size_t ws_bytes)
+{
+    if (a.schedule != 2) return SPLAT_OK;
+    const size_t need = trace_ws_bytes(a.cam.w, a.cam.h);
+    if (!ws || ws_bytes < need)
+        return fail(SPLAT_ENOSPC, "schedule 2 needs a workspace of %zu bytes (got %zu)", need, ws ? ws_bytes : 0);
+    return SPLAT_OK;
+}
+
 int splat_trace(const splat_bvh *bvh, const splat_spheres *sph, const splat_camera *cam, const splat_trace_opts *opts,
-                float *out_rgba, uint32_t *out_hits, void *stream)
+                float *out_rgba, uint32_t *out_hits, void *ws, size_t ws_bytes, void *stream)
 {
     TraceArgs a;
     int rc;
     if ((rc = trace_common(bvh, sph, cam, opts, a))) return rc;
     if (!out_rgba) return fail(SPLAT_EINVAL, "out_rgba is NULL");
+    if ((rc = check_trace_ws(a, ws, ws_bytes))) return rc;
     a.out = reinterpret_cast<float4 *>(out_rgba);
     a.hits = out_hits;
     if ((rc = check_device())) return rc;
-    return hip_status(launch_trace(a, false, static_cast<hipStream_t>(stream)), "trace launch");
+    return hip_status(launch_trace(a, false, ws, static_cast<hipStream_t>(stream)), "trace launch");
 }
 
 int splat_trace_backward(const splat_bvh *bvh, const splat_spheres *sph, const splat_camera *cam,
                          const splat_trace_opts *opts, const float *out_rgba, const float *grad_rgba,
-                         const splat_grads *grads, void *stream)
+                         const splat_grads *grads, void *ws, size_t ws_bytes, void *stream)
 {
     TraceArgs a;
     int rc;
     if ((rc = trace_common(bvh, sph, cam, opts, a))) return rc;
     if (!out_rgba || !grad_rgba) return fail(SPLAT_EINVAL, "out_rgba/grad_rgba is NULL");
+    if ((rc = check_trace_ws(a, ws, ws_bytes))) return rc;
     if (!grads || !grads->d_rgb || !grads->d_alpha) return fail(SPLAT_EINVAL, "grads d_rgb/d_alpha is NULL");
     if (a.mode == SPLAT_ALPHA_SOFT && (!grads->d_radius || !grads->d_centre))
         return fail(SPLAT_EINVAL, "soft mode needs d_radius and d_centre");
@@ -231,7 +256,7 @@ int splat_trace_backward(const splat_bvh *bvh, const splat_spheres *sph, const s
     a.d_radius = grads->d_radius;
     a.d_centre = grads->d_centre;
     if ((rc = check_device())) return rc;
-    return hip_status(launch_trace(a, true, static_cast<hipStream_t>(stream)), "backward launch");
+    return hip_status(launch_trace(a, true, ws, static_cast<hipStream_t>(stream)), "backward launch");
 }
 
 int splat_trace_batched(const splat_batch_job *jobs, const uint32_t *tile_offsets, int32_t n_jobs,

@@ -186,6 +186,22 @@ struct BuildLayout {
     }
 };
 
+// Trace workspace of the heaviest-first tile order (schedule 2).
+constexpr int kOrderBuckets = 64;
+
+struct TileOrderLayout {
+    size_t counts, bucket, order, hist, total;
+    __host__ __device__ explicit TileOrderLayout(uint32_t tiles)
+    {
+        const size_t t = tiles < 1 ? 1 : tiles;
+        counts = 0;
+        bucket = align256(counts + t * 4);
+        order = align256(bucket + t * 4);
+        hist = align256(order + t * 4);
+        total = align256(hist + 2 * kOrderBuckets * 4);  // histogram, then cursors
+    }
+};
+
 // Unprojection workspace: per-block valid counts and their exclusive scan.
 constexpr int kUnprojBlock = 256;
 constexpr int kUnprojItems = 4;

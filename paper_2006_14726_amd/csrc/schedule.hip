@@ -1,0 +1,159 @@
+// Heaviest-first tile order for the trace (schedule 2).
+//
+// A wave's time is set by its slowest ray, and the slow rays are the ones
+// that graze the sphere sheet: they meet many boxes along a long stretch.
+// Where the sheet is seen edge-on, many sphere centres project into few
+// pixels, so the number of centres projecting into a tile, maximised over
+// the tile's neighbourhood (a grazing ray spreads over neighbouring tiles),
+// ranks the tiles by cost well enough.  Launching the heavy tiles first
+// keeps them off the end of the launch, where they would run with the GPU
+// mostly idle.  The order only changes when a tile runs, never what it
+// computes.
+//
+//   zero     per-tile counts, the bucket histogram and the bucket cursors
+//   count    one thread per kSample-th sphere: project the centre (float;
+//            only a ranking) and count it in its tile; neighbouring spheres
+//            share tiles, so a wave adds once per distinct tile
+//   keys     one thread per tile: neighbourhood maximum -> log bucket
+//            (bucket 0 = heaviest) and the bucket histogram
+//   scatter  one thread per tile: its slot in the order, buckets ascending
+#include "common.h"
+#include "kernels.h"
+
+namespace splat {
+
+constexpr int kOrderBlock = 256;
+constexpr int kReach = 3;   // neighbourhood: (2 kReach + 1)^2 tiles
+constexpr int kSample = 4;  // every kSample-th sphere is counted (log-scale keys do not need all)
+
+__global__ void __launch_bounds__(kOrderBlock)
+k_tile_zero(uint32_t *__restrict__ counts, uint32_t tiles, uint32_t *__restrict__ hist)
+{
+    const uint32_t i = blockIdx.x * kOrderBlock + threadIdx.x;
+    if (i < tiles) counts[i] = 0u;
+    if (i < (uint32_t)(2 * kOrderBuckets)) hist[i] = 0u;  // histogram, then cursors
+}
+
+__global__ void __launch_bounds__(kOrderBlock)
+k_tile_count(const float4 *__restrict__ cr, const uint32_t *__restrict__ count, uint32_t cap, Cam cam, int tile_w,
+             int tile_h, int tiles_x, int tiles_y, uint32_t *__restrict__ counts)
+{
+    const uint32_t n = min(*count, cap);
+    const uint64_t i = ((uint64_t)blockIdx.x * kOrderBlock + threadIdx.x) * kSample;
+    uint32_t tile = 0xffffffffu;
+    if (i < n) {
+        const float4 c = cr[i];
+        const float vx = c.x - (float)cam.eye[0], vy = c.y - (float)cam.eye[1], vz = c.z - (float)cam.eye[2];
+        const float z = vx * (float)cam.fwd[0] + vy * (float)cam.fwd[1] + vz * (float)cam.fwd[2];
+        const float th = (float)cam.tan_half, aspect = (float)cam.w / (float)cam.h;
+        const float x = (vx * (float)cam.right[0] + vy * (float)cam.right[1] + vz * (float)cam.right[2]) /
+                        (z * th * aspect);
+        const float y = (vx * (float)cam.up[0] + vy * (float)cam.up[1] + vz * (float)cam.up[2]) / (z * th);
+        const float px = (x + 1.0f) * 0.5f * (float)cam.w, py = (1.0f - y) * 0.5f * (float)cam.h;
+        if (z > 0.0f && px >= 0.0f && py >= 0.0f && px < (float)cam.w && py < (float)cam.h) {
+            const int tx = min((int)px / tile_w, tiles_x - 1), ty = min((int)py / tile_h, tiles_y - 1);
+            tile = (uint32_t)ty * (uint32_t)tiles_x + (uint32_t)tx;
+        }
+    }
+    // one atomic per distinct tile of the wave: the lowest pending lane adds
+    // the number of pending lanes that share its tile; each round retires at
+    // least that lane, so the loop ends within 64 rounds
+    bool pending = tile != 0xffffffffu;
+    for (uint64_t pend = __ballot(pending); pend != 0; pend = __ballot(pending)) {
+        const int leader = __ffsll((unsigned long long)pend) - 1;
+        const uint32_t first = __shfl(tile, leader, kWave);
+        const bool mine = pending && tile == first;
+        const uint64_t same = __ballot(mine);
+        if (mine && (int)__lane_id() == leader) atomicAdd(&counts[first], (uint32_t)__popcll(same));
+        if (mine) pending = false;
+    }
+}
+
+__global__ void __launch_bounds__(kOrderBlock)
+k_tile_keys(const uint32_t *__restrict__ counts, int tiles_x, int tiles_y, uint32_t *__restrict__ bucket,
+            uint32_t *__restrict__ hist)
+{
+    __shared__ uint32_t h[kOrderBuckets];
+    if (threadIdx.x < (unsigned)kOrderBuckets) h[threadIdx.x] = 0u;
+    __syncthreads();
+    const uint32_t tiles = (uint32_t)tiles_x * (uint32_t)tiles_y;
+    const uint32_t t = blockIdx.x * kOrderBlock + threadIdx.x;
+    if (t < tiles) {
+        const int tx = (int)(t % (uint32_t)tiles_x), ty = (int)(t / (uint32_t)tiles_x);
+        uint32_t key = 0;
+        for (int y = max(ty - kReach, 0); y <= min(ty + kReach, tiles_y - 1); ++y)
+            for (int x = max(tx - kReach, 0); x <= min(tx + kReach, tiles_x - 1); ++x)
+                key = max(key, counts[(size_t)y * tiles_x + x]);
+        // four buckets per octave of the key, heaviest first
+        const int level = (int)(4.0f * log2f(1.0f + (float)key));
+        const uint32_t b = (uint32_t)(kOrderBuckets - 1 - min(level, kOrderBuckets - 1));
+        bucket[t] = b;
+        atomicAdd(&h[b], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < (unsigned)kOrderBuckets && h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
+}
+
+// Every block scans the bucket histogram itself (64 entries, one wave);
+// slots are reserved per block and bucket with one atomic on the bucket's
+// cursor, then handed out within the block.  The order inside a bucket is
+// arbitrary.
+__global__ void __launch_bounds__(kOrderBlock)
+k_tile_scatter(const uint32_t *__restrict__ bucket, uint32_t tiles, uint32_t *__restrict__ hist,
+               uint32_t *__restrict__ order)
+{
+    static_assert(kOrderBuckets == kWave, "one bucket per lane");
+    __shared__ uint32_t cnt[kOrderBuckets], base[kOrderBuckets], start[kOrderBuckets];
+    uint32_t *cursor = hist + kOrderBuckets;
+    if (threadIdx.x < (unsigned)kOrderBuckets) {
+        cnt[threadIdx.x] = 0u;
+        const uint32_t v = hist[threadIdx.x];
+        uint32_t incl = v;
+        for (int off = 1; off < kWave; off <<= 1) {
+            const uint32_t o = __shfl_up(incl, off, kWave);
+            if ((int)threadIdx.x >= off) incl += o;
+        }
+        start[threadIdx.x] = incl - v;
+    }
+    __syncthreads();
+    const uint32_t t = blockIdx.x * kOrderBlock + threadIdx.x;
+    uint32_t b = 0, rank = 0;
+    if (t < tiles) {
+        b = bucket[t];
+        rank = atomicAdd(&cnt[b], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < (unsigned)kOrderBuckets && cnt[threadIdx.x])
+        base[threadIdx.x] = start[threadIdx.x] + atomicAdd(&cursor[threadIdx.x], cnt[threadIdx.x]);
+    __syncthreads();
+    if (t < tiles) order[base[b] + rank] = t;
+}
+
+hipError_t launch_tile_order(const TraceArgs &a, int tiles_x, int tiles_y, void *ws, hipStream_t s,
+                             const uint32_t **order_out)
+{
+    const uint32_t tiles = (uint32_t)tiles_x * (uint32_t)tiles_y;
+    const TileOrderLayout W(tiles);
+    char *w = static_cast<char *>(ws);
+    uint32_t *counts = reinterpret_cast<uint32_t *>(w + W.counts);
+    uint32_t *bucket = reinterpret_cast<uint32_t *>(w + W.bucket);
+    uint32_t *order = reinterpret_cast<uint32_t *>(w + W.order);
+    uint32_t *hist = reinterpret_cast<uint32_t *>(w + W.hist);
+    const uint32_t tile_blocks = (tiles + kOrderBlock - 1) / kOrderBlock;
+    const uint32_t cap = a.bvh_capacity;
+    const uint32_t samples = (cap + kSample - 1) / kSample;
+    const uint32_t sphere_blocks = samples ? (samples + kOrderBlock - 1) / kOrderBlock : 1;
+    // the sphere count of the hierarchy (clamped by cap below)
+    const uint32_t *n = &static_cast<const BvhHeader *>(a.bvh_mem)->n;
+    hipLaunchKernelGGL(k_tile_zero, dim3(tile_blocks > 0 ? tile_blocks : 1), dim3(kOrderBlock), 0, s, counts, tiles,
+                       hist);
+    hipLaunchKernelGGL(k_tile_count, dim3(sphere_blocks), dim3(kOrderBlock), 0, s, a.centre_radius, n, cap, a.cam,
+                       a.tile_w, a.tile_h, tiles_x, tiles_y, counts);
+    hipLaunchKernelGGL(k_tile_keys, dim3(tile_blocks), dim3(kOrderBlock), 0, s, counts, tiles_x, tiles_y, bucket,
+                       hist);
+    hipLaunchKernelGGL(k_tile_scatter, dim3(tile_blocks), dim3(kOrderBlock), 0, s, bucket, tiles, hist, order);
+    *order_out = order;
+    return hipGetLastError();
+}
+
+}  // namespace splat

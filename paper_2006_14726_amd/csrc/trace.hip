@@ -564,7 +564,8 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
 // super-tiles of 8 x 8 tiles, dealt round robin to the XCDs; each XCD walks
 // its super-tiles tile by tile, so neighbouring tiles share an L2 while
 // every XCD gets a spread of the image (balanced load).  Schedule 1: each
-// XCD takes one contiguous band of tiles.
+// XCD takes one contiguous band of tiles.  Schedule 2 reads the tile of each
+// block from the heaviest-first order (schedule.hip).
 __device__ inline bool tile_of_block(uint32_t b, int tiles_x, int tiles_y, int schedule, int &tx, int &ty)
 {
     const int xcd = (int)(b % 8), i = (int)(b / 8);
@@ -595,7 +596,14 @@ __global__ void __launch_bounds__(64) k_trace(TraceArgs a, int tiles_x, int tile
 {
     __shared__ WaveLds lds;
     int tx, ty;
-    if (!tile_of_block(blockIdx.x, tiles_x, tiles_y, a.schedule, tx, ty)) return;
+    if (a.order) {
+        if (blockIdx.x >= (uint32_t)(tiles_x * tiles_y)) return;
+        const uint32_t t = a.order[blockIdx.x];
+        tx = (int)(t % (uint32_t)tiles_x);
+        ty = (int)(t / (uint32_t)tiles_x);
+    } else if (!tile_of_block(blockIdx.x, tiles_x, tiles_y, a.schedule, tx, ty)) {
+        return;
+    }
     const char *mem = static_cast<const char *>(a.bvh_mem);
     const BvhLayout L(a.layout_cap);
     const BvhHeader *hdr = reinterpret_cast<const BvhHeader *>(mem);
@@ -652,6 +660,7 @@ k_trace_batched(const splat_batch_job *__restrict__ jobs, const uint32_t *__rest
         a.tile_h = tile_h;
         a.schedule = 0;
         a.walk = LANE ? SPLAT_WALK_LANE : SPLAT_WALK_PACKET;
+        a.order = nullptr;
         a.out = reinterpret_cast<float4 *>(j.out_rgba);
         a.hits = j.out_hits;
         a.grad = nullptr;
@@ -685,11 +694,17 @@ static hipError_t launch_k(const TraceArgs &a, int K, dim3 grid, int tiles_x, in
     return hipGetLastError();
 }
 
-hipError_t launch_trace(const TraceArgs &a, bool backward, hipStream_t s)
+hipError_t launch_trace(const TraceArgs &args, bool backward, void *ws, hipStream_t s)
 {
+    TraceArgs a = args;
     const int tiles_x = (a.cam.w + a.tile_w - 1) / a.tile_w;
     const int tiles_y = (a.cam.h + a.tile_h - 1) / a.tile_h;
-    const dim3 grid(blocks_for(tiles_x, tiles_y, a.schedule));
+    a.order = nullptr;
+    if (a.schedule == 2) {
+        const hipError_t e = launch_tile_order(a, tiles_x, tiles_y, ws, s, &a.order);
+        if (e != hipSuccess) return e;
+    }
+    const dim3 grid(a.order ? (uint32_t)(tiles_x * tiles_y) : blocks_for(tiles_x, tiles_y, a.schedule));
     if (a.walk == SPLAT_WALK_PACKET)
         return backward ? launch_k<true, false>(a, a.kbuf, grid, tiles_x, tiles_y, s)
                         : launch_k<false, false>(a, a.kbuf, grid, tiles_x, tiles_y, s);

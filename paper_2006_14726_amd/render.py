@@ -153,7 +153,7 @@ class TraceOptions:
     mode: int = _lib.SPLAT_ALPHA_CONSTANT
     kbuf: int = 6
     tile: tuple = field(default=(8, 8))
-    schedule: int = 0
+    schedule: int = 2  # 0 super-tiles per XCD, 1 bands, 2 heaviest tiles first
     walk: int = 0  # SPLAT_WALK_LANE (0) or SPLAT_WALK_PACKET (1)
 
     def struct(self) -> _lib.splat_trace_opts:
@@ -185,8 +185,10 @@ def trace(bvh: BVH, sph: Spheres, cam, opts: TraceOptions | None = None, out: to
         raise ValueError("hits must be int32 [H, W]")
     lib = _lib.load()
     c, o, s, b = _lib.camera_struct(cam), opts.struct(), sph.struct(), bvh.struct()
+    need = lib.splat_workspace_bytes(_lib.SPLAT_OP_TRACE, 0, W, H)
+    ws = workspace(need, dev, "trace")
     _lib.check(lib.splat_trace(ctypes.byref(b), ctypes.byref(s), ctypes.byref(c), ctypes.byref(o), _ptr(out),
-                               _ptr(hits), _stream()))
+                               _ptr(hits), _ptr(ws), ws.numel(), _stream()))
     return out, hits
 
 
@@ -210,8 +212,11 @@ def trace_backward(bvh: BVH, sph: Spheres, cam, opts: TraceOptions, out_rgba: to
     g.d_radius, g.d_centre = grads["radius"].data_ptr(), grads["centre"].data_ptr()
     lib = _lib.load()
     c, o, s, b = _lib.camera_struct(cam), opts.struct(), sph.struct(), bvh.struct()
+    need = lib.splat_workspace_bytes(_lib.SPLAT_OP_BACKWARD, 0, W, H)
+    ws = workspace(need, dev, "trace")
     _lib.check(lib.splat_trace_backward(ctypes.byref(b), ctypes.byref(s), ctypes.byref(c), ctypes.byref(o),
-                                        _ptr(out_rgba), _ptr(grad_rgba), ctypes.byref(g), _stream()))
+                                        _ptr(out_rgba), _ptr(grad_rgba), ctypes.byref(g), _ptr(ws), ws.numel(),
+                                        _stream()))
     return grads
 
 

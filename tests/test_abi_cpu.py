@@ -27,7 +27,7 @@ def test_library_exports_every_declared_symbol():
     lib = _lib.load()
     for name in declared_functions():
         assert hasattr(lib, name), name
-    assert lib.splat_version() == 101
+    assert lib.splat_version() == 102
 
 
 def test_sizes_are_pure_host_functions():
@@ -96,20 +96,26 @@ def test_trace_option_validation():
     out = ctypes.c_void_p(4096)
     for kw, code in [({"kbuf": 3}, _lib.SPLAT_EUNSUPPORTED), ({"tile_w": 8, "tile_h": 4}, _lib.SPLAT_EUNSUPPORTED),
                      ({"mode": 5}, _lib.SPLAT_EUNSUPPORTED), ({"alpha_stop": math.nan}, _lib.SPLAT_EINVAL),
-                     ({"t_max": 0.0}, _lib.SPLAT_EINVAL)]:
+                     ({"t_max": 0.0}, _lib.SPLAT_EINVAL), ({"schedule": 3}, _lib.SPLAT_EUNSUPPORTED),
+                     ({"walk": 2}, _lib.SPLAT_EUNSUPPORTED), ({"schedule": 2}, _lib.SPLAT_ENOSPC)]:
         o = _lib.splat_trace_opts()
         o.alpha_stop, o.t_max = 0.99, math.inf
         for k, v in kw.items():
             setattr(o, k, v)
         got, msg = _err(lib.splat_trace(ctypes.byref(bvh), ctypes.byref(sph), ctypes.byref(cam), ctypes.byref(o),
-                                        out, None, None))
+                                        out, None, None, 0, None))
         assert got == code, (kw, msg)
     o = _lib.splat_trace_opts()
     o.alpha_stop, o.t_max = 0.99, math.inf
     bvh.mem = 256 * 64 + 4  # misaligned
     got, msg = _err(lib.splat_trace(ctypes.byref(bvh), ctypes.byref(sph), ctypes.byref(cam), ctypes.byref(o), out,
-                                    None, None))
+                                    None, None, 0, None))
     assert got == _lib.SPLAT_EINVAL and "aligned" in msg
+    # the trace workspace covers every 64-pixel tile shape
+    w, h = 1921, 1081
+    need = lib.splat_workspace_bytes(_lib.SPLAT_OP_TRACE, 0, w, h)
+    assert need >= 3 * 4 * ((w + 63) // 64) * h
+    assert lib.splat_workspace_bytes(_lib.SPLAT_OP_BACKWARD, 0, w, h) == need
 
 
 def test_no_device_is_reported_not_crashed():

@@ -198,13 +198,15 @@ def test_result_independent_of_kbuf_and_tile(sp):
         for k in (1, 2, 4, 6, 8, 16):
             for tile in ((8, 8), (16, 4), (32, 2)):
                 for walk in (0, 1):
-                    img, hits = sp.trace(bvh, sph, cam, sp.TraceOptions(alpha_stop=stop, kbuf=k, tile=tile, walk=walk))
-                    if ref is None:
-                        ref = (img.clone(), hits.clone())
-                        if stop == NEVER:
-                            assert int(hits.max()) > 16  # several restarts at k = 1, 2, 4, 6, 8
-                    else:
-                        assert torch.equal(img, ref[0]) and torch.equal(hits, ref[1]), (k, tile, walk)
+                    for sched in (0, 1, 2):
+                        o = sp.TraceOptions(alpha_stop=stop, kbuf=k, tile=tile, walk=walk, schedule=sched)
+                        img, hits = sp.trace(bvh, sph, cam, o)
+                        if ref is None:
+                            ref = (img.clone(), hits.clone())
+                            if stop == NEVER:
+                                assert int(hits.max()) > 16  # several restarts at k = 1, 2, 4, 6, 8
+                        else:
+                            assert torch.equal(img, ref[0]) and torch.equal(hits, ref[1]), (k, tile, walk, sched)
 
 
 def test_tiny_config_full_frame(sp):
