@@ -32,6 +32,7 @@ def parse():
     p.add_argument("--kbuf", type=int, default=6)
     p.add_argument("--tile", type=str, default="8x8")
     p.add_argument("--walk", type=int, default=0, help="0 per-lane BVH walk, 1 packet walk")
+    p.add_argument("--schedule", type=int, default=2, help="tile order: 0 super-tiles per XCD, 1 bands, 2 heaviest first")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--no-bwd", action="store_true", help="skip the fwd+bwd measurement")
     p.add_argument("--batch-frames", type=int, default=64,
@@ -46,7 +47,7 @@ def measured_traffic(args):
     when the trace kernel source or the launch configuration differs from the one profiled."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "trace_client_frame_hbm_traffic.txt")
-    if not os.path.exists(path) or (args.kbuf, args.tile, args.scale, args.walk) != (6, "8x8", 1.0, 0):
+    if not os.path.exists(path) or (args.kbuf, args.tile, args.scale, args.walk, args.schedule) != (6, "8x8", 1.0, 0, 2):
         return None
     rec = {}
     for line in open(path):
@@ -95,7 +96,7 @@ def main():
     rgba = torch.from_numpy(rgba_np).to(dev)
     depth = torch.from_numpy(depth_np).to(dev)
     tw, th = (int(v) for v in args.tile.split("x"))
-    opts = sp.TraceOptions(alpha_stop=0.99, kbuf=args.kbuf, tile=(tw, th), walk=args.walk)
+    opts = sp.TraceOptions(alpha_stop=0.99, kbuf=args.kbuf, tile=(tw, th), walk=args.walk, schedule=args.schedule)
     P = dst.width * dst.height
 
     sph = sp.alloc_spheres(src.width * src.height, dev, half=True)
@@ -162,7 +163,8 @@ def main():
         "config": {"workload": f"client frame: {src.width}x{src.height} source ({n} spheres, radius scale "
                                f"{args.scale}) -> {dst.width}x{dst.height} target, yaw {work.yaw} pitch {work.pitch}",
                    "rays": P, "spheres": n, "kbuf": args.kbuf, "tile": args.tile,
-                   "walk": "per-lane" if args.walk == 0 else "packet", "alpha_stop": 0.99},
+                   "walk": "per-lane" if args.walk == 0 else "packet",
+                   "schedule": ["xcd super-tiles", "xcd bands", "heaviest first"][args.schedule], "alpha_stop": 0.99},
         "stages_ms": {"unproject": round(float(np.median(stage[:, 0])), 4),
                       "build": round(float(np.median(stage[:, 1])), 4),
                       "trace": round(float(np.median(stage[:, 2])), 4)},
@@ -171,7 +173,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": measured_traffic(args),
                      "kernel": f"k_trace<{args.kbuf}, false, {'true' if args.walk == 0 else 'false'}>",
-                     "algorithmic_bytes": tb, "avg_launch_ms": round(trace_ms, 4)},
+                     "algorithmic_bytes": tb, "avg_launch_ms": round(trace_ms, 4),
+                     "note": "avg_launch_ms times the whole trace call (with schedule 2 it includes the ~25 us of "
+                             "tile-ordering kernels), so achieved is a lower bound for the trace kernel alone"},
     }
 
     if not args.no_bwd:
@@ -255,15 +259,17 @@ def cpu_baseline(sph, dst, n):
     col = sph.rgba[:n].cpu().numpy()
     rng = np.random.default_rng(0)
     table = oracle.sphere_table(cr, col)
-    probe = rng.integers(0, dst.width * dst.height, 64)
-    t0 = time.perf_counter()
-    oracle.render_table(table, dst, pixels=probe)
-    dt = time.perf_counter() - t0
-    count = int(min(max(64, 64 * 12.0 / max(dt, 1e-3)), 200000))
-    pix = rng.integers(0, dst.width * dst.height, count)
-    t0 = time.perf_counter()
-    oracle.render_table(table, dst, pixels=pix)
-    dt = time.perf_counter() - t0
+    oracle.render_table(table, dst, pixels=rng.integers(0, dst.width * dst.height, 64))  # warm
+    # batches of random pixels until at least 10 s of oracle time
+    count, dt, batch = 0, 0.0, 2048
+    while dt < 10.0 and count < 400000:
+        pix = rng.integers(0, dst.width * dst.height, batch)
+        t0 = time.perf_counter()
+        oracle.render_table(table, dst, pixels=pix)
+        step = time.perf_counter() - t0
+        dt += step
+        count += batch
+        batch = int(min(max(batch, batch * (10.0 - dt) / max(step, 1e-3)), 100000)) if dt < 10.0 else batch
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": round(count / dt / 1e6, 6), "unit": "Mrays/s", "cores": cores, "kind": "oracle",
             "sample": f"{count} random pixels of the same 1920x1080 frame, all {n} spheres tested per ray "
