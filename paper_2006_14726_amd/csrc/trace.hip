@@ -339,6 +339,25 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
             const uint32_t o0 = 2u * cn + gn, o2 = 2u * (1u - cn) + gf;
             return o0 | ((o0 ^ 1u) << 2) | (o2 << 4) | ((o2 ^ 1u) << 6);
         };
+        // per lane: hit mask and entry distance of each slot
+        auto box_hits_tn = [&](const float *f, uint32_t kinds, float pf, float tn_out[4]) -> uint32_t {
+            uint32_t hits = 0;
+#pragma unroll
+            for (int side = 0; side < 4; ++side) {
+                tn_out[side] = INFINITY;
+                if (!((kinds >> (4 + side)) & 1u)) continue;
+                const float *s = f + 6 * side;
+                const float t1x = fmaf(s[0], ray.inv[0], -ray.oPi[0]), t2x = fmaf(s[3], ray.inv[0], -ray.oMi[0]);
+                const float t1y = fmaf(s[1], ray.inv[1], -ray.oPi[1]), t2y = fmaf(s[4], ray.inv[1], -ray.oMi[1]);
+                const float t1z = fmaf(s[2], ray.inv[2], -ray.oPi[2]), t2z = fmaf(s[5], ray.inv[2], -ray.oMi[2]);
+                const float tn = fmaxf(fmaxf(fminf(t1x, t2x), fminf(t1y, t2y)), fminf(t1z, t2z));
+                const float tf = fminf(fminf(fmaxf(t1x, t2x), fmaxf(t1y, t2y)), fmaxf(t1z, t2z)) * 1.0000005f;
+                const bool h = (tn <= tf) & (tf >= lo_f) & (tn <= pf);
+                hits |= h ? 1u << side : 0u;
+                tn_out[side] = h ? tn : INFINITY;
+            }
+            return hits;
+        };
         auto slot_ref = [](const float *f, uint32_t o) -> uint32_t {
             return o == 0 ? __float_as_uint(f[24]) : o == 1 ? __float_as_uint(f[25])
                  : o == 2 ? __float_as_uint(f[26]) : __float_as_uint(f[27]);
@@ -348,9 +367,9 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
         if (LANE) {
             // Per-lane walk: every lane follows its own ray through the tree
             // (vector loads of its node; stack in its own LDS column, a ring
-            // of kLaneStack entries).  A wave costs the longest path of its
-            // lanes rather than the union of their paths.
-            const uint32_t neg = (ray.d[0] < 0.0 ? 1u : 0u) | (ray.d[1] < 0.0 ? 2u : 0u) | (ray.d[2] < 0.0 ? 4u : 0u);
+            // of kLaneStack entries; children entered nearest box entry
+            // first).  A wave costs the longest path of its lanes rather than
+            // the union of their paths.
             uint32_t node = 0, top = 0, depth = 0, steps = 0;
             bool walking = active;
             while (__ballot(walking)) {
@@ -367,13 +386,23 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
                     }
                     const uint32_t kinds = __float_as_uint(f[31]);
                     queue_leaves(f, node, kinds, pr_f);
-                    const uint32_t boxes = box_hits(f, kinds, pr_f);
+                    float tn[4];
+                    const uint32_t boxes = box_hits_tn(f, kinds, pr_f, tn);
                     if (boxes) {
-                        const uint32_t order = slot_order(f, neg);
+                        // sort the slots by entry distance (misses last)
+                        uint32_t sl[4] = {0u, 1u, 2u, 3u};
+                        auto cx = [&](int i, int j) {
+                            const bool sw = tn[j] < tn[i];
+                            const float ti = tn[i], tj = tn[j];
+                            const uint32_t si = sl[i], sj = sl[j];
+                            tn[i] = sw ? tj : ti; tn[j] = sw ? ti : tj;
+                            sl[i] = sw ? sj : si; sl[j] = sw ? si : sj;
+                        };
+                        cx(0, 1); cx(2, 3); cx(0, 2); cx(1, 3); cx(1, 2);
                         uint32_t next = kEmpty;
 #pragma unroll
                         for (int i = 3; i >= 0; --i) {
-                            const uint32_t o = (order >> (2 * i)) & 3u;
+                            const uint32_t o = sl[i];
                             if (!((boxes >> o) & 1u)) continue;
                             if (next != kEmpty) {
                                 // a full ring drops its oldest entry; the packet walk
