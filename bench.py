@@ -37,6 +37,9 @@ def parse():
     p.add_argument("--no-bwd", action="store_true", help="skip the fwd+bwd measurement")
     p.add_argument("--batch-frames", type=int, default=64,
                    help="frames of the batched graph measurement (0 skips it)")
+    p.add_argument("--no-extra", action="store_true",
+                   help="skip the radius-scale sweep, the large-frame orbit and the copy bandwidth")
+    p.add_argument("--orbit-frames", type=int, default=30, help="frames of the large-frame orbit (0 skips it)")
     p.add_argument("--calib-copy-mib", type=int, default=0,
                    help="run one plain device copy of this many MiB first (scales the HBM byte counters)")
     return p.parse_args()
@@ -168,6 +171,9 @@ def main():
         "stages_ms": {"unproject": round(float(np.median(stage[:, 0])), 4),
                       "build": round(float(np.median(stage[:, 1])), 4),
                       "trace": round(float(np.median(stage[:, 2])), 4)},
+        "stages_p10_p90_ms": {k: [round(float(np.percentile(stage[:, i], 10)), 4),
+                                  round(float(np.percentile(stage[:, i], 90)), 4)]
+                              for i, k in enumerate(("unproject", "build", "trace"))},
         "trace_only_mrays_s": round(P / (trace_ms * 1e-3) / 1e6, 2),
         "mean_hits_per_ray": round(float(hit_stats.mean()), 3),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -178,6 +184,12 @@ def main():
                              "tile-ordering kernels), so achieved is a lower bound for the trace kernel alone"},
     }
 
+    if not args.no_extra:
+        result["copy_gbs"] = copy_bandwidth(torch, dev)
+        result["roofline"]["frac_of_copy"] = round(achieved / result["copy_gbs"], 5)
+        result["scale_sweep"] = scale_sweep(sp, torch, src, rgba, depth, dst, opts, max(args.steps, 20))
+        if args.orbit_frames > 0:
+            result["large_orbit"] = large_orbit(sp, torch, synth, dev, opts, args.orbit_frames)
     if not args.no_bwd:
         result["fwd_bwd"] = fwd_bwd(sp, torch, synth, dev, args.steps)
     if args.batch_frames > 0:
@@ -252,6 +264,87 @@ def batched(sp, torch, synth, dev, n_frames):
             "input_generation_s": round(gen_s, 1)}
 
 
+def _events(torch, fns):
+    """Device ms of each callable in `fns`, run back to back, events on the launch stream."""
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(fns) + 1)]
+    ev[0].record()
+    for i, fn in enumerate(fns):
+        fn()
+        ev[i + 1].record()
+    torch.cuda.synchronize()
+    return [ev[i].elapsed_time(ev[i + 1]) for i in range(len(fns))]
+
+
+def copy_bandwidth(torch, dev):
+    """Achievable HBM bandwidth: a 1 GiB device-to-device copy (2 GiB moved), best of 5."""
+    a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    best = min(_events(torch, [lambda: b.copy_(a)])[0] for _ in range(5))
+    del a, b
+    return round(2 * (1 << 30) / (best * 1e-3) / 1e9, 1)
+
+
+def scale_sweep(sp, torch, src, rgba, depth, dst, opts, reps):
+    """Client frame at radius scale 0.5, 1, 2: median, p10 and p90 of each stage."""
+    out = {}
+    for scale in (0.5, 1.0, 2.0):
+        sph = sp.unproject(src, rgba, depth, scale, True)
+        bvh = sp.build_bvh(sph)
+        img, hits = sp.trace(bvh, sph, dst, opts)
+        t = np.array([_events(torch, [lambda: sp.unproject(src, rgba, depth, scale, True, out=sph),
+                                      lambda: sp.build_bvh(sph, bvh),
+                                      lambda: sp.trace(bvh, sph, dst, opts, out=img, hits=hits)])
+                      for _ in range(reps)])
+        rec = {"spheres": sph.n()}
+        for i, k in enumerate(("unproject", "build", "trace")):
+            rec[k] = [round(float(np.percentile(t[:, i], q)), 4) for q in (50, 10, 90)]
+        rec["trace_mrays_s"] = round(dst.width * dst.height / (np.median(t[:, 2]) * 1e-3) / 1e6, 1)
+        out[f"s{scale}"] = rec
+    out["format"] = "stage: [median, p10, p90] ms"
+    return out
+
+
+def large_orbit(sp, torch, synth, dev, opts, frames):
+    """Large frame: 3840x2160 source -> 3840x2160 targets at yaw 15 + k deg, k = 0..frames-1;
+    unproject, rebuild and trace every frame."""
+    rgba_np, depth_np, src, dst0 = synth.source_image(synth.LARGE)
+    rgba = torch.from_numpy(rgba_np).to(dev)
+    depth = torch.from_numpy(depth_np).to(dev)
+    sph = sp.alloc_spheres(src.width * src.height, dev, half=True)
+    bvh = sp.alloc_bvh(sph.capacity, dev)
+    img = torch.empty((dst0.height, dst0.width, 4), dtype=torch.float32, device=dev)
+    hits = torch.empty((dst0.height, dst0.width), dtype=torch.int32, device=dev)
+    cams = [synth.rotated_camera(src, synth.LARGE.yaw + k, 0.0) for k in range(frames)]
+    sp.unproject(src, rgba, depth, 1.0, True, out=sph)
+    sp.build_bvh(sph, bvh)
+    sp.trace(bvh, sph, cams[0], opts, out=img, hits=hits)  # warm
+    t = np.array([_events(torch, [lambda: sp.unproject(src, rgba, depth, 1.0, True, out=sph),
+                                  lambda: sp.build_bvh(sph, bvh),
+                                  lambda c=c: sp.trace(bvh, sph, c, opts, out=img, hits=hits)]) for c in cams])
+    rays = dst0.width * dst0.height
+    frame = t.sum(axis=1)
+    res = {"workload": f"{src.width}x{src.height} source ({sph.n()} spheres) -> {dst0.width}x{dst0.height}, "
+                       f"yaw {synth.LARGE.yaw}+k deg, k = 0..{frames - 1}, rebuilt every frame",
+           "frame_ms_mean": round(float(frame.mean()), 4), "frame_mrays_s": round(rays / (frame.mean() * 1e-3) / 1e6, 1),
+           "trace_mrays_s": round(rays / (t[:, 2].mean() * 1e-3) / 1e6, 1)}
+    for i, k in enumerate(("unproject", "build", "trace")):
+        res[k + "_ms"] = [round(float(t[:, i].mean()), 4), round(float(t[:, i].min()), 4), round(float(t[:, i].max()), 4)]
+    res["format"] = "stage_ms: [mean, min, max] over the frames"
+    del sph, bvh, img, hits
+    return res
+
+
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(sph, dst, n):
     """The FP64 brute-force oracle on a bounded pixel sample of the same frame, on the host cores."""
     import oracle
@@ -272,6 +365,7 @@ def cpu_baseline(sph, dst, n):
         batch = int(min(max(batch, batch * (10.0 - dt) / max(step, 1e-3)), 100000)) if dt < 10.0 else batch
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": round(count / dt / 1e6, 6), "unit": "Mrays/s", "cores": cores, "kind": "oracle",
+            "nproc": os.cpu_count(), "cpu_model": _cpu_model(),
             "sample": f"{count} random pixels of the same 1920x1080 frame, all {n} spheres tested per ray "
                       f"(brute force, FP64), {dt:.1f} s"}
 
