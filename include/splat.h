@@ -111,9 +111,10 @@ typedef struct splat_bvh {
  *   schedule    order of the tiles: 0 super-tiles of 8x8 tiles dealt round
  *               robin to the XCDs, 1 one contiguous band per XCD, 2 heaviest
  *               first (tiles ranked by the sphere centres that project near
- *               them; needs the trace workspace); the result does not
- *               depend on it.  The batched launch ignores it (it has its own
- *               work queue)
+ *               them; needs the trace workspace; images of at most 8192
+ *               tiles, whose waves all fit on the GPU at once, run as 0);
+ *               the result does not depend on it.  The batched launch
+ *               ignores it (it has its own work queue)
  *   walk        SPLAT_WALK_LANE (each ray on its own path; default) or
  *               SPLAT_WALK_PACKET (a wavefront's rays as one packet); the
  *               result does not depend on it

@@ -188,6 +188,7 @@ struct BuildLayout {
 
 // Trace workspace of the heaviest-first tile order (schedule 2).
 constexpr int kOrderBuckets = 64;
+constexpr int kOrderMinTiles = 8192;  // fewer tiles: the order is skipped (schedule 0)
 
 struct TileOrderLayout {
     size_t counts, bucket, order, hist, total;

@@ -729,6 +729,9 @@ hipError_t launch_trace(const TraceArgs &args, bool backward, void *ws, hipStrea
     const int tiles_x = (a.cam.w + a.tile_w - 1) / a.tile_w;
     const int tiles_y = (a.cam.h + a.tile_h - 1) / a.tile_h;
     a.order = nullptr;
+    // with few tiles every wave is resident from the start and the order
+    // cannot pay for its kernels: schedule 0 then
+    if (a.schedule == 2 && tiles_x * tiles_y <= kOrderMinTiles) a.schedule = 0;
     if (a.schedule == 2) {
         const hipError_t e = launch_tile_order(a, tiles_x, tiles_y, ws, s, &a.order);
         if (e != hipSuccess) return e;

@@ -186,6 +186,31 @@ def test_column_along_the_view_ray(sp, stop):
     assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
 
 
+def test_heaviest_first_order_matches_other_schedules(sp):
+    """Above the tile threshold the heaviest-first order is computed and used;
+    the image and hit counts match schedules 0 and 1 bit for bit, for both
+    walks, and the oracle on sampled pixels."""
+    cr, col = synth.random_spheres(6000, seed=31, r_lo=0.004, r_hi=0.03)
+    cam = synth.rotated_camera(synth.source_camera(1024, 768), 9.0, 4.0)
+    assert (1024 // 8) * (768 // 8) > 8192
+    sph = sp.spheres_from_tensors(up(cr), up(col))
+    bvh = sp.build_bvh(sph)
+    ref = None
+    for walk in (0, 1):
+        for sched in (2, 0, 1):
+            img, hits = sp.trace(bvh, sph, cam, sp.TraceOptions(schedule=sched, walk=walk))
+            if ref is None:
+                ref = (img.clone(), hits.clone())
+            else:
+                assert torch.equal(img, ref[0]) and torch.equal(hits, ref[1]), (walk, sched)
+    pix = np.random.default_rng(3).integers(0, cam.width * cam.height, 3000)
+    g = ref[0].cpu().numpy().reshape(-1, 4)[pix]
+    n = ref[1].cpu().numpy().reshape(-1)[pix]
+    st = compare(g, n, oracle.render(cr, col, cam, pixels=pix))
+    assert_parity(st, exempt_frac=None, context="heaviest first")
+    assert st["hits_checked"] > 300
+
+
 def test_result_independent_of_kbuf_and_tile(sp):
     """The hit buffer size and the tile shape change the schedule, never the image."""
     cr, col = synth.random_spheres(400, seed=11, r_lo=0.03, r_hi=0.15)
