@@ -13,6 +13,8 @@ over pixels), brute force: every ray against every sphere, hits sorted by
                  composited front to back with an alpha stop
 * ``grad``       analytic gradient of a per-pixel loss through ``render``
 * ``half_bits``  double -> binary16 with round-to-nearest-even
+* ``raymarch``   the server stage before the path (Sec. 3.1): volume ray
+                 marcher writing premultiplied colour and a representative depth
 """
 from __future__ import annotations
 
@@ -86,6 +88,12 @@ def _load():
         lib.orc_sphere_test.restype = ctypes.c_int
         lib.orc_pixels_near.argtypes = [ctypes.POINTER(_Cam), _P, ctypes.c_double, _P, ctypes.c_int64]
         lib.orc_pixels_near.restype = ctypes.c_int64
+        lib.orc_volume_sample.argtypes = [_P, ctypes.c_int32, _P]
+        lib.orc_volume_sample.restype = ctypes.c_double
+        lib.orc_raymarch.argtypes = [_P, ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.POINTER(_Cam),
+                                     ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double, _P,
+                                     ctypes.c_int64, _P]
+        lib.orc_raymarch.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -194,3 +202,38 @@ def pixels_near(cam, centre, radius: float) -> np.ndarray:
     out = np.zeros(cap, dtype=np.int64)
     n = _load().orc_pixels_near(ctypes.byref(c), ctr.ctypes.data, float(radius), out.ctypes.data, cap)
     return out[:n].copy()
+
+
+# server stage defaults: the workloads' transfer and depth rules
+MARCH_STEP = 0.5          # voxels between samples
+MARCH_ALPHA_SCALE = 0.05  # sample alpha = clamp(0.05 v, 0, 1)
+MARCH_DEPTH_ALPHA = 0.5   # depth = first sample at which A >= 0.5
+MARCH_STOP_ALPHA = 0.999  # stop after the sample at which A >= 0.999
+
+
+def volume_sample(vol: np.ndarray, p) -> float:
+    """Trilinear (clamp-to-edge) value of vol [n][n][n] (z, y, x) at normalised position p."""
+    v = np.ascontiguousarray(vol, dtype=np.float32)
+    q = np.ascontiguousarray(p, dtype=np.float64)
+    return float(_load().orc_volume_sample(v.ctypes.data, int(v.shape[0]), q.ctypes.data))
+
+
+def raymarch(vol: np.ndarray, box_lo: float, box_size: float, cam, pixels=None, step: float = MARCH_STEP,
+             alpha_scale: float = MARCH_ALPHA_SCALE, depth_alpha: float = MARCH_DEPTH_ALPHA,
+             stop_alpha: float = MARCH_STOP_ALPHA) -> dict:
+    """Server ray marcher in double precision.  Returns {"rgba": [k][4] premultiplied, "depth": [k]}
+    (float64) for all pixels (row-major) or the given pixel indices."""
+    v = np.ascontiguousarray(vol, dtype=np.float32)
+    n = int(v.shape[0])
+    assert v.shape == (n, n, n)
+    c = _cam(cam)
+    if pixels is None:
+        count, pix = int(cam.width) * int(cam.height), None
+    else:
+        pix = np.ascontiguousarray(pixels, dtype=np.int64)
+        count = len(pix)
+    out = np.zeros((count, 5), dtype=np.float64)
+    _load().orc_raymarch(v.ctypes.data, n, float(box_lo), float(box_size), ctypes.byref(c), float(step),
+                         float(alpha_scale), float(depth_alpha), float(stop_alpha),
+                         None if pix is None else pix.ctypes.data, count, out.ctypes.data)
+    return {"rgba": out[:, :4].copy(), "depth": out[:, 4].copy()}

@@ -20,6 +20,9 @@
  *   orc_pixels_near lists the pixels whose ray passes near a point.
  *   orc_sphere_test one ray against one sphere (exposed for closed-form pins).
  *   orc_half_bits   double -> IEEE binary16, round to nearest even.
+ *   orc_raymarch    the server stage before the path (Sec. 3.1): a volume
+ *                   ray marcher writing colour and a representative depth;
+ *   orc_volume_sample  its trilinear reconstruction (exposed for pins).
  *
  * Readings of the paper (it specifies none of these):
  *   - camera: pinhole, ray through pixel centre (x+1/2, y+1/2), row 0 at top,
@@ -484,4 +487,117 @@ int64_t orc_pixels_near(const orc_camera *cam, const double centre[3], double ra
         }
     }
     return n;
+}
+
+/* ------------------------------------------------------------------ server
+ * The server stage before the client path (Sec. 3.1: a ray marcher renders
+ * the volume and writes, per pixel, the composited colour and one
+ * representative depth t).  The paper names only a standard ray marcher and
+ * a depth heuristic from earlier work; the rules written out here are the
+ * reading this build uses:
+ *   - volume v[z][y][x] of n^3 floats filling the cube [lo, lo + size]^3,
+ *     voxel (i, j, k) centred at lo + (i + 1/2, j + 1/2, k + 1/2) size / n;
+ *     reconstruction is trilinear with clamp-to-edge;
+ *   - the pixel ray (as above) meets the cube over [t_in, t_out], t_in >= 0;
+ *     samples at t_j = t_in + (j + 1/2) dt while t_j < t_out, with
+ *     dt = step * size / n (step in voxels);
+ *   - transfer: u = clamp(v, 0, 1), colour (u, 4u(1 - u), 1 - u), sample
+ *     alpha s = clamp(alpha_scale v, 0, 1);
+ *   - front to back: w = (1 - A) s, C += w colour, A += w; the depth is the
+ *     first t_j at which A >= depth_alpha (infinite if never); marching
+ *     stops after the sample at which A >= stop_alpha;
+ *   - output: premultiplied (C, A) and depth, as float.
+ */
+
+/* Trilinear value at normalised position p in [0,1]^3 (clamp to edge):
+ * the sum over the 8 surrounding voxel centres of value x weight. */
+double orc_volume_sample(const float *vol, int32_t n, const double p[3])
+{
+    int64_t base[3];
+    double frac[3];
+    for (int a = 0; a < 3; ++a) {
+        const double g = p[a] * (double)n - 0.5;  /* position in voxel-centre units */
+        const double fl = floor(g);
+        base[a] = (int64_t)fl;
+        frac[a] = g - fl;
+    }
+    double sum = 0.0;
+    for (int corner = 0; corner < 8; ++corner) {
+        int64_t idx[3];
+        double w = 1.0;
+        for (int a = 0; a < 3; ++a) {
+            const int up = (corner >> a) & 1;
+            int64_t i = base[a] + up;
+            if (i < 0) i = 0;
+            if (i > n - 1) i = n - 1;
+            idx[a] = i;
+            w *= up ? frac[a] : 1.0 - frac[a];
+        }
+        sum += w * (double)vol[(idx[2] * n + idx[1]) * n + idx[0]];
+    }
+    return sum;
+}
+
+static double orc_clamp(double v, double lo, double hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+/* One pixel of the marcher; returns the number of samples taken. */
+static int64_t orc_march_pixel(const float *vol, int32_t n, double lo, double size, const orc_camera *cam,
+                               int64_t x, int64_t y, double step, double alpha_scale, double depth_alpha,
+                               double stop_alpha, double out[5])
+{
+    double d[3];
+    orc_ray(cam, x, y, d);
+    double t_in = 0.0, t_out = INFINITY;
+    for (int a = 0; a < 3; ++a) {
+        const double o = cam->eye[a];
+        if (d[a] == 0.0) {
+            if (o < lo || o > lo + size) t_out = -1.0;  /* parallel to the slab and outside it */
+            continue;
+        }
+        double ta = (lo - o) / d[a], tb = (lo + size - o) / d[a];
+        if (ta > tb) { const double s = ta; ta = tb; tb = s; }
+        if (ta > t_in) t_in = ta;
+        if (tb < t_out) t_out = tb;
+    }
+    double C[3] = {0.0, 0.0, 0.0}, A = 0.0, depth = INFINITY;
+    int64_t taken = 0;
+    if (t_in < t_out) {
+        const double dt = step * size / (double)n;
+        for (int64_t j = 0;; ++j) {
+            const double t = t_in + ((double)j + 0.5) * dt;
+            if (!(t < t_out)) break;
+            double p[3];
+            for (int a = 0; a < 3; ++a) p[a] = (cam->eye[a] + t * d[a] - lo) / size;
+            const double v = orc_volume_sample(vol, n, p);
+            const double u = orc_clamp(v, 0.0, 1.0);
+            const double s = orc_clamp(alpha_scale * v, 0.0, 1.0);
+            const double w = (1.0 - A) * s;
+            C[0] += w * u;
+            C[1] += w * (4.0 * u * (1.0 - u));
+            C[2] += w * (1.0 - u);
+            A += w;
+            ++taken;
+            if (depth == INFINITY && A >= depth_alpha) depth = t;
+            if (A >= stop_alpha) break;
+        }
+    }
+    out[0] = C[0]; out[1] = C[1]; out[2] = C[2]; out[3] = A; out[4] = depth;
+    return taken;
+}
+
+/* The marcher over all pixels (pixels == NULL) or a list of pixel indices;
+ * out is double [count][5]: C (3), A, depth.  Returns 0. */
+int orc_raymarch(const float *vol, int32_t n, double lo, double size, const orc_camera *cam, double step,
+                 double alpha_scale, double depth_alpha, double stop_alpha, const int64_t *pixels, int64_t count,
+                 double *out)
+{
+    const int64_t W = cam->width;
+    const int64_t total = pixels ? count : W * (int64_t)cam->height;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < total; ++k) {
+        const int64_t pix = pixels ? pixels[k] : k;
+        orc_march_pixel(vol, n, lo, size, cam, pix % W, pix / W, step, alpha_scale, depth_alpha, stop_alpha,
+                        out + 5 * k);
+    }
+    return 0;
 }

@@ -9,6 +9,7 @@ import pytest
 
 import oracle
 import test_oracle_grad_pins as G
+import test_oracle_march_pins as M
 import test_oracle_pins as P
 
 SRC = open(os.path.join(os.path.dirname(oracle.__file__), "oracle.c")).read()
@@ -39,6 +40,12 @@ MUTANTS = [
     ("half truncates", "double q = rint(ldexp(a, 10 - E));", "double q = floor(ldexp(a, 10 - E));"),
     ("no colour clamp", "col[k] = kc < 0.0 ? 0.0 : (kc > 1.0 ? 1.0 : kc);", "col[k] = kc;"),
     ("premultiplied colour kept", "double kc = (double)rgba[4 * i + k] / A;", "double kc = (double)rgba[4 * i + k];"),
+    ("march samples at interval starts", "const double t = t_in + ((double)j + 0.5) * dt;",
+     "const double t = t_in + (double)j * dt;"),
+    ("march weight without transmittance", "const double w = (1.0 - A) * s;", "const double w = s;"),
+    ("trilinear weights swapped", "w *= up ? frac[a] : 1.0 - frac[a];", "w *= up ? 1.0 - frac[a] : frac[a];"),
+    ("march colour ramp", "C[1] += w * (4.0 * u * (1.0 - u));", "C[1] += w * (u * (1.0 - u));"),
+    ("march never stops", "if (A >= stop_alpha) break;", "if (A > 2.0) break;"),
 ]
 
 # pins run against each mutant (parametrised pins with their cases)
@@ -61,6 +68,12 @@ PINS = [
     G.test_soft_alpha_closed_form,
     G.test_two_sphere_constant_alpha_derivatives,
     lambda: G.test_analytic_gradient_matches_central_differences(oracle.MODE_SOFT, 0.99),
+    lambda: [M.test_constant_volume_closed_form(v) for v in (0.6, 1.7, 12.0)],
+    M.test_eye_inside_the_volume,
+    M.test_linear_ramp_is_reproduced_and_clamped,
+    M.test_trilinear_weights_on_a_single_voxel_pulse,
+    M.test_ray_missing_the_cube_is_background,
+    M.test_matches_the_input_generators_caster,
 ]
 
 
