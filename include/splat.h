@@ -160,6 +160,44 @@ size_t splat_workspace_bytes(int32_t op, uint32_t capacity, int32_t width, int32
 size_t splat_bvh_bytes(uint32_t capacity);
 
 /*
+ * Volume for the server stage: n^3 floats v[z][y][x] (x fastest) filling the
+ * cube [box_lo, box_lo + box_size]^3, voxel (i, j, k) centred at
+ * box_lo + (i + 1/2, j + 1/2, k + 1/2) box_size / n.
+ */
+typedef struct splat_volume {
+    const float *data;             /* device, n^3 floats */
+    int32_t n;                     /* 1..1024 */
+    double box_lo, box_size;       /* box_size > 0 */
+} splat_volume;
+
+/*
+ * Server ray-marcher options (0 fields take the defaults in brackets).
+ *   step         voxels between samples, >= 0.01 [0.5]
+ *   alpha_scale  sample alpha = clamp(alpha_scale v, 0, 1) [0.05]
+ *   depth_alpha  the depth is the first sample at which A >= depth_alpha [0.5]
+ *   stop_alpha   marching stops after the sample at which A >= stop_alpha [0.999]
+ */
+typedef struct splat_march_opts {
+    double step, alpha_scale, depth_alpha, stop_alpha;
+} splat_march_opts;
+
+/*
+ * Server stage before the client path (Sec. 3.1: the server ray-marches the
+ * volume and writes colour and one representative depth per pixel).  For
+ * every pixel of `cam`: samples at t_j = t_in + (j + 1/2) dt along the pixel
+ * ray inside the cube (t_in >= 0, dt = step box_size / n), trilinear with
+ * clamp to edge; u = clamp(v, 0, 1), colour (u, 4u(1 - u), 1 - u), sample
+ * alpha s = clamp(alpha_scale v, 0, 1); front to back, w = (1 - A) s,
+ * C += w colour, A += w.  Positions and compositing in double.
+ *   out_rgba   device float [height][width][4]: premultiplied (C, A), the
+ *              input of splat_unproject
+ *   out_depth  device float [height][width]: the depth t, +inf if A never
+ *              reaches depth_alpha (no sample there)
+ */
+int splat_raymarch(const splat_volume *vol, const splat_camera *cam, const splat_march_opts *opts, float *out_rgba,
+                   float *out_depth, void *stream);
+
+/*
  * Unprojection (Sec. 3.1, Eq. 1).  For every source pixel whose depth t is
  * finite and positive and whose alpha A is positive: centre p = o + d t in
  * double (d the unit pixel-centre ray of `src`), radius

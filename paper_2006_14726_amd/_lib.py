@@ -14,8 +14,8 @@ SPLAT_WALK_LANE, SPLAT_WALK_PACKET = 0, 1
 SPLAT_OP_UNPROJECT, SPLAT_OP_BUILD, SPLAT_OP_TRACE, SPLAT_OP_BACKWARD, SPLAT_OP_BATCHED = range(5)
 
 # every symbol include/splat.h declares
-EXPORTS = ["splat_workspace_bytes", "splat_bvh_bytes", "splat_unproject", "splat_build_bvh", "splat_trace",
-           "splat_trace_backward", "splat_trace_batched", "splat_last_error", "splat_version"]
+EXPORTS = ["splat_workspace_bytes", "splat_bvh_bytes", "splat_raymarch", "splat_unproject", "splat_build_bvh",
+           "splat_trace", "splat_trace_backward", "splat_trace_batched", "splat_last_error", "splat_version"]
 
 _P = ctypes.c_void_p
 
@@ -39,6 +39,15 @@ class splat_trace_opts(ctypes.Structure):
     _fields_ = [("alpha_stop", ctypes.c_float), ("mode", ctypes.c_int32), ("t_max", ctypes.c_double),
                 ("kbuf", ctypes.c_int32), ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
                 ("schedule", ctypes.c_int32), ("walk", ctypes.c_int32)]
+
+
+class splat_volume(ctypes.Structure):
+    _fields_ = [("data", _P), ("n", ctypes.c_int32), ("box_lo", ctypes.c_double), ("box_size", ctypes.c_double)]
+
+
+class splat_march_opts(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_double), ("alpha_scale", ctypes.c_double), ("depth_alpha", ctypes.c_double),
+                ("stop_alpha", ctypes.c_double)]
 
 
 class splat_grads(ctypes.Structure):
@@ -86,7 +95,9 @@ def load() -> ctypes.CDLL:
         lib.splat_last_error.restype = ctypes.c_char_p
         lib.splat_version.argtypes = []
         lib.splat_version.restype = ctypes.c_int
-        for name in ("splat_unproject", "splat_build_bvh", "splat_trace", "splat_trace_backward",
+        lib.splat_raymarch.argtypes = [ctypes.POINTER(splat_volume), ctypes.POINTER(splat_camera),
+                                       ctypes.POINTER(splat_march_opts), _P, _P, _P]
+        for name in ("splat_raymarch", "splat_unproject", "splat_build_bvh", "splat_trace", "splat_trace_backward",
                      "splat_trace_batched"):
             getattr(lib, name).restype = ctypes.c_int
         _lib = lib

@@ -150,6 +150,34 @@ size_t splat_workspace_bytes(int32_t op, uint32_t capacity, int32_t width, int32
     }
 }
 
+int splat_raymarch(const splat_volume *vol, const splat_camera *cam, const splat_march_opts *opts, float *out_rgba,
+                   float *out_depth, void *stream)
+{
+    int rc;
+    if (!vol || !vol->data) return fail(SPLAT_EINVAL, "volume is NULL");
+    if (vol->n < 1 || vol->n > 1024) return fail(SPLAT_EINVAL, "volume n %d not in 1..1024", vol->n);
+    if (!std::isfinite(vol->box_lo) || !std::isfinite(vol->box_size) || !(vol->box_size > 0))
+        return fail(SPLAT_EINVAL, "volume box must be finite with box_size > 0");
+    if ((rc = check_camera(cam, "source"))) return rc;
+    if (!out_rgba || !out_depth) return fail(SPLAT_EINVAL, "out_rgba/out_depth is NULL");
+    splat_march_opts o = {0.5, 0.05, 0.5, 0.999};
+    if (opts) {
+        if (opts->step != 0) o.step = opts->step;
+        if (opts->alpha_scale != 0) o.alpha_scale = opts->alpha_scale;
+        if (opts->depth_alpha != 0) o.depth_alpha = opts->depth_alpha;
+        if (opts->stop_alpha != 0) o.stop_alpha = opts->stop_alpha;
+    }
+    // the sample count per ray is at most sqrt(3) n / step
+    if (!std::isfinite(o.step) || o.step < 0.01) return fail(SPLAT_EINVAL, "march step must be >= 0.01 voxel");
+    if (!std::isfinite(o.alpha_scale) || o.alpha_scale < 0 || !std::isfinite(o.depth_alpha) ||
+        !std::isfinite(o.stop_alpha))
+        return fail(SPLAT_EINVAL, "march alpha options must be finite, alpha_scale >= 0");
+    if ((rc = check_device())) return rc;
+    return hip_status(launch_raymarch(vol->data, vol->n, vol->box_lo, vol->box_size, make_cam(*cam), o, out_rgba,
+                                      out_depth, static_cast<hipStream_t>(stream)),
+                      "raymarch launch");
+}
+
 int splat_unproject(const splat_camera *src, const float *rgba_premul, const float *depth, float radius_scale,
                     const splat_spheres *out, void *ws, size_t ws_bytes, void *stream)
 {

@@ -28,6 +28,9 @@ struct TraceArgs {
     float *d_rgb, *d_alpha, *d_radius, *d_centre;
 };
 
+hipError_t launch_raymarch(const float *vol, int32_t n, double lo, double size, const Cam &cam,
+                           const splat_march_opts &o, float *out_rgba, float *out_depth, hipStream_t s);
+
 hipError_t launch_unproject(const Cam &cam, const float *rgba, const float *depth, float radius_scale,
                             const splat_spheres &out, void *ws, hipStream_t s);
 

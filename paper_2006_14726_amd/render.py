@@ -96,6 +96,36 @@ def alloc_spheres(capacity: int, device, half: bool = True) -> Spheres:
                    torch.empty((capacity,), dtype=torch.int32, device=device))
 
 
+def raymarch(volume: torch.Tensor, box_lo: float, box_size: float, cam, step: float = 0.5,
+             alpha_scale: float = 0.05, depth_alpha: float = 0.5, stop_alpha: float = 0.999,
+             out_rgba: torch.Tensor | None = None, out_depth: torch.Tensor | None = None):
+    """Server stage (splat_raymarch): ray-march the float32 volume [n, n, n] (z, y, x) filling the cube
+    [box_lo, box_lo + box_size]^3.  Returns (premultiplied rgba [H, W, 4], depth [H, W]), the input of
+    `unproject`."""
+    _require_cuda(volume, "volume", torch.float32)
+    n = int(volume.shape[0])
+    if tuple(volume.shape) != (n, n, n):
+        raise ValueError("volume must be [n, n, n]")
+    H, W = int(cam.height), int(cam.width)
+    if out_rgba is None:
+        out_rgba = torch.empty((H, W, 4), dtype=torch.float32, device=volume.device)
+    if out_depth is None:
+        out_depth = torch.empty((H, W), dtype=torch.float32, device=volume.device)
+    _require_cuda(out_rgba, "out_rgba", torch.float32)
+    _require_cuda(out_depth, "out_depth", torch.float32)
+    if tuple(out_rgba.shape) != (H, W, 4) or tuple(out_depth.shape) != (H, W):
+        raise ValueError(f"out_rgba must be [{H}, {W}, 4] and out_depth [{H}, {W}]")
+    v = _lib.splat_volume()
+    v.data, v.n, v.box_lo, v.box_size = volume.data_ptr(), n, float(box_lo), float(box_size)
+    o = _lib.splat_march_opts()
+    o.step, o.alpha_scale, o.depth_alpha, o.stop_alpha = float(step), float(alpha_scale), float(depth_alpha), \
+        float(stop_alpha)
+    c = _lib.camera_struct(cam)
+    _lib.check(_lib.load().splat_raymarch(ctypes.byref(v), ctypes.byref(c), ctypes.byref(o), _ptr(out_rgba),
+                                          _ptr(out_depth), _stream()))
+    return out_rgba, out_depth
+
+
 def unproject(src_cam, rgba: torch.Tensor, depth: torch.Tensor, radius_scale: float = 1.0, half: bool = True,
               out: Spheres | None = None) -> Spheres:
     """Eq. 1 unprojection of a premultiplied RGBA + depth image into spheres (splat_unproject)."""

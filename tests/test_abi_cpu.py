@@ -44,6 +44,8 @@ def test_struct_layouts_match_the_header():
     assert ctypes.sizeof(_lib.splat_camera) == 13 * 8 + 2 * 4
     assert ctypes.sizeof(_lib.splat_spheres) == 8 + 8 + 4 + 4 + 8 + 8 + 8
     assert ctypes.sizeof(_lib.splat_trace_opts) == 40
+    assert ctypes.sizeof(_lib.splat_volume) == 32
+    assert ctypes.sizeof(_lib.splat_march_opts) == 32
     assert ctypes.sizeof(_lib.splat_batch_job) == 3 * 8 + 2 * 4 + 112 + 2 * 8
 
 
@@ -130,3 +132,23 @@ def test_no_device_is_reported_not_crashed():
     fake = ctypes.c_void_p(4096)
     code, msg = _err(lib.splat_unproject(ctypes.byref(cam), fake, fake, 1.0, ctypes.byref(sph), fake, 1 << 20, None))
     assert code == _lib.SPLAT_ENODEV, msg
+
+
+def test_raymarch_option_validation():
+    lib = _lib.load()
+    cam = _lib.camera_struct(_Cam())
+    out = ctypes.c_void_p(4096)
+    for vol_kw, opt_kw, code in [({"n": 0}, {}, _lib.SPLAT_EINVAL), ({"n": 1025}, {}, _lib.SPLAT_EINVAL),
+                                 ({"box_size": 0.0}, {}, _lib.SPLAT_EINVAL),
+                                 ({"box_lo": math.nan}, {}, _lib.SPLAT_EINVAL),
+                                 ({}, {"step": 0.001}, _lib.SPLAT_EINVAL),
+                                 ({}, {"alpha_scale": -1.0}, _lib.SPLAT_EINVAL)]:
+        v = _lib.splat_volume()
+        v.data, v.n, v.box_lo, v.box_size = 4096, 8, -0.25, 1.5
+        for k, val in vol_kw.items():
+            setattr(v, k, val)
+        o = _lib.splat_march_opts()
+        for k, val in opt_kw.items():
+            setattr(o, k, val)
+        got, msg = _err(lib.splat_raymarch(ctypes.byref(v), ctypes.byref(cam), ctypes.byref(o), out, out, None))
+        assert got == code, (vol_kw, opt_kw, msg)
