@@ -199,6 +199,7 @@ def main():
         result["scale_sweep"] = scale_sweep(sp, torch, src, rgba, depth, dst, opts, max(args.steps, 20))
         if args.orbit_frames > 0:
             result["large_orbit"] = large_orbit(sp, torch, synth, dev, opts, args.orbit_frames)
+        result["server_stage"] = server_stage(sp, torch, synth, dev, src, dst, opts, max(args.steps, 10))
     if not args.no_bwd:
         result["fwd_bwd"] = fwd_bwd(sp, torch, synth, dev, args.steps)
     if args.batch_frames > 0:
@@ -345,6 +346,28 @@ def large_orbit(sp, torch, synth, dev, opts, frames):
     res["format"] = "stage_ms: [mean, min, max] over the frames"
     del sph, bvh, img, hits
     return res
+
+
+def server_stage(sp, torch, synth, dev, src, dst, opts, reps):
+    """The stage before the path on the GPU: ray-march the client frame's 256^3 volume into the 1024^2
+    source image, then the whole server + client frame (march, unproject, build, trace)."""
+    vol = torch.from_numpy(synth.volume_of(synth.CLIENT_FRAME)).to(dev)
+    rgba, depth = sp.raymarch(vol, synth.BOX_LO, synth.BOX_SIZE, src)
+    sph = sp.unproject(src, rgba, depth, 1.0, True)
+    bvh = sp.build_bvh(sph)
+    img, hits = sp.trace(bvh, sph, dst, opts)
+    t = np.array([_events(torch, [lambda: sp.raymarch(vol, synth.BOX_LO, synth.BOX_SIZE, src, out_rgba=rgba,
+                                                      out_depth=depth),
+                                  lambda: sp.unproject(src, rgba, depth, 1.0, True, out=sph),
+                                  lambda: sp.build_bvh(sph, bvh),
+                                  lambda: sp.trace(bvh, sph, dst, opts, out=img, hits=hits)]) for _ in range(reps)])
+    med = np.median(t, axis=0)
+    return {"workload": f"256^3 volume -> {src.width}x{src.height} source ({sph.n()} spheres) -> "
+                        f"{dst.width}x{dst.height} target",
+            "march_ms": round(float(med[0]), 4),
+            "march_mrays_s": round(src.width * src.height / (med[0] * 1e-3) / 1e6, 1),
+            "frame_ms": round(float(t.sum(axis=1).mean()), 4),
+            "stages_ms": {k: round(float(v), 4) for k, v in zip(("march", "unproject", "build", "trace"), med)}}
 
 
 def _cpu_model() -> str:
