@@ -15,6 +15,8 @@ over pixels), brute force: every ray against every sphere, hits sorted by
 * ``half_bits``  double -> binary16 with round-to-nearest-even
 * ``raymarch``   the server stage before the path (Sec. 3.1): volume ray
                  marcher writing premultiplied colour and a representative depth
+* ``encode``, ``decode``  the wire format: 64 bits per sample (quantised
+                 position + radius), 32 bits per colour (Sec. 3.1, Sec. 5)
 """
 from __future__ import annotations
 
@@ -94,6 +96,14 @@ def _load():
                                      ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double, _P,
                                      ctypes.c_int64, _P]
         lib.orc_raymarch.restype = ctypes.c_int
+        lib.orc_encode_position.argtypes = [_P, ctypes.c_double, _P, ctypes.c_double, ctypes.c_double]
+        lib.orc_encode_position.restype = ctypes.c_uint64
+        lib.orc_encode_colour.argtypes = [_P]
+        lib.orc_encode_colour.restype = ctypes.c_uint32
+        lib.orc_encode.argtypes = [_P, _P, ctypes.c_int64, _P, ctypes.c_double, ctypes.c_double, _P, _P]
+        lib.orc_encode.restype = None
+        lib.orc_decode.argtypes = [_P, _P, ctypes.c_int64, _P, ctypes.c_double, ctypes.c_double, _P, _P]
+        lib.orc_decode.restype = None
         _lib = lib
     return _lib
 
@@ -237,3 +247,44 @@ def raymarch(vol: np.ndarray, box_lo: float, box_size: float, cam, pixels=None, 
                          float(alpha_scale), float(depth_alpha), float(stop_alpha),
                          None if pix is None else pix.ctypes.data, count, out.ctypes.data)
     return {"rgba": out[:, :4].copy(), "depth": out[:, 4].copy()}
+
+
+CODEC_POS_BITS = 18      # per axis
+CODEC_R_STEPS = 64       # radius codes per octave around r_unit (code 512 = r_unit)
+
+
+def encode(centre_radius: np.ndarray, rgba: np.ndarray, box_lo, box_size: float, r_unit: float):
+    """Spheres -> (uint64 [n] position+radius words, uint32 [n] RGBA8 colours)."""
+    cr = np.ascontiguousarray(centre_radius, dtype=np.float32).reshape(-1, 4)
+    col = np.ascontiguousarray(rgba, dtype=np.float64).reshape(-1, 4)
+    n = cr.shape[0]
+    lo = np.ascontiguousarray(np.broadcast_to(np.asarray(box_lo, dtype=np.float64), (3,)))
+    pos = np.zeros(n, dtype=np.uint64)
+    out = np.zeros(n, dtype=np.uint32)
+    _load().orc_encode(cr.ctypes.data, col.ctypes.data, n, lo.ctypes.data, float(box_size), float(r_unit),
+                       pos.ctypes.data, out.ctypes.data)
+    return pos, out
+
+
+def decode(pos: np.ndarray, col: np.ndarray, box_lo, box_size: float, r_unit: float):
+    """(words, colours) -> (centre_radius float32 [n][4], rgba float32 [n][4])."""
+    p = np.ascontiguousarray(pos, dtype=np.uint64)
+    c = np.ascontiguousarray(col, dtype=np.uint32)
+    n = p.shape[0]
+    lo = np.ascontiguousarray(np.broadcast_to(np.asarray(box_lo, dtype=np.float64), (3,)))
+    cr = np.zeros((n, 4), dtype=np.float32)
+    rgba = np.zeros((n, 4), dtype=np.float32)
+    _load().orc_decode(p.ctypes.data, c.ctypes.data, n, lo.ctypes.data, float(box_size), float(r_unit),
+                       cr.ctypes.data, rgba.ctypes.data)
+    return cr, rgba
+
+
+def encode_position(c, r: float, box_lo, box_size: float, r_unit: float) -> int:
+    cc = np.ascontiguousarray(c, dtype=np.float64)
+    lo = np.ascontiguousarray(np.broadcast_to(np.asarray(box_lo, dtype=np.float64), (3,)))
+    return int(_load().orc_encode_position(cc.ctypes.data, float(r), lo.ctypes.data, float(box_size), float(r_unit)))
+
+
+def encode_colour(k) -> int:
+    kk = np.ascontiguousarray(k, dtype=np.float64)
+    return int(_load().orc_encode_colour(kk.ctypes.data))

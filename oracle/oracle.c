@@ -23,6 +23,8 @@
  *   orc_raymarch    the server stage before the path (Sec. 3.1): a volume
  *                   ray marcher writing colour and a representative depth;
  *   orc_volume_sample  its trilinear reconstruction (exposed for pins).
+ *   orc_encode, orc_decode  the 64-bit sample + 32-bit colour wire format
+ *                   (Sec. 3.1, Sec. 5), with per-value helpers for pins.
  *
  * Readings of the paper (it specifies none of these):
  *   - camera: pinhole, ray through pixel centre (x+1/2, y+1/2), row 0 at top,
@@ -600,4 +602,83 @@ int orc_raymarch(const float *vol, int32_t n, double lo, double size, const orc_
                         out + 5 * k);
     }
     return 0;
+}
+
+/* ------------------------------------------------------------------ codec
+ * The sample codec of the wire format (Sec. 3.1: each object-space sample's
+ * quantised coordinate is packed with its radius into 64 bits; Sec. 5: 32
+ * bits per colour).  The paper leaves the bit split open; the reading here:
+ *   - position: 18 bits per axis, q = clamp(floor((x - lo) / size 2^18),
+ *     0, 2^18 - 1), decoded at the cell centre lo + (q + 1/2) size / 2^18;
+ *   - radius: 10 bits, c = clamp(round_half_up(64 log2(r / r_unit)) + 512,
+ *     0, 1023), decoded as r_unit 2^((c - 512) / 64);
+ *   - word = qx | qy << 18 | qz << 36 | c << 54;
+ *   - colour: 8 bits per straight channel and alpha,
+ *     b = floor(clamp(v, 0, 1) 255 + 1/2), decoded as b / 255, byte 0 = red.
+ */
+
+static uint64_t orc_quant(double v, double lo, double size, int bits)
+{
+    const double cells = (double)((uint64_t)1 << bits);
+    double q = floor((v - lo) / size * cells);
+    if (!(q >= 0.0)) q = 0.0;  /* also NaN */
+    if (q > cells - 1.0) q = cells - 1.0;
+    return (uint64_t)q;
+}
+
+uint64_t orc_encode_position(const double c[3], double r, const double lo[3], double size, double r_unit)
+{
+    uint64_t w = 0;
+    for (int a = 0; a < 3; ++a) w |= orc_quant(c[a], lo[a], size, 18) << (18 * a);
+    double code = floor(64.0 * log2(r / r_unit) + 0.5) + 512.0;
+    if (!(code >= 0.0)) code = 0.0;
+    if (code > 1023.0) code = 1023.0;
+    return w | ((uint64_t)code << 54);
+}
+
+void orc_decode_position(uint64_t w, const double lo[3], double size, double r_unit, double c[3], double *r)
+{
+    const double step = size / (double)((uint64_t)1 << 18);
+    for (int a = 0; a < 3; ++a) c[a] = lo[a] + ((double)((w >> (18 * a)) & 0x3ffffu) + 0.5) * step;
+    *r = r_unit * exp2(((double)(w >> 54) - 512.0) / 64.0);
+}
+
+uint32_t orc_encode_colour(const double k[4])
+{
+    uint32_t w = 0;
+    for (int ch = 0; ch < 4; ++ch) {
+        const double v = k[ch] < 0.0 ? 0.0 : (k[ch] > 1.0 ? 1.0 : (k[ch] == k[ch] ? k[ch] : 0.0));
+        w |= (uint32_t)floor(v * 255.0 + 0.5) << (8 * ch);
+    }
+    return w;
+}
+
+void orc_decode_colour(uint32_t w, double k[4])
+{
+    for (int ch = 0; ch < 4; ++ch) k[ch] = (double)((w >> (8 * ch)) & 0xffu) / 255.0;
+}
+
+/* Whole arrays: spheres (n x [c, r] and n x straight rgba) -> words, and back
+ * (the decoded centre and radius rounded to float, the colour to float). */
+void orc_encode(const float *centre_radius, const double *rgba, int64_t n, const double lo[3], double size,
+                double r_unit, uint64_t *pos, uint32_t *col)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        const double c[3] = {centre_radius[4 * i], centre_radius[4 * i + 1], centre_radius[4 * i + 2]};
+        pos[i] = orc_encode_position(c, (double)centre_radius[4 * i + 3], lo, size, r_unit);
+        col[i] = orc_encode_colour(rgba + 4 * i);
+    }
+}
+
+void orc_decode(const uint64_t *pos, const uint32_t *col, int64_t n, const double lo[3], double size, double r_unit,
+                float *centre_radius, float *rgba)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        double c[3], r, k[4];
+        orc_decode_position(pos[i], lo, size, r_unit, c, &r);
+        orc_decode_colour(col[i], k);
+        for (int a = 0; a < 3; ++a) centre_radius[4 * i + a] = (float)c[a];
+        centre_radius[4 * i + 3] = (float)r;
+        for (int ch = 0; ch < 4; ++ch) rgba[4 * i + ch] = (float)k[ch];
+    }
 }

@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 
 import oracle
+import test_oracle_codec_pins as K
 import test_oracle_grad_pins as G
 import test_oracle_march_pins as M
 import test_oracle_pins as P
@@ -46,6 +47,14 @@ MUTANTS = [
     ("trilinear weights swapped", "w *= up ? frac[a] : 1.0 - frac[a];", "w *= up ? 1.0 - frac[a] : frac[a];"),
     ("march colour ramp", "C[1] += w * (4.0 * u * (1.0 - u));", "C[1] += w * (u * (1.0 - u));"),
     ("march never stops", "if (A >= stop_alpha) break;", "if (A > 2.0) break;"),
+    ("codec decodes cell corners", "c[a] = lo[a] + ((double)((w >> (18 * a)) & 0x3ffffu) + 0.5) * step;",
+     "c[a] = lo[a] + ((double)((w >> (18 * a)) & 0x3ffffu)) * step;"),
+    ("codec radius steps", "double code = floor(64.0 * log2(r / r_unit) + 0.5) + 512.0;",
+     "double code = floor(32.0 * log2(r / r_unit) + 0.5) + 512.0;"),
+    ("codec colour truncates", "w |= (uint32_t)floor(v * 255.0 + 0.5) << (8 * ch);",
+     "w |= (uint32_t)floor(v * 255.0) << (8 * ch);"),
+    ("codec axis order", "w |= orc_quant(c[a], lo[a], size, 18) << (18 * a);",
+     "w |= orc_quant(c[2 - a], lo[a], size, 18) << (18 * a);"),
 ]
 
 # pins run against each mutant (parametrised pins with their cases)
@@ -74,6 +83,10 @@ PINS = [
     M.test_trilinear_weights_on_a_single_voxel_pulse,
     M.test_ray_missing_the_cube_is_background,
     M.test_matches_the_input_generators_caster,
+    K.test_hand_computed_words,
+    K.test_round_trip_error_bounds,
+    K.test_decoded_values_encode_to_the_same_words,
+    K.test_clamping_and_monotone_codes,
 ]
 
 
