@@ -198,6 +198,34 @@ int splat_raymarch(const splat_volume *vol, const splat_camera *cam, const splat
                    float *out_depth, void *stream);
 
 /*
+ * Sample codec of the wire format (Sec. 3.1: the quantised coordinate is
+ * packed with the radius into 64 bits; Sec. 5: 32 bits per colour).  The bit
+ * split is this library's reading:
+ *   position word = qx | qy << 18 | qz << 36 | c << 54, with
+ *     q = clamp(floor((x - box_lo) / box_size 2^18), 0, 2^18 - 1) per axis,
+ *     decoded at the cell centre (error <= box_size / 2^19 per axis), and
+ *     c = clamp(floor(64 log2(r / r_unit) + 1/2) + 512, 0, 1023), decoded as
+ *     r_unit 2^((c - 512) / 64) (relative error <= 2^(1/128) - 1);
+ *   colour word = RGBA8 of the straight colour and alpha, byte 0 red,
+ *     b = floor(clamp(v, 0, 1) 255 + 1/2), decoded as b / 255.
+ */
+typedef struct splat_codec {
+    double box_lo[3];              /* quantisation box: [box_lo, box_lo + box_size] per axis */
+    double box_size;               /* > 0 */
+    double r_unit;                 /* radius of code 512, > 0 */
+} splat_codec;
+
+/* Encode the first *sph->count spheres (device count) into out_pos (device
+ * uint64 [sph->capacity]) and out_rgba (device uint32 [sph->capacity]). */
+int splat_encode_samples(const splat_spheres *sph, const splat_codec *codec, uint64_t *out_pos, uint32_t *out_rgba,
+                         void *stream);
+
+/* Decode min(*count, out->capacity) samples (count: device uint32) into the
+ * sphere set `out` (its count is written on the device). */
+int splat_decode_samples(const uint64_t *pos, const uint32_t *rgba, const uint32_t *count, const splat_codec *codec,
+                         const splat_spheres *out, void *stream);
+
+/*
  * Unprojection (Sec. 3.1, Eq. 1).  For every source pixel whose depth t is
  * finite and positive and whose alpha A is positive: centre p = o + d t in
  * double (d the unit pixel-centre ray of `src`), radius

@@ -14,8 +14,9 @@ SPLAT_WALK_LANE, SPLAT_WALK_PACKET = 0, 1
 SPLAT_OP_UNPROJECT, SPLAT_OP_BUILD, SPLAT_OP_TRACE, SPLAT_OP_BACKWARD, SPLAT_OP_BATCHED = range(5)
 
 # every symbol include/splat.h declares
-EXPORTS = ["splat_workspace_bytes", "splat_bvh_bytes", "splat_raymarch", "splat_unproject", "splat_build_bvh",
-           "splat_trace", "splat_trace_backward", "splat_trace_batched", "splat_last_error", "splat_version"]
+EXPORTS = ["splat_workspace_bytes", "splat_bvh_bytes", "splat_raymarch", "splat_encode_samples",
+           "splat_decode_samples", "splat_unproject", "splat_build_bvh", "splat_trace", "splat_trace_backward",
+           "splat_trace_batched", "splat_last_error", "splat_version"]
 
 _P = ctypes.c_void_p
 
@@ -48,6 +49,10 @@ class splat_volume(ctypes.Structure):
 class splat_march_opts(ctypes.Structure):
     _fields_ = [("step", ctypes.c_double), ("alpha_scale", ctypes.c_double), ("depth_alpha", ctypes.c_double),
                 ("stop_alpha", ctypes.c_double)]
+
+
+class splat_codec(ctypes.Structure):
+    _fields_ = [("box_lo", ctypes.c_double * 3), ("box_size", ctypes.c_double), ("r_unit", ctypes.c_double)]
 
 
 class splat_grads(ctypes.Structure):
@@ -97,7 +102,10 @@ def load() -> ctypes.CDLL:
         lib.splat_version.restype = ctypes.c_int
         lib.splat_raymarch.argtypes = [ctypes.POINTER(splat_volume), ctypes.POINTER(splat_camera),
                                        ctypes.POINTER(splat_march_opts), _P, _P, _P]
-        for name in ("splat_raymarch", "splat_unproject", "splat_build_bvh", "splat_trace", "splat_trace_backward",
+        lib.splat_encode_samples.argtypes = [ctypes.POINTER(splat_spheres), ctypes.POINTER(splat_codec), _P, _P, _P]
+        lib.splat_decode_samples.argtypes = [_P, _P, _P, ctypes.POINTER(splat_codec), ctypes.POINTER(splat_spheres),
+                                             _P]
+        for name in ("splat_raymarch", "splat_encode_samples", "splat_decode_samples", "splat_unproject", "splat_build_bvh", "splat_trace", "splat_trace_backward",
                      "splat_trace_batched"):
             getattr(lib, name).restype = ctypes.c_int
         _lib = lib

@@ -178,6 +178,40 @@ int splat_raymarch(const splat_volume *vol, const splat_camera *cam, const splat
                       "raymarch launch");
 }
 
+static int check_codec(const splat_codec *c)
+{
+    if (!c) return fail(SPLAT_EINVAL, "codec is NULL");
+    for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(c->box_lo[k])) return fail(SPLAT_EINVAL, "codec box_lo is not finite");
+    if (!std::isfinite(c->box_size) || !(c->box_size > 0)) return fail(SPLAT_EINVAL, "codec box_size must be > 0");
+    if (!std::isfinite(c->r_unit) || !(c->r_unit > 0)) return fail(SPLAT_EINVAL, "codec r_unit must be > 0");
+    return SPLAT_OK;
+}
+
+int splat_encode_samples(const splat_spheres *sph, const splat_codec *codec, uint64_t *out_pos, uint32_t *out_rgba,
+                         void *stream)
+{
+    int rc;
+    if ((rc = check_spheres(sph, true))) return rc;
+    if ((rc = check_codec(codec))) return rc;
+    if (!out_pos || !out_rgba) return fail(SPLAT_EINVAL, "out_pos/out_rgba is NULL");
+    if ((rc = check_device())) return rc;
+    return hip_status(launch_encode(*sph, *codec, out_pos, out_rgba, static_cast<hipStream_t>(stream)),
+                      "encode launch");
+}
+
+int splat_decode_samples(const uint64_t *pos, const uint32_t *rgba, const uint32_t *count, const splat_codec *codec,
+                         const splat_spheres *out, void *stream)
+{
+    int rc;
+    if (!pos || !rgba || !count) return fail(SPLAT_EINVAL, "pos/rgba/count is NULL");
+    if ((rc = check_spheres(out, true))) return rc;
+    if ((rc = check_codec(codec))) return rc;
+    if ((rc = check_device())) return rc;
+    return hip_status(launch_decode(pos, rgba, count, *codec, *out, static_cast<hipStream_t>(stream)),
+                      "decode launch");
+}
+
 int splat_unproject(const splat_camera *src, const float *rgba_premul, const float *depth, float radius_scale,
                     const splat_spheres *out, void *ws, size_t ws_bytes, void *stream)
 {

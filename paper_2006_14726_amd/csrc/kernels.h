@@ -31,6 +31,11 @@ struct TraceArgs {
 hipError_t launch_raymarch(const float *vol, int32_t n, double lo, double size, const Cam &cam,
                            const splat_march_opts &o, float *out_rgba, float *out_depth, hipStream_t s);
 
+hipError_t launch_encode(const splat_spheres &sph, const splat_codec &c, uint64_t *pos, uint32_t *col,
+                         hipStream_t s);
+hipError_t launch_decode(const uint64_t *pos, const uint32_t *col, const uint32_t *count, const splat_codec &c,
+                         const splat_spheres &out, hipStream_t s);
+
 hipError_t launch_unproject(const Cam &cam, const float *rgba, const float *depth, float radius_scale,
                             const splat_spheres &out, void *ws, hipStream_t s);
 

@@ -126,6 +126,39 @@ def raymarch(volume: torch.Tensor, box_lo: float, box_size: float, cam, step: fl
     return out_rgba, out_depth
 
 
+def _codec(box_lo, box_size: float, r_unit: float) -> _lib.splat_codec:
+    c = _lib.splat_codec()
+    lo = [float(box_lo)] * 3 if isinstance(box_lo, (int, float)) else [float(v) for v in box_lo]
+    c.box_lo[:] = lo
+    c.box_size, c.r_unit = float(box_size), float(r_unit)
+    return c
+
+
+def encode_samples(sph: Spheres, box_lo, box_size: float, r_unit: float):
+    """Wire format of a sphere set (splat_encode_samples): (uint64-as-int64 [capacity] position+radius
+    words, int32 [capacity] RGBA8 words); the first sph.count entries are valid."""
+    dev = sph.centre_radius.device
+    pos = torch.empty((sph.capacity,), dtype=torch.int64, device=dev)
+    col = torch.empty((sph.capacity,), dtype=torch.int32, device=dev)
+    c, s = _codec(box_lo, box_size, r_unit), sph.struct()
+    _lib.check(_lib.load().splat_encode_samples(ctypes.byref(s), ctypes.byref(c), _ptr(pos), _ptr(col), _stream()))
+    return pos, col
+
+
+def decode_samples(pos: torch.Tensor, col: torch.Tensor, count: torch.Tensor, box_lo, box_size: float,
+                   r_unit: float, half: bool = True, out: Spheres | None = None) -> Spheres:
+    """Sphere set from the wire format (splat_decode_samples); count is a device int32 [1]."""
+    _require_cuda(pos, "pos", torch.int64)
+    _require_cuda(col, "col", torch.int32)
+    _require_cuda(count, "count", torch.int32)
+    if out is None:
+        out = alloc_spheres(int(pos.numel()), pos.device, half)
+    c, s = _codec(box_lo, box_size, r_unit), out.struct()
+    _lib.check(_lib.load().splat_decode_samples(_ptr(pos), _ptr(col), _ptr(count), ctypes.byref(c), ctypes.byref(s),
+                                                _stream()))
+    return out
+
+
 def unproject(src_cam, rgba: torch.Tensor, depth: torch.Tensor, radius_scale: float = 1.0, half: bool = True,
               out: Spheres | None = None) -> Spheres:
     """Eq. 1 unprojection of a premultiplied RGBA + depth image into spheres (splat_unproject)."""

@@ -46,6 +46,7 @@ def test_struct_layouts_match_the_header():
     assert ctypes.sizeof(_lib.splat_trace_opts) == 40
     assert ctypes.sizeof(_lib.splat_volume) == 32
     assert ctypes.sizeof(_lib.splat_march_opts) == 32
+    assert ctypes.sizeof(_lib.splat_codec) == 40
     assert ctypes.sizeof(_lib.splat_batch_job) == 3 * 8 + 2 * 4 + 112 + 2 * 8
 
 
