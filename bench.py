@@ -200,6 +200,7 @@ def main():
         if args.orbit_frames > 0:
             result["large_orbit"] = large_orbit(sp, torch, synth, dev, opts, args.orbit_frames)
         result["server_stage"] = server_stage(sp, torch, synth, dev, src, dst, opts, max(args.steps, 10))
+        result["codec"] = codec(sp, torch, synth, sph, bvh, src, dst, opts, max(args.steps, 10))
     if not args.no_bwd:
         result["fwd_bwd"] = fwd_bwd(sp, torch, synth, dev, args.steps)
     if args.batch_frames > 0:
@@ -368,6 +369,23 @@ def server_stage(sp, torch, synth, dev, src, dst, opts, reps):
             "march_mrays_s": round(src.width * src.height / (med[0] * 1e-3) / 1e6, 1),
             "frame_ms": round(float(t.sum(axis=1).mean()), 4),
             "stages_ms": {k: round(float(v), 4) for k, v in zip(("march", "unproject", "build", "trace"), med)}}
+
+
+def codec(sp, torch, synth, sph, bvh, src, dst, opts, reps):
+    """Wire format of the client frame's spheres: encode + decode time, bytes, and the image change."""
+    ru = 2.0 * src.tan_half_fov_y / src.height
+    pos, col = sp.encode_samples(sph, synth.BOX_LO, synth.BOX_SIZE, ru)
+    dec = sp.decode_samples(pos, col, sph.count, synth.BOX_LO, synth.BOX_SIZE, ru, half=True)
+    t = np.array([_events(torch, [lambda: sp.encode_samples(sph, synth.BOX_LO, synth.BOX_SIZE, ru),
+                                  lambda: sp.decode_samples(pos, col, sph.count, synth.BOX_LO, synth.BOX_SIZE, ru,
+                                                            half=True, out=dec)]) for _ in range(reps)])
+    img, _ = sp.trace(bvh, sph, dst, opts)
+    dimg, _ = sp.trace(sp.build_bvh(dec), dec, dst, opts)
+    diff = (img - dimg).abs()
+    n = sph.n()
+    return {"spheres": n, "bytes_per_sample": 12, "bytes_per_sample_unpacked": 24,
+            "encode_ms": round(float(np.median(t[:, 0])), 4), "decode_ms": round(float(np.median(t[:, 1])), 4),
+            "image_mean_abs_change": round(float(diff.mean()), 6), "image_max_abs_change": round(float(diff.max()), 4)}
 
 
 def _cpu_model() -> str:
