@@ -2,7 +2,7 @@
  * splat.h -- C ABI of the MI355X (gfx950) splat ray tracer.
  *
  * The client side of image-warping remote volume rendering with ray tracing
- * (Zellmann, arXiv 2006.14726, Sec. 3.1 and Fig. 2): the samples of a 2.5D
+ * (Zellmann, arXiv 2006.14726, Sec. 4.1 and Fig. 2): the samples of a 2.5D
  * RGBA + depth image become coloured semi-transparent spheres, a linear BVH
  * is built over them, and the view from a new camera is ray traced through
  * them with front-to-back compositing.
@@ -56,7 +56,7 @@ extern "C" {
  * normalize(forward + sx right + sy up) with
  *   sx = ((2x+1)/width - 1) tan_half_fov_y width/height,
  *   sy = (1 - (2y+1)/height) tan_half_fov_y.
- * The paper ships the camera with the buffers (Sec. 3.2).
+ * The paper ships the camera with the buffers (Sec. 4.2).
  */
 typedef struct splat_camera {
     double eye[3];
@@ -69,7 +69,7 @@ typedef struct splat_camera {
 } splat_camera;
 
 /*
- * Sphere set (Sec. 3.1: samples reinterpreted as semi-transparent spheres),
+ * Sphere set (Sec. 4.1: samples reinterpreted as semi-transparent spheres),
  * structure of arrays, `capacity` slots, the first *count used.
  *   centre_radius  device float4[capacity]: x, y, z, r (object space)
  *   rgba           device half4 or float4 [capacity]: straight colour k, alpha a
@@ -89,7 +89,7 @@ typedef struct splat_spheres {
 } splat_spheres;
 
 /*
- * Linear BVH (Sec. 3.1, the LBVH of the paper) over at most `capacity`
+ * Linear BVH (Sec. 4.1, the LBVH of the paper) over at most `capacity`
  * spheres, in one device allocation of splat_bvh_bytes(capacity) bytes,
  * 256-byte aligned.  Opaque layout; valid after splat_build_bvh.
  */
@@ -182,7 +182,7 @@ typedef struct splat_march_opts {
 } splat_march_opts;
 
 /*
- * Server stage before the client path (Sec. 3.1: the server ray-marches the
+ * Server stage before the client path (Sec. 4.1: the server ray-marches the
  * volume and writes colour and one representative depth per pixel).  For
  * every pixel of `cam`: samples at t_j = t_in + (j + 1/2) dt along the pixel
  * ray inside the cube (t_in >= 0, dt = step box_size / n), trilinear with
@@ -198,8 +198,8 @@ int splat_raymarch(const splat_volume *vol, const splat_camera *cam, const splat
                    float *out_depth, void *stream);
 
 /*
- * Sample codec of the wire format (Sec. 3.1: the quantised coordinate is
- * packed with the radius into 64 bits; Sec. 5: 32 bits per colour).  The bit
+ * Sample codec of the wire format (Sec. 4.1: the quantised coordinate is
+ * packed with the radius into 64 bits; Sec. 6: 32 bits per colour).  The bit
  * split is this library's reading:
  *   position word = qx | qy << 18 | qz << 36 | c << 54, with
  *     q = clamp(floor((x - box_lo) / box_size 2^18), 0, 2^18 - 1) per axis,
@@ -226,7 +226,7 @@ int splat_decode_samples(const uint64_t *pos, const uint32_t *rgba, const uint32
                          const splat_spheres *out, void *stream);
 
 /*
- * Unprojection (Sec. 3.1, Eq. 1).  For every source pixel whose depth t is
+ * Unprojection (Sec. 4.1, Eq. 1).  For every source pixel whose depth t is
  * finite and positive and whose alpha A is positive: centre p = o + d t in
  * double (d the unit pixel-centre ray of `src`), radius
  * r = radius_scale * 2 t tan_half_fov_y / height (the pixel footprint at t),
@@ -242,7 +242,7 @@ int splat_unproject(const splat_camera *src, const float *rgba_premul, const flo
                     const splat_spheres *out, void *ws, size_t ws_bytes, void *stream);
 
 /*
- * LBVH build (Sec. 3.1): scene bounds, 30-bit Morton codes of the centres,
+ * LBVH build (Sec. 4.1): scene bounds, 30-bit Morton codes of the centres,
  * stable LDS radix sort of (code, id), Karras radix-tree hierarchy, and a
  * bottom-up refit of boxes rounded outward to float.  refit_only != 0 keeps
  * the hierarchy of the previous build over the same centres and recomputes
@@ -257,7 +257,7 @@ int splat_build_bvh(const splat_spheres *sph, const splat_bvh *bvh, int32_t refi
                     void *stream);
 
 /*
- * Trace and composite (Sec. 3.1, Fig. 2).  For every pixel of `cam`: all
+ * Trace and composite (Sec. 4.1, Fig. 2).  For every pixel of `cam`: all
  * spheres hit by its ray (disc >= 0, 0 < t0 < t_max) in ascending
  * (t0, sphere id), composited front to back, C += T alpha k, A += T alpha,
  * T *= 1 - alpha, stopping after the hit at which A >= alpha_stop.  Ray,

@@ -8,15 +8,15 @@ Everything is computed in double precision by ``oracle.c`` (plain C, OpenMP
 over pixels), brute force: every ray against every sphere, hits sorted by
 (t0, id), composited in order.  This module only marshals arrays:
 
-* ``unproject``  Sec. 3.1, Eq. 1 (p = o + d t_i), footprint radius, compaction
-* ``render``     Sec. 3.1 / Fig. 2: spheres traced from a new camera,
+* ``unproject``  Sec. 4.1, Eq. 1 (p = o + d t_i), footprint radius, compaction
+* ``render``     Sec. 4.1 / Fig. 2: spheres traced from a new camera,
                  composited front to back with an alpha stop
 * ``grad``       analytic gradient of a per-pixel loss through ``render``
 * ``half_bits``  double -> binary16 with round-to-nearest-even
-* ``raymarch``   the server stage before the path (Sec. 3.1): volume ray
+* ``raymarch``   the server stage before the path (Sec. 4.1): volume ray
                  marcher writing premultiplied colour and a representative depth
 * ``encode``, ``decode``  the wire format: 64 bits per sample (quantised
-                 position + radius), 32 bits per colour (Sec. 3.1, Sec. 5)
+                 position + radius), 32 bits per colour (Sec. 4.1, Sec. 6)
 """
 from __future__ import annotations
 

@@ -11,20 +11,20 @@
  * sphere, the hits are sorted, and they are composited one by one in double
  * precision.  Functions:
  *
- *   orc_unproject   Sec. 3.1, Eq. 1: p = o + d t_i per pixel, a footprint
+ *   orc_unproject   Sec. 4.1, Eq. 1: p = o + d t_i per pixel, a footprint
  *                   radius, compaction of pixels without a sample.
- *   orc_render      Sec. 3.1 / Fig. 2: the samples as coloured
+ *   orc_render      Sec. 4.1 / Fig. 2: the samples as coloured
  *                   semi-transparent spheres, traced from a new camera,
  *                   composited front to back, stopping at a given alpha.
  *   orc_grad        gradient of a per-pixel loss through orc_render.
  *   orc_pixels_near lists the pixels whose ray passes near a point.
  *   orc_sphere_test one ray against one sphere (exposed for closed-form pins).
  *   orc_half_bits   double -> IEEE binary16, round to nearest even.
- *   orc_raymarch    the server stage before the path (Sec. 3.1): a volume
+ *   orc_raymarch    the server stage before the path (Sec. 4.1): a volume
  *                   ray marcher writing colour and a representative depth;
  *   orc_volume_sample  its trilinear reconstruction (exposed for pins).
  *   orc_encode, orc_decode  the 64-bit sample + 32-bit colour wire format
- *                   (Sec. 3.1, Sec. 5), with per-value helpers for pins.
+ *                   (Sec. 4.1, Sec. 6), with per-value helpers for pins.
  *
  * Readings of the paper (it specifies none of these):
  *   - camera: pinhole, ray through pixel centre (x+1/2, y+1/2), row 0 at top,
@@ -492,7 +492,7 @@ int64_t orc_pixels_near(const orc_camera *cam, const double centre[3], double ra
 }
 
 /* ------------------------------------------------------------------ server
- * The server stage before the client path (Sec. 3.1: a ray marcher renders
+ * The server stage before the client path (Sec. 4.1: a ray marcher renders
  * the volume and writes, per pixel, the composited colour and one
  * representative depth t).  The paper names only a standard ray marcher and
  * a depth heuristic from earlier work; the rules written out here are the
@@ -605,8 +605,8 @@ int orc_raymarch(const float *vol, int32_t n, double lo, double size, const orc_
 }
 
 /* ------------------------------------------------------------------ codec
- * The sample codec of the wire format (Sec. 3.1: each object-space sample's
- * quantised coordinate is packed with its radius into 64 bits; Sec. 5: 32
+ * The sample codec of the wire format (Sec. 4.1: each object-space sample's
+ * quantised coordinate is packed with its radius into 64 bits; Sec. 6: 32
  * bits per colour).  The paper leaves the bit split open; the reading here:
  *   - position: 18 bits per axis, q = clamp(floor((x - lo) / size 2^18),
  *     0, 2^18 - 1), decoded at the cell centre lo + (q + 1/2) size / 2^18;

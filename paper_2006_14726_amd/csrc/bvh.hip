@@ -1,4 +1,4 @@
-// LBVH construction over the spheres (Sec. 3.1: the client builds a linear
+// LBVH construction over the spheres (Sec. 4.1: the client builds a linear
 // BVH over the received samples).
 //
 //   bounds   block partial min/max of the centres

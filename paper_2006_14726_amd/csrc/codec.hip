@@ -1,6 +1,6 @@
-// Sample codec of the wire format between server and client (Sec. 3.1: each
+// Sample codec of the wire format between server and client (Sec. 4.1: each
 // object-space sample's quantised coordinate is packed with its radius into
-// 64 bits; Sec. 5: 32 bits per colour).  The paper leaves the bit split
+// 64 bits; Sec. 6: 32 bits per colour).  The paper leaves the bit split
 // open; this library uses
 //   word   = qx | qy << 18 | qz << 36 | c << 54,
 //   q      = clamp(floor((x - lo) / size 2^18), 0, 2^18 - 1) per axis,

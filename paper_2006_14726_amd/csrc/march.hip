@@ -1,4 +1,4 @@
-// Server stage before the client path (Sec. 3.1): a volume ray marcher
+// Server stage before the client path (Sec. 4.1): a volume ray marcher
 // that writes, per source pixel, the front-to-back composited colour and one
 // representative depth t (the first sample at which the accumulated alpha
 // reaches depth_alpha), the image that splat_unproject turns into spheres.

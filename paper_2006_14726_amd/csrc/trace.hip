@@ -1,5 +1,5 @@
 // Ray tracing of the sphere set with exact front-to-back compositing
-// (Sec. 3.1 and Fig. 2: the client renders the samples as coloured
+// (Sec. 4.1 and Fig. 2: the client renders the samples as coloured
 // semi-transparent spheres from the current camera).
 //
 // One 64-lane wavefront traces one tile of pixels as a packet: the BVH walk

@@ -1,4 +1,4 @@
-// Unprojection of a 2.5D RGBA + depth image into spheres (Sec. 3.1, Eq. 1),
+// Unprojection of a 2.5D RGBA + depth image into spheres (Sec. 4.1, Eq. 1),
 // with stable compaction of the pixels that carry a sample (the paper moves
 // zero-radius samples aside before sending; here it is a GPU scan).
 //

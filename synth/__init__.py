@@ -1,9 +1,9 @@
 """Seeded synthetic inputs shared by the CPU oracle and the GPU path.
 
 The paper evaluates on an unnamed volume data set that is not available
-(Sec. 4, Fig. 3, Table 1), so seeded Gaussian-blob volumes stand in for it.
+(Sec. 5, Fig. 3, Table 1), so seeded Gaussian-blob volumes stand in for it.
 This module only *produces inputs*: cameras, blob volumes, the server-side
-ray-cast 2.5D image (RGBA + depth, Sec. 3.1) and random sphere sets for small
+ray-cast 2.5D image (RGBA + depth, Sec. 4.1) and random sphere sets for small
 tests.  It holds none of the client method's arithmetic (unprojection,
 hierarchy construction, sphere tracing, compositing of splats).
 """

@@ -3,7 +3,7 @@
  * that turns it into a 2.5D premultiplied RGBA + depth image.
  *
  * This is input generation only.  It stands in for the server of the paper
- * (Sec. 3.1: a volume ray marcher writes a colour and a representative ray
+ * (Sec. 4.1: a volume ray marcher writes a colour and a representative ray
  * parameter t_i per pixel) and holds none of the client method's arithmetic
  * (unprojection, hierarchy, sphere tracing, compositing of splats).  Both the
  * CPU oracle and the GPU path consume what it writes.

@@ -1,5 +1,5 @@
 """GPU parity of the sample codec (splat_encode_samples / splat_decode_samples,
-the wire format of Sec. 3.1 and Sec. 5) against the oracle's codec, and the
+the wire format of Sec. 4.1 and Sec. 5) against the oracle's codec, and the
 client path run on decoded samples."""
 import numpy as np
 import pytest

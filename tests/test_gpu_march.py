@@ -1,5 +1,5 @@
 """GPU parity of the server ray marcher (splat_raymarch, the stage before the
-path, Sec. 3.1) against the oracle's FP64 marcher, through the C ABI."""
+path, Sec. 4.1) against the oracle's FP64 marcher, through the C ABI."""
 import math
 
 import numpy as np

@@ -1,6 +1,6 @@
 """Pins of the oracle's sample codec (64 bits per sample: 3 x 18-bit
 quantised position + 10-bit log radius; 32 bits per colour: RGBA8; the wire
-format of Sec. 3.1 and Sec. 5): hand-computed words, the error bounds of a
+format of Sec. 4.1 and Sec. 5): hand-computed words, the error bounds of a
 round trip, idempotence on decoded values, clamping and monotonicity."""
 import math
 
