@@ -17,6 +17,9 @@ over pixels), brute force: every ray against every sphere, hits sorted by
                  marcher writing premultiplied colour and a representative depth
 * ``encode``, ``decode``  the wire format: 64 bits per sample (quantised
                  position + radius), 32 bits per colour (Sec. 4.1, Sec. 6)
+* ``accumulate`` temporal accumulation across frames (Sec. 7): the new
+                 frame's samples, then the history samples whose grid cell the
+                 frame does not occupy and that are not too old
 """
 from __future__ import annotations
 
@@ -104,6 +107,9 @@ def _load():
         lib.orc_encode.restype = None
         lib.orc_decode.argtypes = [_P, _P, ctypes.c_int64, _P, ctypes.c_double, ctypes.c_double, _P, _P]
         lib.orc_decode.restype = None
+        lib.orc_accumulate.argtypes = [_P, ctypes.c_int64, _P, _P, ctypes.c_int64, _P, ctypes.c_double,
+                                       ctypes.c_int32, ctypes.c_int32, _P]
+        lib.orc_accumulate.restype = ctypes.c_int64
         _lib = lib
     return _lib
 
@@ -288,3 +294,43 @@ def encode_position(c, r: float, box_lo, box_size: float, r_unit: float) -> int:
 def encode_colour(k) -> int:
     kk = np.ascontiguousarray(k, dtype=np.float64)
     return int(_load().orc_encode_colour(kk.ctypes.data))
+
+
+def accumulate_survivors(frame_cr: np.ndarray, hist_cr: np.ndarray, hist_age: np.ndarray, box_lo, box_size: float,
+                         grid: int, max_age: int) -> np.ndarray:
+    """Indices (ascending) of the history samples that survive the merge with a new frame."""
+    f = np.ascontiguousarray(frame_cr, dtype=np.float32).reshape(-1, 4)
+    h = np.ascontiguousarray(hist_cr, dtype=np.float32).reshape(-1, 4)
+    age = np.ascontiguousarray(hist_age, dtype=np.uint8).reshape(-1)
+    assert age.shape[0] == h.shape[0]
+    lo = np.ascontiguousarray(np.broadcast_to(np.asarray(box_lo, dtype=np.float64), (3,)))
+    kept = np.zeros(max(h.shape[0], 1), dtype=np.int64)
+    n = _load().orc_accumulate(f.ctypes.data, f.shape[0], h.ctypes.data, age.ctypes.data, h.shape[0], lo.ctypes.data,
+                               float(box_size), int(grid), int(max_age), kept.ctypes.data)
+    if n < 0:
+        raise RuntimeError("orc_accumulate: out of memory")
+    return kept[:n].copy()
+
+
+def accumulate(frame: dict, history: dict, box_lo, box_size: float, grid: int, max_age: int,
+               capacity: int | None = None) -> dict:
+    """Merged sample set of a new frame and the history (Sec. 7, temporal accumulation).
+
+    ``frame`` holds ``cr`` (float32 [n][4]) and ``rgba`` ([n][4], any dtype),
+    optionally ``src`` (uint32 [n]); ``history`` the same plus ``age`` (uint8
+    [m]).  The result: frame samples with age 0, then the surviving history
+    samples with age + 1, cut to ``capacity``."""
+    keep = accumulate_survivors(frame["cr"], history["cr"], history["age"], box_lo, box_size, grid, max_age)
+    out = {
+        "cr": np.concatenate([np.asarray(frame["cr"]).reshape(-1, 4), np.asarray(history["cr"]).reshape(-1, 4)[keep]]),
+        "rgba": np.concatenate([np.asarray(frame["rgba"]).reshape(-1, 4),
+                                np.asarray(history["rgba"]).reshape(-1, 4)[keep]]),
+        "age": np.concatenate([np.zeros(len(frame["cr"]), dtype=np.uint8),
+                               (np.asarray(history["age"], dtype=np.int32)[keep] + 1).astype(np.uint8)]),
+    }
+    if "src" in frame and "src" in history:
+        out["src"] = np.concatenate([np.asarray(frame["src"]), np.asarray(history["src"])[keep]]).astype(np.uint32)
+    if capacity is not None:
+        out = {k: v[:capacity] for k, v in out.items()}
+    out["kept"] = keep
+    return out

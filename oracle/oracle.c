@@ -25,6 +25,8 @@
  *   orc_volume_sample  its trilinear reconstruction (exposed for pins).
  *   orc_encode, orc_decode  the 64-bit sample + 32-bit colour wire format
  *                   (Sec. 4.1, Sec. 6), with per-value helpers for pins.
+ *   orc_accumulate  temporal accumulation of samples across frames (Sec. 7):
+ *                   which history samples survive the merge with a new frame.
  *
  * Readings of the paper (it specifies none of these):
  *   - camera: pinhole, ray through pixel centre (x+1/2, y+1/2), row 0 at top,
@@ -681,4 +683,56 @@ void orc_decode(const uint64_t *pos, const uint32_t *col, int64_t n, const doubl
         centre_radius[4 * i + 3] = (float)r;
         for (int ch = 0; ch < 4; ++ch) rgba[4 * i + ch] = (float)k[ch];
     }
+}
+
+/*
+ * Temporal accumulation (Sec. 7 names keeping samples across a few frames as
+ * an extension; it gives no policy).  The reading here:
+ *   - a uniform grid of `grid`^3 cells covers [lo, lo + size]^3; a centre x
+ *     lies in cell q = clamp(floor((x - lo) / size grid), 0, grid - 1) per
+ *     axis (centres outside the box fall into the border cells);
+ *   - the merged set is the new frame's samples, in their order, with age 0,
+ *     followed by the history samples, in their order, that survive: a
+ *     history sample survives iff its age + 1 <= max_age and no centre of the
+ *     new frame lies in its cell; it carries age + 1;
+ *   - if the merged set exceeds the capacity, its first `capacity` samples
+ *     are kept (the newest, since the list stays sorted by age).
+ * orc_accumulate returns the number of surviving history samples and their
+ * indices, ascending.  The frame's cells are sorted once and looked up by
+ * binary search; everything else is one pass over the history.
+ */
+static uint64_t orc_cell_key(const float *cr, const double lo[3], double size, int32_t grid)
+{
+    uint64_t key = 0;
+    for (int a = 0; a < 3; ++a) {
+        double q = floor(((double)cr[a] - lo[a]) / size * (double)grid);
+        if (!(q >= 0.0)) q = 0.0; /* also NaN */
+        if (q > (double)(grid - 1)) q = (double)(grid - 1);
+        key |= (uint64_t)q << (20 * a);
+    }
+    return key;
+}
+
+static int orc_key_cmp(const void *pa, const void *pb)
+{
+    const uint64_t a = *(const uint64_t *)pa, b = *(const uint64_t *)pb;
+    return (a > b) - (a < b);
+}
+
+int64_t orc_accumulate(const float *frame_cr, int64_t n_frame, const float *hist_cr, const uint8_t *hist_age,
+                       int64_t n_hist, const double lo[3], double size, int32_t grid, int32_t max_age, int64_t *kept)
+{
+    uint64_t *keys = (uint64_t *)malloc((size_t)(n_frame > 0 ? n_frame : 1) * sizeof(uint64_t));
+    if (!keys) return -1;
+    for (int64_t i = 0; i < n_frame; ++i) keys[i] = orc_cell_key(frame_cr + 4 * i, lo, size, grid);
+    qsort(keys, (size_t)n_frame, sizeof(uint64_t), orc_key_cmp);
+    int64_t n_kept = 0;
+    for (int64_t i = 0; i < n_hist; ++i) {
+        if ((int32_t)hist_age[i] + 1 > max_age) continue;
+        const uint64_t key = orc_cell_key(hist_cr + 4 * i, lo, size, grid);
+        if (n_frame > 0 && bsearch(&key, keys, (size_t)n_frame, sizeof(uint64_t), orc_key_cmp)) continue;
+        kept[n_kept++] = i;
+    }
+    free(keys);
+    return n_kept;
 }

@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 
 import oracle
+import test_oracle_accum_pins as T
 import test_oracle_codec_pins as K
 import test_oracle_grad_pins as G
 import test_oracle_march_pins as M
@@ -55,6 +56,17 @@ MUTANTS = [
      "w |= (uint32_t)floor(v * 255.0) << (8 * ch);"),
     ("codec axis order", "w |= orc_quant(c[a], lo[a], size, 18) << (18 * a);",
      "w |= orc_quant(c[2 - a], lo[a], size, 18) << (18 * a);"),
+    ("accumulate reads x for every axis", "double q = floor(((double)cr[a] - lo[a]) / size * (double)grid);",
+     "double q = floor(((double)cr[0] - lo[a]) / size * (double)grid);"),
+    ("accumulate cells overlap in the key", "key |= (uint64_t)q << (20 * a);", "key |= (uint64_t)q << (2 * a);"),
+    ("accumulate one origin for all axes", "double q = floor(((double)cr[a] - lo[a]) / size * (double)grid);",
+     "double q = floor(((double)cr[a] - lo[0]) / size * (double)grid);"),
+    ("accumulate rounds to the nearest cell", "double q = floor(((double)cr[a] - lo[a]) / size * (double)grid);",
+     "double q = rint(((double)cr[a] - lo[a]) / size * (double)grid);"),
+    ("accumulate no lower clamp", "if (!(q >= 0.0)) q = 0.0; /* also NaN */", ""),
+    ("accumulate no upper clamp", "if (q > (double)(grid - 1)) q = (double)(grid - 1);", ""),
+    ("accumulate keeps one frame too long", "if ((int32_t)hist_age[i] + 1 > max_age) continue;",
+     "if ((int32_t)hist_age[i] > max_age) continue;"),
 ]
 
 # pins run against each mutant (parametrised pins with their cases)
@@ -87,6 +99,11 @@ PINS = [
     K.test_round_trip_error_bounds,
     K.test_decoded_values_encode_to_the_same_words,
     K.test_clamping_and_monotone_codes,
+    T.test_hand_placed_cells,
+    T.test_age_limits,
+    lambda: [T.test_random_cells_by_construction(sd) for sd in (0, 1, 2)],
+    T.test_merging_a_frame_twice,
+    T.test_merged_layout_and_capacity,
 ]
 
 
