@@ -206,7 +206,7 @@ def main():
     if args.batch_frames > 0:
         result["batched"] = batched(sp, torch, synth, dev, args.batch_frames)
     if not args.no_cpu:
-        result["cpu_baseline"] = cpu_baseline(sph, dst, n)
+        result["cpu_baseline"] = cpu_baseline(rgba_np, depth_np, src, dst)
     print(json.dumps(result), flush=True)
 
 
@@ -398,11 +398,11 @@ def _cpu_model() -> str:
     return "unknown"
 
 
-def cpu_baseline(sph, dst, n):
-    """The FP64 brute-force oracle on a bounded pixel sample of the same frame, on the host cores."""
+def cpu_baseline(rgba_np, depth_np, src, dst):
+    """The FP64 brute-force oracle on a bounded pixel sample of the same frame, on the host cores.
+    Its spheres come from its own unprojection of the source image."""
     import oracle
-    cr = sph.centre_radius[:n].cpu().numpy()
-    col = sph.rgba[:n].cpu().numpy()
+    cr, col, _ = oracle.unproject(src, rgba_np, depth_np, 1.0, True)
     rng = np.random.default_rng(0)
     table = oracle.sphere_table(cr, col)
     oracle.render_table(table, dst, pixels=rng.integers(0, dst.width * dst.height, 64))  # warm

@@ -49,6 +49,7 @@ extern "C" {
 #define SPLAT_OP_TRACE 2
 #define SPLAT_OP_BACKWARD 3
 #define SPLAT_OP_BATCHED 4
+#define SPLAT_OP_ACCUMULATE 5
 
 /*
  * Pinhole camera, all in double.  forward/right/up must be orthonormal
@@ -224,6 +225,48 @@ int splat_encode_samples(const splat_spheres *sph, const splat_codec *codec, uin
  * sphere set `out` (its count is written on the device). */
 int splat_decode_samples(const uint64_t *pos, const uint32_t *rgba, const uint32_t *count, const splat_codec *codec,
                          const splat_spheres *out, void *stream);
+
+/*
+ * Temporal accumulation options (Sec. 7 names keeping samples across a few
+ * frames as an extension; the merge policy below is this library's reading).
+ *   box_lo, box_size  the grid covers [box_lo, box_lo + box_size] per axis
+ *   grid              cells per axis, 1..1024; a centre x lies in cell
+ *                     q = clamp(floor((x - box_lo) / box_size grid), 0, grid - 1)
+ *                     per axis, in double (centres outside the box fall into
+ *                     the border cells)
+ *   max_age           0..255: a history sample survives only while its age
+ *                     after the merge is at most max_age
+ */
+typedef struct splat_accum_opts {
+    double box_lo[3];
+    double box_size;
+    int32_t grid;
+    int32_t max_age;
+} splat_accum_opts;
+
+/*
+ * Temporal accumulation (Sec. 7).  The merged set `out` is the first
+ * *frame->count samples of the new frame, in order, with age 0, followed by
+ * the history samples, in order, that survive: a history sample survives iff
+ * its age + 1 <= max_age and no centre of the new frame lies in its cell; it
+ * carries age + 1.  *out->count = min(merged, out->capacity): the excess is
+ * cut from the end, where the oldest samples are.  Centre, radius, colour and
+ * src_index are copied bit for bit.  Build (not refit) the BVH of the merged
+ * set before tracing it.
+ *   history      NULL for none; otherwise its colour dtype equals the frame's
+ *   history_age  device uint8 [history->capacity] (ignored without history)
+ *   out          colour dtype equal to the frame's; out->src_index NULL, or
+ *                set together with the frame's and the history's; no array of
+ *                out (nor out_age) may overlap an input array (SPLAT_EINVAL)
+ *   out_age      device uint8 [out->capacity]
+ *   ws           device, >= splat_workspace_bytes(SPLAT_OP_ACCUMULATE,
+ *                history capacity (0 without history), grid, 0): the cell
+ *                bitmap (grid^3 / 8 bytes) and per-tile survivor counts.
+ *                Calls that overlap on one workspace race.
+ */
+int splat_accumulate(const splat_spheres *frame, const splat_spheres *history, const uint8_t *history_age,
+                     const splat_accum_opts *opts, const splat_spheres *out, uint8_t *out_age, void *ws,
+                     size_t ws_bytes, void *stream);
 
 /*
  * Unprojection (Sec. 4.1, Eq. 1).  For every source pixel whose depth t is

@@ -8,11 +8,11 @@ front-to-back compositing.  Every step runs in the HIP kernels of
 """
 from . import _lib
 from ._lib import (SPLAT_ALPHA_CONSTANT, SPLAT_ALPHA_SOFT, SPLAT_F16, SPLAT_F32, SplatError)
-from .render import (BVH, Spheres, TraceOptions, alloc_bvh, alloc_spheres, build_bvh, decode_samples,
+from .render import (BVH, Spheres, TraceOptions, accumulate, alloc_bvh, alloc_spheres, build_bvh, decode_samples,
                      encode_samples, raymarch, render, spheres_from_tensors, trace, trace_backward, unproject)
 
 __all__ = ["BVH", "Spheres", "TraceOptions", "SplatError", "alloc_bvh", "alloc_spheres", "build_bvh", "raymarch", "render",
-           "spheres_from_tensors", "trace", "trace_backward", "unproject", "encode_samples", "decode_samples", "SPLAT_ALPHA_CONSTANT",
+           "spheres_from_tensors", "trace", "trace_backward", "unproject", "encode_samples", "decode_samples", "accumulate", "SPLAT_ALPHA_CONSTANT",
            "SPLAT_ALPHA_SOFT", "SPLAT_F16", "SPLAT_F32", "load_library"]
 
 

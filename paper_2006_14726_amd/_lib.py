@@ -11,11 +11,11 @@ SPLAT_OK, SPLAT_EINVAL, SPLAT_ENOSPC, SPLAT_ENODEV, SPLAT_EHIP, SPLAT_EUNSUPPORT
 SPLAT_F32, SPLAT_F16 = 0, 1
 SPLAT_ALPHA_CONSTANT, SPLAT_ALPHA_SOFT = 0, 1
 SPLAT_WALK_LANE, SPLAT_WALK_PACKET = 0, 1
-SPLAT_OP_UNPROJECT, SPLAT_OP_BUILD, SPLAT_OP_TRACE, SPLAT_OP_BACKWARD, SPLAT_OP_BATCHED = range(5)
+SPLAT_OP_UNPROJECT, SPLAT_OP_BUILD, SPLAT_OP_TRACE, SPLAT_OP_BACKWARD, SPLAT_OP_BATCHED, SPLAT_OP_ACCUMULATE = range(6)
 
 # every symbol include/splat.h declares
 EXPORTS = ["splat_workspace_bytes", "splat_bvh_bytes", "splat_raymarch", "splat_encode_samples",
-           "splat_decode_samples", "splat_unproject", "splat_build_bvh", "splat_trace", "splat_trace_backward",
+           "splat_decode_samples", "splat_accumulate", "splat_unproject", "splat_build_bvh", "splat_trace", "splat_trace_backward",
            "splat_trace_batched", "splat_last_error", "splat_version"]
 
 _P = ctypes.c_void_p
@@ -53,6 +53,11 @@ class splat_march_opts(ctypes.Structure):
 
 class splat_codec(ctypes.Structure):
     _fields_ = [("box_lo", ctypes.c_double * 3), ("box_size", ctypes.c_double), ("r_unit", ctypes.c_double)]
+
+
+class splat_accum_opts(ctypes.Structure):
+    _fields_ = [("box_lo", ctypes.c_double * 3), ("box_size", ctypes.c_double), ("grid", ctypes.c_int32),
+                ("max_age", ctypes.c_int32)]
 
 
 class splat_grads(ctypes.Structure):
@@ -105,7 +110,11 @@ def load() -> ctypes.CDLL:
         lib.splat_encode_samples.argtypes = [ctypes.POINTER(splat_spheres), ctypes.POINTER(splat_codec), _P, _P, _P]
         lib.splat_decode_samples.argtypes = [_P, _P, _P, ctypes.POINTER(splat_codec), ctypes.POINTER(splat_spheres),
                                              _P]
-        for name in ("splat_raymarch", "splat_encode_samples", "splat_decode_samples", "splat_unproject", "splat_build_bvh", "splat_trace", "splat_trace_backward",
+        lib.splat_accumulate.argtypes = [ctypes.POINTER(splat_spheres), ctypes.POINTER(splat_spheres), _P,
+                                         ctypes.POINTER(splat_accum_opts), ctypes.POINTER(splat_spheres), _P, _P,
+                                         ctypes.c_size_t, _P]
+        for name in ("splat_raymarch", "splat_encode_samples", "splat_decode_samples", "splat_accumulate",
+                     "splat_unproject", "splat_build_bvh", "splat_trace", "splat_trace_backward",
                      "splat_trace_batched"):
             getattr(lib, name).restype = ctypes.c_int
         _lib = lib

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsplat.so")
-SOURCES = ["api.hip", "unproject.hip", "bvh.hip", "trace.hip", "schedule.hip", "march.hip", "codec.hip"]
+SOURCES = ["api.hip", "unproject.hip", "bvh.hip", "trace.hip", "schedule.hip", "march.hip", "codec.hip", "accum.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

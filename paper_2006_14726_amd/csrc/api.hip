@@ -118,7 +118,7 @@ int hip_status(hipError_t e, const char *what)
 
 extern "C" {
 
-int splat_version(void) { return 102; }
+int splat_version(void) { return 103; }
 
 const char *splat_last_error(void) { return g_err; }
 
@@ -146,6 +146,7 @@ size_t splat_workspace_bytes(int32_t op, uint32_t capacity, int32_t width, int32
     case SPLAT_OP_TRACE:
     case SPLAT_OP_BACKWARD: return (width > 0 && height > 0) ? trace_ws_bytes(width, height) : 0;
     case SPLAT_OP_BATCHED: return 256;
+    case SPLAT_OP_ACCUMULATE: return (width >= 1 && width <= 1024) ? AccumLayout(width, capacity).total : 0;
     default: return 0;
     }
 }
@@ -210,6 +211,69 @@ int splat_decode_samples(const uint64_t *pos, const uint32_t *rgba, const uint32
     if ((rc = check_device())) return rc;
     return hip_status(launch_decode(pos, rgba, count, *codec, *out, static_cast<hipStream_t>(stream)),
                       "decode launch");
+}
+
+namespace {
+struct Span {
+    const void *p;
+    size_t bytes;
+};
+bool overlaps(const Span &a, const Span &b)
+{
+    if (!a.p || !b.p || !a.bytes || !b.bytes) return false;
+    const uintptr_t a0 = reinterpret_cast<uintptr_t>(a.p), b0 = reinterpret_cast<uintptr_t>(b.p);
+    return a0 < b0 + b.bytes && b0 < a0 + a.bytes;
+}
+size_t colour_bytes(const splat_spheres &s) { return (size_t)s.capacity * (s.rgba_dtype == SPLAT_F16 ? 8 : 16); }
+}  // namespace
+
+int splat_accumulate(const splat_spheres *frame, const splat_spheres *history, const uint8_t *history_age,
+                     const splat_accum_opts *opts, const splat_spheres *out, uint8_t *out_age, void *ws,
+                     size_t ws_bytes, void *stream)
+{
+    int rc;
+    if ((rc = check_spheres(frame, true))) return rc;
+    if ((rc = check_spheres(out, true))) return rc;
+    if (history) {
+        if ((rc = check_spheres(history, true))) return rc;
+        if (!history_age) return fail(SPLAT_EINVAL, "history_age is NULL");
+        if (history->rgba_dtype != frame->rgba_dtype)
+            return fail(SPLAT_EINVAL, "history and frame colour dtypes differ");
+    }
+    if (out->rgba_dtype != frame->rgba_dtype) return fail(SPLAT_EINVAL, "out and frame colour dtypes differ");
+    if (!out_age) return fail(SPLAT_EINVAL, "out_age is NULL");
+    if (out->src_index && (!frame->src_index || (history && !history->src_index)))
+        return fail(SPLAT_EINVAL, "out->src_index needs src_index on the frame and the history");
+    if (!opts) return fail(SPLAT_EINVAL, "accumulation opts is NULL");
+    for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(opts->box_lo[k])) return fail(SPLAT_EINVAL, "accumulation box_lo is not finite");
+    if (!std::isfinite(opts->box_size) || !(opts->box_size > 0))
+        return fail(SPLAT_EINVAL, "accumulation box_size must be > 0");
+    if (opts->grid < 1 || opts->grid > 1024) return fail(SPLAT_EINVAL, "accumulation grid %d not in 1..1024", opts->grid);
+    if (opts->max_age < 0 || opts->max_age > 255)
+        return fail(SPLAT_EINVAL, "accumulation max_age %d not in 0..255", opts->max_age);
+    const uint32_t hcap = history ? history->capacity : 0u;
+    const Span outs[5] = {{out->centre_radius, (size_t)out->capacity * 16}, {out->rgba, colour_bytes(*out)},
+                          {out->src_index, out->src_index ? (size_t)out->capacity * 4 : 0}, {out->count, 4},
+                          {out_age, out->capacity}};
+    const Span ins[9] = {{frame->centre_radius, (size_t)frame->capacity * 16},
+                         {frame->rgba, colour_bytes(*frame)},
+                         {frame->src_index, frame->src_index ? (size_t)frame->capacity * 4 : 0},
+                         {frame->count, 4},
+                         {history ? history->centre_radius : nullptr, (size_t)hcap * 16},
+                         {history ? history->rgba : nullptr, history ? colour_bytes(*history) : 0},
+                         {history ? history->src_index : nullptr, history && history->src_index ? (size_t)hcap * 4 : 0},
+                         {history ? history->count : nullptr, 4},
+                         {history ? history_age : nullptr, hcap}};
+    for (const Span &o : outs)
+        for (const Span &i : ins)
+            if (overlaps(o, i)) return fail(SPLAT_EINVAL, "an output array of the accumulation overlaps an input");
+    const size_t need = AccumLayout(opts->grid, hcap).total;
+    if (!ws || ws_bytes < need) return fail(SPLAT_ENOSPC, "accumulation workspace needs %zu bytes", need);
+    if ((rc = check_device())) return rc;
+    return hip_status(launch_accumulate(*frame, history, history_age, *opts, *out, out_age, ws,
+                                        static_cast<hipStream_t>(stream)),
+                      "accumulate launch");
 }
 
 int splat_unproject(const splat_camera *src, const float *rgba_premul, const float *depth, float radius_scale,

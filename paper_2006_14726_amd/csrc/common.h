@@ -214,4 +214,22 @@ __host__ __device__ inline size_t unproject_ws_bytes(int64_t pixels)
     return align256((blocks + 1) * 4);
 }
 
+// Temporal accumulation workspace: the occupancy bitmap of the grid (one bit
+// per cell), the per-tile survivor counts of the history and their scan, and
+// the survivor total.  Tiles are kUnprojTile history samples.
+struct AccumLayout {
+    size_t bits, tile_counts, total_slot, total;
+    uint32_t words, tiles;
+    __host__ __device__ AccumLayout(int32_t grid, uint32_t history_capacity)
+    {
+        const uint64_t cells = (uint64_t)grid * (uint64_t)grid * (uint64_t)grid;
+        words = (uint32_t)((cells + 31) / 32);
+        tiles = history_capacity ? (history_capacity + kUnprojTile - 1) / kUnprojTile : 1;
+        bits = 0;
+        tile_counts = align256(bits + (size_t)words * 4);
+        total_slot = align256(tile_counts + (size_t)tiles * 4);
+        total = align256(total_slot + 4);
+    }
+};
+
 }  // namespace splat

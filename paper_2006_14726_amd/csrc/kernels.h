@@ -36,6 +36,14 @@ hipError_t launch_encode(const splat_spheres &sph, const splat_codec &c, uint64_
 hipError_t launch_decode(const uint64_t *pos, const uint32_t *col, const uint32_t *count, const splat_codec &c,
                          const splat_spheres &out, hipStream_t s);
 
+// Exclusive scan of n per-tile counts in place (one workgroup); the total to *total.
+hipError_t launch_tile_scan(uint32_t *counts, uint32_t n, uint32_t *total, hipStream_t s);
+
+// Temporal accumulation: frame first, then the history samples that survive.
+hipError_t launch_accumulate(const splat_spheres &frame, const splat_spheres *history, const uint8_t *history_age,
+                             const splat_accum_opts &o, const splat_spheres &out, uint8_t *out_age, void *ws,
+                             hipStream_t s);
+
 hipError_t launch_unproject(const Cam &cam, const float *rgba, const float *depth, float radius_scale,
                             const splat_spheres &out, void *ws, hipStream_t s);
 

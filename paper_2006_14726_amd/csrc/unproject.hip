@@ -127,6 +127,12 @@ k_unproject_write(Cam cam, const float *__restrict__ rgba, const float *__restri
     }
 }
 
+hipError_t launch_tile_scan(uint32_t *counts, uint32_t n, uint32_t *total, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_unproject_scan, dim3(1), dim3(1024), 0, s, counts, n, total);
+    return hipGetLastError();
+}
+
 hipError_t launch_unproject(const Cam &cam, const float *rgba, const float *depth, float radius_scale,
                             const splat_spheres &out, void *ws, hipStream_t s)
 {

@@ -159,6 +159,37 @@ def decode_samples(pos: torch.Tensor, col: torch.Tensor, count: torch.Tensor, bo
     return out
 
 
+def accumulate(frame: Spheres, history: Spheres | None, history_age: torch.Tensor | None, box_lo, box_size: float,
+               grid: int, max_age: int, out: Spheres | None = None, out_age: torch.Tensor | None = None):
+    """Temporal accumulation (splat_accumulate): the new frame's samples, then the history samples whose grid
+    cell the frame leaves free and whose age + 1 <= max_age.  Returns (merged Spheres, uint8 ages)."""
+    dev = frame.centre_radius.device
+    if history is not None:
+        _require_cuda(history_age, "history_age", torch.uint8)
+    if out is None:
+        cap = frame.capacity + (history.capacity if history is not None else 0)
+        out = alloc_spheres(cap, dev, frame.half)
+        if frame.src_index is None or (history is not None and history.src_index is None):
+            out.src_index = None
+    if out_age is None:
+        out_age = torch.empty((out.capacity,), dtype=torch.uint8, device=dev)
+    _require_cuda(out_age, "out_age", torch.uint8)
+    o = _lib.splat_accum_opts()
+    lo = [float(v) for v in (box_lo if hasattr(box_lo, "__len__") else (box_lo,) * 3)]
+    for k in range(3):
+        o.box_lo[k] = lo[k]
+    o.box_size, o.grid, o.max_age = float(box_size), int(grid), int(max_age)
+    lib = _lib.load()
+    hcap = history.capacity if history is not None else 0
+    ws = workspace(lib.splat_workspace_bytes(_lib.SPLAT_OP_ACCUMULATE, hcap, int(grid), 0), dev, "accumulate")
+    f, r = frame.struct(), out.struct()
+    h = history.struct() if history is not None else None
+    _lib.check(lib.splat_accumulate(ctypes.byref(f), ctypes.byref(h) if h is not None else None,
+                                    _ptr(history_age) if history is not None else None, ctypes.byref(o),
+                                    ctypes.byref(r), _ptr(out_age), _ptr(ws), ws.numel(), _stream()))
+    return out, out_age
+
+
 def unproject(src_cam, rgba: torch.Tensor, depth: torch.Tensor, radius_scale: float = 1.0, half: bool = True,
               out: Spheres | None = None) -> Spheres:
     """Eq. 1 unprojection of a premultiplied RGBA + depth image into spheres (splat_unproject)."""

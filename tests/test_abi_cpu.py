@@ -27,7 +27,7 @@ def test_library_exports_every_declared_symbol():
     lib = _lib.load()
     for name in declared_functions():
         assert hasattr(lib, name), name
-    assert lib.splat_version() == 102
+    assert lib.splat_version() == 103
 
 
 def test_sizes_are_pure_host_functions():
@@ -38,6 +38,11 @@ def test_sizes_are_pure_host_functions():
     assert lib.splat_workspace_bytes(_lib.SPLAT_OP_BUILD, 1 << 20, 0, 0) >= (1 << 20) * 16
     assert lib.splat_workspace_bytes(_lib.SPLAT_OP_BATCHED, 4, 0, 0) >= 4
     assert lib.splat_workspace_bytes(99, 1, 1, 1) == 0
+    # accumulation: the cell bitmap (grid^3 bits) and the tile counts of the history
+    assert lib.splat_workspace_bytes(_lib.SPLAT_OP_ACCUMULATE, 1 << 20, 256, 0) >= (256 ** 3) // 8 + 1024 * 4
+    assert lib.splat_workspace_bytes(_lib.SPLAT_OP_ACCUMULATE, 0, 1024, 0) >= (1024 ** 3) // 8
+    assert lib.splat_workspace_bytes(_lib.SPLAT_OP_ACCUMULATE, 10, 0, 0) == 0
+    assert lib.splat_workspace_bytes(_lib.SPLAT_OP_ACCUMULATE, 10, 1025, 0) == 0
 
 
 def test_struct_layouts_match_the_header():
@@ -47,6 +52,7 @@ def test_struct_layouts_match_the_header():
     assert ctypes.sizeof(_lib.splat_volume) == 32
     assert ctypes.sizeof(_lib.splat_march_opts) == 32
     assert ctypes.sizeof(_lib.splat_codec) == 40
+    assert ctypes.sizeof(_lib.splat_accum_opts) == 40
     assert ctypes.sizeof(_lib.splat_batch_job) == 3 * 8 + 2 * 4 + 112 + 2 * 8
 
 
@@ -153,3 +159,58 @@ def test_raymarch_option_validation():
             setattr(o, k, val)
         got, msg = _err(lib.splat_raymarch(ctypes.byref(v), ctypes.byref(cam), ctypes.byref(o), out, out, None))
         assert got == code, (vol_kw, opt_kw, msg)
+
+
+def _fake_set(base, cap=64, dtype=_lib.SPLAT_F16, src=True):
+    """A sphere set at fake device addresses, one 1 MiB region per array."""
+    s = _lib.splat_spheres()
+    s.centre_radius, s.rgba, s.count, s.capacity, s.rgba_dtype = base, base + (1 << 20), base + (2 << 20), cap, dtype
+    s.src_index = base + (3 << 20) if src else None
+    return s
+
+
+def test_accumulate_validation():
+    """Every argument of splat_accumulate is checked on the host; with valid ones and no GPU, ENODEV."""
+    import torch
+    lib = _lib.load()
+    frame, hist, out = _fake_set(1 << 30), _fake_set(2 << 30), _fake_set(3 << 30)
+    hage, oage, ws = ctypes.c_void_p((4 << 30)), ctypes.c_void_p(5 << 30), ctypes.c_void_p(6 << 30)
+
+    def opts(**kw):
+        o = _lib.splat_accum_opts()
+        o.box_lo[0], o.box_lo[1], o.box_lo[2] = -1.0, 0.0, 0.5
+        o.box_size, o.grid, o.max_age = 2.0, 64, 3
+        for k, v in kw.items():
+            setattr(o, k, v)
+        return o
+
+    need = lib.splat_workspace_bytes(_lib.SPLAT_OP_ACCUMULATE, hist.capacity, 64, 0)
+
+    def call(f=frame, h=hist, ha=hage, o=None, r=out, ra=oage, w=ws, wb=need):
+        o = o or opts()
+        return _err(lib.splat_accumulate(ctypes.byref(f), ctypes.byref(h) if h is not None else None, ha,
+                                         ctypes.byref(o), ctypes.byref(r), ra, w, wb, None))
+
+    assert call(o=opts(grid=0))[0] == _lib.SPLAT_EINVAL
+    assert call(o=opts(grid=1025))[0] == _lib.SPLAT_EINVAL
+    assert call(o=opts(max_age=256))[0] == _lib.SPLAT_EINVAL
+    assert call(o=opts(max_age=-1))[0] == _lib.SPLAT_EINVAL
+    assert call(o=opts(box_size=0.0))[0] == _lib.SPLAT_EINVAL
+    assert call(o=opts(box_size=math.inf))[0] == _lib.SPLAT_EINVAL
+    assert call(ha=None)[0] == _lib.SPLAT_EINVAL
+    assert call(ra=None)[0] == _lib.SPLAT_EINVAL
+    assert call(h=_fake_set(2 << 30, dtype=_lib.SPLAT_F32))[0] == _lib.SPLAT_EINVAL
+    assert call(r=_fake_set(3 << 30, dtype=_lib.SPLAT_F32))[0] == _lib.SPLAT_EINVAL
+    assert call(f=_fake_set(1 << 30, src=False))[0] == _lib.SPLAT_EINVAL  # out wants src_index
+    assert call(r=_fake_set(2 << 30))[0] == _lib.SPLAT_EINVAL  # out is the history
+    alias = _fake_set(3 << 30)
+    alias.count = frame.count
+    assert call(r=alias)[0] == _lib.SPLAT_EINVAL  # out count is the frame's
+    assert call(ra=ctypes.c_void_p(hage.value + 8))[0] == _lib.SPLAT_EINVAL  # out_age inside history_age
+    assert call(wb=need - 1)[0] == _lib.SPLAT_ENOSPC
+    assert call(w=None)[0] == _lib.SPLAT_ENOSPC
+    if not torch.cuda.is_available():
+        assert call()[0] == _lib.SPLAT_ENODEV
+        # no history: the workspace for capacity 0 suffices
+        need0 = lib.splat_workspace_bytes(_lib.SPLAT_OP_ACCUMULATE, 0, 64, 0)
+        assert call(h=None, ha=None, wb=need0)[0] == _lib.SPLAT_ENODEV

@@ -22,10 +22,13 @@ def sp():
 
 @pytest.fixture(scope="module")
 def client(sp):
+    """The client frame's spheres from the oracle's unprojection (CPU), uploaded:
+    both sides of every comparison start from the same oracle-made arrays."""
     rgba, depth, src, dst = synth.source_image(synth.CLIENT_FRAME)
-    s = sp.unproject(src, torch.from_numpy(rgba).to("cuda:0"), torch.from_numpy(depth).to("cuda:0"), 1.0, True)
+    cr, col, _ = oracle.unproject(src, rgba, depth, 1.0, True)
+    s = sp.spheres_from_tensors(torch.from_numpy(cr).to("cuda:0"), torch.from_numpy(col).to("cuda:0"))
     torch.cuda.synchronize()
-    return s, src, dst
+    return s, src, dst, cr, col
 
 
 def r_unit_of(src):
@@ -35,14 +38,13 @@ def r_unit_of(src):
 
 @pytest.mark.parametrize("half_out", [True, False])
 def test_codec_bit_exact_on_the_client_frame(sp, client, half_out):
-    s, src, _ = client
+    s, src, _, cr, k16 = client
     ru = r_unit_of(src)
     n = s.n()
+    assert n == cr.shape[0]
     print(f"codec encode/decode {n} spheres, half out {half_out}", flush=True)
     pos, col = sp.encode_samples(s, LO, SIZE, ru)
-    cr = s.centre_radius[:n].cpu().numpy()
-    k = s.rgba[:n].cpu().numpy().astype(np.float64)
-    opos, ocol = oracle.encode(cr, k, LO, SIZE, ru)
+    opos, ocol = oracle.encode(cr, k16.astype(np.float64), LO, SIZE, ru)
     gpos = pos[:n].cpu().numpy().view(np.uint64)
     gcol = col[:n].cpu().numpy().view(np.uint32)
     assert np.array_equal(gpos, opos), f"{(gpos != opos).sum()} position words differ"
@@ -68,9 +70,8 @@ def test_codec_bit_exact_on_the_client_frame(sp, client, half_out):
 def test_client_path_on_decoded_samples(sp, client):
     """Decoded spheres traced on the GPU match the oracle on the same decoded
     spheres; the image stays close to the one from the unquantised spheres."""
-    s, src, dst = client
+    s, src, dst, cr, k16 = client
     ru = r_unit_of(src)
-    n = s.n()
     pos, col = sp.encode_samples(s, LO, SIZE, ru)
     d = sp.decode_samples(pos, col, s.count, LO, SIZE, ru, half=True)
     bvh = sp.build_bvh(d)
@@ -79,8 +80,12 @@ def test_client_path_on_decoded_samples(sp, client):
     torch.cuda.synchronize()
     rng = np.random.default_rng(11)
     pix = rng.integers(0, dst.width * dst.height, 2000)
-    dcr = d.centre_radius[:n].cpu().numpy()
-    dcol = d.rgba[:n].cpu().numpy()
+    # the oracle's side: its own encode and decode of its own spheres (decoded
+    # colours rounded to half, as the GPU stores them)
+    opos, ocol = oracle.encode(cr, k16.astype(np.float64), LO, SIZE, ru)
+    dcr, _ = oracle.decode(opos, ocol, LO, SIZE, ru)
+    b = np.stack([(ocol >> (8 * ch)) & 0xFF for ch in range(4)], axis=1).astype(np.float64) / 255.0
+    dcol = b.astype(np.float16)  # double -> half, round to nearest even
     g = img.cpu().numpy().reshape(-1, 4)[pix]
     h = hits.cpu().numpy().reshape(-1)[pix]
     assert_parity(compare(g, h, oracle.render(dcr, dcol, dst, pixels=pix)), exempt_frac=1e-4, context="decoded")
@@ -89,7 +94,7 @@ def test_client_path_on_decoded_samples(sp, client):
 
 
 def test_codec_rejects_bad_parameters(sp, client):
-    s, src, _ = client
+    s, src = client[0], client[1]
     with pytest.raises(sp.SplatError):
         sp.encode_samples(s, LO, 0.0, 1e-3)
     with pytest.raises(sp.SplatError):
