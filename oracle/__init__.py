@@ -96,8 +96,11 @@ def _load():
         lib.orc_volume_sample.argtypes = [_P, ctypes.c_int32, _P]
         lib.orc_volume_sample.restype = ctypes.c_double
         lib.orc_raymarch.argtypes = [_P, ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.POINTER(_Cam),
-                                     ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double, _P,
-                                     ctypes.c_int64, _P]
+                                     ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_double, ctypes.c_double, _P, ctypes.c_int64, _P]
+        lib.orc_unproject_policy.argtypes = [ctypes.POINTER(_Cam), _P, _P, _P, ctypes.c_int32, ctypes.c_double,
+                                             ctypes.c_double, ctypes.c_double, _P, _P, _P, _P]
+        lib.orc_unproject_policy.restype = ctypes.c_int64
         lib.orc_raymarch.restype = ctypes.c_int
         lib.orc_encode_position.argtypes = [_P, ctypes.c_double, _P, ctypes.c_double, ctypes.c_double]
         lib.orc_encode_position.restype = ctypes.c_uint64
@@ -142,6 +145,36 @@ def unproject(cam, rgba: np.ndarray, depth: np.ndarray, radius_scale: float, hal
     c = _cam(cam)
     n = _load().orc_unproject(ctypes.byref(c), rgba.ctypes.data, depth.ctypes.data, float(radius_scale),
                               cr.ctypes.data, _ptr(col32), _ptr(col16), idx.ctypes.data)
+    col = col16.view(np.float16) if half else col32
+    return cr[:n].copy(), col[:n].copy(), idx[:n].copy()
+
+
+RADIUS_FOOTPRINT, RADIUS_OPACITY, RADIUS_INTERVAL = 0, 1, 2
+
+
+def unproject_policy(cam, rgba: np.ndarray, depth: np.ndarray, mode: int, radius_scale: float = 1.0,
+                     opacity_floor: float = 0.05, interval_scale: float = 1.0, interval: np.ndarray | None = None,
+                     half: bool = True):
+    """Unprojection with a radius policy (Sec. 7): footprint, opacity (r = s fp sqrt(max(A, floor))) or
+    interval (centre at the depth interval's midpoint, r = max(s fp, kappa half-length)).
+    Returns (centre_radius float32 [N][4], colour [N][4] float16 or float32, src_index uint32 [N])."""
+    H, W = int(cam.height), int(cam.width)
+    rgba = np.ascontiguousarray(rgba, dtype=np.float32).reshape(H, W, 4)
+    depth = np.ascontiguousarray(depth, dtype=np.float32).reshape(H, W)
+    itv = None
+    if mode == RADIUS_INTERVAL:
+        itv = np.ascontiguousarray(interval, dtype=np.float32).reshape(H, W, 2)
+    cap = H * W
+    cr = np.zeros((cap, 4), dtype=np.float32)
+    col32 = None if half else np.zeros((cap, 4), dtype=np.float32)
+    col16 = np.zeros((cap, 4), dtype=np.uint16) if half else None
+    idx = np.zeros(cap, dtype=np.uint32)
+    c = _cam(cam)
+    # the floor and kappa are float parameters of the GPU call: use their float values
+    n = _load().orc_unproject_policy(ctypes.byref(c), rgba.ctypes.data, depth.ctypes.data, _ptr(itv), int(mode),
+                                     float(np.float32(radius_scale)), float(np.float32(opacity_floor)),
+                                     float(np.float32(interval_scale)), cr.ctypes.data, _ptr(col32), _ptr(col16),
+                                     idx.ctypes.data)
     col = col16.view(np.float16) if half else col32
     return cr[:n].copy(), col[:n].copy(), idx[:n].copy()
 
@@ -225,6 +258,8 @@ MARCH_STEP = 0.5          # voxels between samples
 MARCH_ALPHA_SCALE = 0.05  # sample alpha = clamp(0.05 v, 0, 1)
 MARCH_DEPTH_ALPHA = 0.5   # depth = first sample at which A >= 0.5
 MARCH_STOP_ALPHA = 0.999  # stop after the sample at which A >= 0.999
+MARCH_INTERVAL_LO = 0.25  # depth interval: first sample at which A >= 0.25 ...
+MARCH_INTERVAL_HI = 0.75  # ... to the first at which A >= 0.75 (or the last sample taken)
 
 
 def volume_sample(vol: np.ndarray, p) -> float:
@@ -236,9 +271,10 @@ def volume_sample(vol: np.ndarray, p) -> float:
 
 def raymarch(vol: np.ndarray, box_lo: float, box_size: float, cam, pixels=None, step: float = MARCH_STEP,
              alpha_scale: float = MARCH_ALPHA_SCALE, depth_alpha: float = MARCH_DEPTH_ALPHA,
-             stop_alpha: float = MARCH_STOP_ALPHA) -> dict:
-    """Server ray marcher in double precision.  Returns {"rgba": [k][4] premultiplied, "depth": [k]}
-    (float64) for all pixels (row-major) or the given pixel indices."""
+             stop_alpha: float = MARCH_STOP_ALPHA, interval_lo: float = MARCH_INTERVAL_LO,
+             interval_hi: float = MARCH_INTERVAL_HI) -> dict:
+    """Server ray marcher in double precision.  Returns {"rgba": [k][4] premultiplied, "depth": [k],
+    "interval": [k][2] (t_lo, t_hi)} (float64) for all pixels (row-major) or the given pixel indices."""
     v = np.ascontiguousarray(vol, dtype=np.float32)
     n = int(v.shape[0])
     assert v.shape == (n, n, n)
@@ -248,11 +284,11 @@ def raymarch(vol: np.ndarray, box_lo: float, box_size: float, cam, pixels=None, 
     else:
         pix = np.ascontiguousarray(pixels, dtype=np.int64)
         count = len(pix)
-    out = np.zeros((count, 5), dtype=np.float64)
+    out = np.zeros((count, 7), dtype=np.float64)
     _load().orc_raymarch(v.ctypes.data, n, float(box_lo), float(box_size), ctypes.byref(c), float(step),
-                         float(alpha_scale), float(depth_alpha), float(stop_alpha),
-                         None if pix is None else pix.ctypes.data, count, out.ctypes.data)
-    return {"rgba": out[:, :4].copy(), "depth": out[:, 4].copy()}
+                         float(alpha_scale), float(depth_alpha), float(stop_alpha), float(interval_lo),
+                         float(interval_hi), None if pix is None else pix.ctypes.data, count, out.ctypes.data)
+    return {"rgba": out[:, :4].copy(), "depth": out[:, 4].copy(), "interval": out[:, 5:7].copy()}
 
 
 CODEC_POS_BITS = 18      # per axis

@@ -13,6 +13,8 @@
  *
  *   orc_unproject   Sec. 4.1, Eq. 1: p = o + d t_i per pixel, a footprint
  *                   radius, compaction of pixels without a sample.
+ *   orc_unproject_policy  the same with the radius set by opacity or by a
+ *                   depth interval (Sec. 7).
  *   orc_render      Sec. 4.1 / Fig. 2: the samples as coloured
  *                   semi-transparent spheres, traced from a new camera,
  *                   composited front to back, stopping at a given alpha.
@@ -111,6 +113,66 @@ int64_t orc_unproject(const orc_camera *cam, const float *rgba, const float *dep
             for (int k = 0; k < 3; ++k) centre_radius[4 * n + k] = (float)(cam->eye[k] + d[k] * t);
             double footprint = 2.0 * t * cam->tan_half_fov_y / (double)H;
             centre_radius[4 * n + 3] = (float)(radius_scale * footprint);
+            double col[4];
+            for (int k = 0; k < 3; ++k) {
+                double kc = (double)rgba[4 * i + k] / A;
+                col[k] = kc < 0.0 ? 0.0 : (kc > 1.0 ? 1.0 : kc);
+            }
+            col[3] = A;
+            for (int k = 0; k < 4; ++k) {
+                if (col_f32) col_f32[4 * n + k] = (float)col[k];
+                if (col_f16) col_f16[4 * n + k] = orc_half_bits(col[k]);
+            }
+            if (src_index) src_index[n] = (uint32_t)i;
+            ++n;
+        }
+    }
+    return n;
+}
+
+/*
+ * Radius policies (Sec. 7 suggests varying the radius with the sample's
+ * opacity, or with how uncertain its depth is, smearing uncertain samples
+ * over an interval along the ray; no rule is given).  The readings here:
+ *   - mode 0, footprint: as orc_unproject, r = s fp(t), fp(t) = 2 t tan(fov/2) / H;
+ *   - mode 1, opacity: r = s fp(t) sqrt(max(A, a_floor)): the sphere's disc
+ *     area grows in proportion to the pixel's opacity (the paper's own rule,
+ *     radius 0 without opacity and the full footprint with it, is the step
+ *     version of this);
+ *   - mode 2, interval: the pixel's depth interval [t_lo, t_hi] (from the
+ *     marcher) replaces the single depth: the centre sits at its midpoint
+ *     t_c = (t_lo + t_hi) / 2 on the ray and r = max(s fp(t_c),
+ *     kappa (t_hi - t_lo) / 2), so the sphere covers the interval.  A pixel
+ *     holds a sample iff the depth rule holds and 0 < t_lo <= t_hi, both finite.
+ * Colour, alpha, order and compaction are those of orc_unproject.
+ */
+int64_t orc_unproject_policy(const orc_camera *cam, const float *rgba, const float *depth, const float *interval,
+                             int32_t mode, double radius_scale, double a_floor, double kappa, float *centre_radius,
+                             float *col_f32, uint16_t *col_f16, uint32_t *src_index)
+{
+    const int64_t W = cam->width, H = cam->height;
+    int64_t n = 0;
+    for (int64_t y = 0; y < H; ++y) {
+        for (int64_t x = 0; x < W; ++x) {
+            const int64_t i = y * W + x;
+            double t = depth[i];
+            const double A = rgba[4 * i + 3];
+            if (!(isfinite(t) && t > 0.0 && A > 0.0)) continue;
+            double half_len = 0.0;
+            if (mode == 2) {
+                const double lo = interval[2 * i], hi = interval[2 * i + 1];
+                if (!(isfinite(lo) && isfinite(hi) && lo > 0.0 && hi >= lo)) continue;
+                t = 0.5 * (lo + hi);
+                half_len = 0.5 * (hi - lo);
+            }
+            double d[3];
+            orc_ray(cam, x, y, d);
+            for (int k = 0; k < 3; ++k) centre_radius[4 * n + k] = (float)(cam->eye[k] + d[k] * t);
+            const double footprint = 2.0 * t * cam->tan_half_fov_y / (double)H;
+            double r = radius_scale * footprint;
+            if (mode == 1) r = r * sqrt(A > a_floor ? A : a_floor);
+            if (mode == 2 && kappa * half_len > r) r = kappa * half_len;
+            centre_radius[4 * n + 3] = (float)r;
             double col[4];
             for (int k = 0; k < 3; ++k) {
                 double kc = (double)rgba[4 * i + k] / A;
@@ -510,7 +572,11 @@ int64_t orc_pixels_near(const orc_camera *cam, const double centre[3], double ra
  *   - front to back: w = (1 - A) s, C += w colour, A += w; the depth is the
  *     first t_j at which A >= depth_alpha (infinite if never); marching
  *     stops after the sample at which A >= stop_alpha;
- *   - output: premultiplied (C, A) and depth, as float.
+ *   - the depth interval (for the interval radius policy, Sec. 7): t_lo is
+ *     the first t_j at which A >= interval_lo, t_hi the first at which
+ *     A >= interval_hi, or the last t_j taken if A never gets there (both
+ *     infinite if A never reaches interval_lo);
+ *   - output: premultiplied (C, A), depth and interval, as float.
  */
 
 /* Trilinear value at normalised position p in [0,1]^3 (clamp to edge):
@@ -547,7 +613,7 @@ static double orc_clamp(double v, double lo, double hi) { return v < lo ? lo : (
 /* One pixel of the marcher; returns the number of samples taken. */
 static int64_t orc_march_pixel(const float *vol, int32_t n, double lo, double size, const orc_camera *cam,
                                int64_t x, int64_t y, double step, double alpha_scale, double depth_alpha,
-                               double stop_alpha, double out[5])
+                               double stop_alpha, double interval_lo, double interval_hi, double out[7])
 {
     double d[3];
     orc_ray(cam, x, y, d);
@@ -563,7 +629,7 @@ static int64_t orc_march_pixel(const float *vol, int32_t n, double lo, double si
         if (ta > t_in) t_in = ta;
         if (tb < t_out) t_out = tb;
     }
-    double C[3] = {0.0, 0.0, 0.0}, A = 0.0, depth = INFINITY;
+    double C[3] = {0.0, 0.0, 0.0}, A = 0.0, depth = INFINITY, t_lo = INFINITY, t_hi = INFINITY, t_last = INFINITY;
     int64_t taken = 0;
     if (t_in < t_out) {
         const double dt = step * size / (double)n;
@@ -581,19 +647,24 @@ static int64_t orc_march_pixel(const float *vol, int32_t n, double lo, double si
             C[2] += w * (1.0 - u);
             A += w;
             ++taken;
+            t_last = t;
             if (depth == INFINITY && A >= depth_alpha) depth = t;
+            if (t_lo == INFINITY && A >= interval_lo) t_lo = t;
+            if (t_hi == INFINITY && A >= interval_hi) t_hi = t;
             if (A >= stop_alpha) break;
         }
     }
-    out[0] = C[0]; out[1] = C[1]; out[2] = C[2]; out[3] = A; out[4] = depth;
+    /* an interval that opened but never reached interval_hi closes at the last sample taken */
+    if (t_lo != INFINITY && t_hi == INFINITY) t_hi = t_last;
+    out[0] = C[0]; out[1] = C[1]; out[2] = C[2]; out[3] = A; out[4] = depth; out[5] = t_lo; out[6] = t_hi;
     return taken;
 }
 
 /* The marcher over all pixels (pixels == NULL) or a list of pixel indices;
- * out is double [count][5]: C (3), A, depth.  Returns 0. */
+ * out is double [count][7]: C (3), A, depth, t_lo, t_hi.  Returns 0. */
 int orc_raymarch(const float *vol, int32_t n, double lo, double size, const orc_camera *cam, double step,
-                 double alpha_scale, double depth_alpha, double stop_alpha, const int64_t *pixels, int64_t count,
-                 double *out)
+                 double alpha_scale, double depth_alpha, double stop_alpha, double interval_lo, double interval_hi,
+                 const int64_t *pixels, int64_t count, double *out)
 {
     const int64_t W = cam->width;
     const int64_t total = pixels ? count : W * (int64_t)cam->height;
@@ -601,7 +672,7 @@ int orc_raymarch(const float *vol, int32_t n, double lo, double size, const orc_
     for (int64_t k = 0; k < total; ++k) {
         const int64_t pix = pixels ? pixels[k] : k;
         orc_march_pixel(vol, n, lo, size, cam, pix % W, pix / W, step, alpha_scale, depth_alpha, stop_alpha,
-                        out + 5 * k);
+                        interval_lo, interval_hi, out + 7 * k);
     }
     return 0;
 }

@@ -12,6 +12,7 @@ import test_oracle_accum_pins as T
 import test_oracle_codec_pins as K
 import test_oracle_grad_pins as G
 import test_oracle_march_pins as M
+import test_oracle_policy_pins as R
 import test_oracle_pins as P
 
 SRC = open(os.path.join(os.path.dirname(oracle.__file__), "oracle.c")).read()
@@ -63,6 +64,19 @@ MUTANTS = [
      "double q = floor(((double)cr[a] - lo[0]) / size * (double)grid);"),
     ("accumulate rounds to the nearest cell", "double q = floor(((double)cr[a] - lo[a]) / size * (double)grid);",
      "double q = rint(((double)cr[a] - lo[a]) / size * (double)grid);"),
+    ("opacity radius linear in alpha", "if (mode == 1) r = r * sqrt(A > a_floor ? A : a_floor);",
+     "if (mode == 1) r = r * (A > a_floor ? A : a_floor);"),
+    ("opacity floor ignored", "if (mode == 1) r = r * sqrt(A > a_floor ? A : a_floor);",
+     "if (mode == 1) r = r * sqrt(A);"),
+    ("interval centre at its near end", "t = 0.5 * (lo + hi);", "t = lo;"),
+    ("interval full length as radius", "half_len = 0.5 * (hi - lo);", "half_len = hi - lo;"),
+    ("interval radius ignores the footprint", "if (mode == 2 && kappa * half_len > r) r = kappa * half_len;",
+     "if (mode == 2) r = kappa * half_len;"),
+    ("interval accepts a reversed interval", "if (!(isfinite(lo) && isfinite(hi) && lo > 0.0 && hi >= lo)) continue;",
+     "if (!(isfinite(lo) && isfinite(hi) && lo > 0.0)) continue;"),
+    ("interval left open", "if (t_lo != INFINITY && t_hi == INFINITY) t_hi = t_last;", ""),
+    ("interval opens at the depth alpha", "if (t_lo == INFINITY && A >= interval_lo) t_lo = t;",
+     "if (t_lo == INFINITY && A >= depth_alpha) t_lo = t;"),
     ("accumulate no lower clamp", "if (!(q >= 0.0)) q = 0.0; /* also NaN */", ""),
     ("accumulate no upper clamp", "if (q > (double)(grid - 1)) q = (double)(grid - 1);", ""),
     ("accumulate keeps one frame too long", "if ((int32_t)hist_age[i] + 1 > max_age) continue;",
@@ -99,6 +113,13 @@ PINS = [
     K.test_round_trip_error_bounds,
     K.test_decoded_values_encode_to_the_same_words,
     K.test_clamping_and_monotone_codes,
+    lambda: [R.test_marcher_interval_closed_form(v, st) for v, st in [(12.0, 0.999), (1.7, 0.999), (0.6, 0.999),
+                                                                       (0.3, 0.999), (1.7, 0.5), (0.05, 0.999)]],
+    R.test_policies_on_the_axis_hand_computed,
+    lambda: [R.test_invalid_interval_drops_the_pixel(b) for b in [(np.inf, 3.0), (1.0, np.inf), (3.0, 1.0),
+                                                                  (0.0, 1.0), (-1.0, 1.0), (np.nan, 1.0)]],
+    R.test_interval_centre_on_the_pixel_ray,
+    R.test_footprint_policy_is_the_plain_unprojection_and_full_opacity_too,
     T.test_hand_placed_cells,
     T.test_age_limits,
     lambda: [T.test_random_cells_by_construction(sd) for sd in (0, 1, 2)],
