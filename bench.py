@@ -10,6 +10,7 @@ HBM.  Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import copy
 import json
 import os
 import sys
@@ -201,6 +202,8 @@ def main():
             result["large_orbit"] = large_orbit(sp, torch, synth, dev, opts, args.orbit_frames)
         result["server_stage"] = server_stage(sp, torch, synth, dev, src, dst, opts, max(args.steps, 10))
         result["codec"] = codec(sp, torch, synth, sph, bvh, src, dst, opts, max(args.steps, 10))
+        result["accumulate"] = accumulate(sp, torch, synth, dev, src, sph, max(args.steps, 10))
+        result["radius_policies"] = radius_policies(sp, torch, synth, dev, src, dst, opts, max(args.steps, 10))
     if not args.no_bwd:
         result["fwd_bwd"] = fwd_bwd(sp, torch, synth, dev, args.steps)
     if args.batch_frames > 0:
@@ -371,6 +374,42 @@ def server_stage(sp, torch, synth, dev, src, dst, opts, reps):
             "stages_ms": {k: round(float(v), 4) for k, v in zip(("march", "unproject", "build", "trace"), med)}}
 
 
+def radius_policies(sp, torch, synth, dev, src, dst, opts, reps):
+    """The client frame under each radius policy: the GPU marcher with the depth interval, then
+    unproject (policy), build and trace; per policy the stage times, the mean composited hits and
+    the mean image change against the footprint policy."""
+    vol = torch.from_numpy(synth.volume_of(synth.CLIENT_FRAME)).to(dev)
+    rgba, depth, itv = sp.raymarch(vol, synth.BOX_LO, synth.BOX_SIZE, src, with_interval=True)
+    out, base = {}, None
+    for name, mode, kw in (("footprint", sp.SPLAT_RADIUS_FOOTPRINT, {}),
+                           ("opacity", sp.SPLAT_RADIUS_OPACITY, {"opacity_floor": 0.05}),
+                           ("interval", sp.SPLAT_RADIUS_INTERVAL, {"interval_scale": 0.1}),
+                           ("interval_wide", sp.SPLAT_RADIUS_INTERVAL, {"interval_scale": 0.25})):
+        sph = sp.unproject_policy(src, rgba, depth, mode, interval=itv, **kw)
+        bvh = sp.build_bvh(sph)
+        img, hits = sp.trace(bvh, sph, dst, opts)
+        t = np.array([_events(torch, [lambda: sp.unproject_policy(src, rgba, depth, mode, interval=itv, out=sph, **kw),
+                                      lambda: sp.build_bvh(sph, bvh),
+                                      lambda: sp.trace(bvh, sph, dst, opts, out=img, hits=hits)])
+                      for _ in range(reps)])
+        med = np.median(t, axis=0)
+        # wide spheres overlap many times over: a larger hit buffer saturates the stop in fewer passes
+        o16 = copy.copy(opts)
+        o16.kbuf = 16
+        sp.trace(bvh, sph, dst, o16, out=img, hits=hits)
+        t16 = float(np.median([_events(torch, [lambda: sp.trace(bvh, sph, dst, o16, out=img, hits=hits)])[0]
+                               for _ in range(reps)]))
+        if base is None:
+            base = img.clone()
+        r = sph.centre_radius[:sph.n(), 3]
+        out[name] = {"params": kw, "spheres": sph.n(), "median_radius": round(float(r.median()), 6),
+                     "mean_hits": round(float(hits.float().mean()), 3),
+                     "stages_ms": {k: round(float(v), 4) for k, v in zip(("unproject", "build", "trace"), med)},
+                     "trace_ms_kbuf16": round(t16, 4),
+                     "image_mean_abs_change": round(float((img - base).abs().mean()), 6)}
+    return out
+
+
 def codec(sp, torch, synth, sph, bvh, src, dst, opts, reps):
     """Wire format of the client frame's spheres: encode + decode time, bytes, and the image change."""
     ru = 2.0 * src.tan_half_fov_y / src.height
@@ -388,6 +427,30 @@ def codec(sp, torch, synth, sph, bvh, src, dst, opts, reps):
             "image_mean_abs_change": round(float(diff.mean()), 6), "image_max_abs_change": round(float(diff.max()), 4)}
 
 
+def accumulate(sp, torch, synth, dev, src, sph, reps, grid=256, max_age=8):
+    """Temporal accumulation at the client frame's source size: the frame seen
+    from a source view 10 degrees on merged with the current frame as history.
+    Algorithmic bytes: the frame read (28 B: centre + radius, half colour,
+    source index) and written with its age (29 B); per history sample the
+    centre and age read once (17 B); per survivor the colour and index read
+    (12 B) and 29 B written; the cell bitmap cleared (grid^3 / 8 B)."""
+    vol = synth.volume_of(synth.CLIENT_FRAME)
+    src1 = synth.rotated_camera(src, 10.0, 0.0)
+    rgba1, depth1 = synth.raycast(vol, src1)
+    frame = sp.unproject(src1, torch.from_numpy(rgba1).to(dev), torch.from_numpy(depth1).to(dev), 1.0, True)
+    age = torch.zeros((sph.capacity,), dtype=torch.uint8, device=dev)
+    out, out_age = sp.accumulate(frame, sph, age, synth.BOX_LO, synth.BOX_SIZE, grid, max_age)
+    t = np.array([_events(torch, [lambda: sp.accumulate(frame, sph, age, synth.BOX_LO, synth.BOX_SIZE, grid, max_age,
+                                                        out=out, out_age=out_age)])[0] for _ in range(reps)])
+    nf, nh, nm = frame.n(), sph.n(), out.n()
+    kept = nm - nf
+    alg = nf * (28 + 29) + nh * 17 + kept * (12 + 29) + grid ** 3 // 8
+    ms = float(np.median(t))
+    return {"frame_samples": nf, "history_samples": nh, "merged": nm, "grid": grid, "max_age": max_age,
+            "ms": round(ms, 4), "algorithmic_bytes": int(alg), "gb_s": round(alg / (ms * 1e-3) / 1e9, 1),
+            "frac_of_hbm_peak": round(alg / (ms * 1e-3) / 8e12, 4)}
+
+
 def _cpu_model() -> str:
     try:
         for line in open("/proc/cpuinfo"):
@@ -403,6 +466,7 @@ def cpu_baseline(rgba_np, depth_np, src, dst):
     Its spheres come from its own unprojection of the source image."""
     import oracle
     cr, col, _ = oracle.unproject(src, rgba_np, depth_np, 1.0, True)
+    n = cr.shape[0]
     rng = np.random.default_rng(0)
     table = oracle.sphere_table(cr, col)
     oracle.render_table(table, dst, pixels=rng.integers(0, dst.width * dst.height, 64))  # warm

@@ -177,9 +177,14 @@ typedef struct splat_volume {
  *   alpha_scale  sample alpha = clamp(alpha_scale v, 0, 1) [0.05]
  *   depth_alpha  the depth is the first sample at which A >= depth_alpha [0.5]
  *   stop_alpha   marching stops after the sample at which A >= stop_alpha [0.999]
+ *   interval_lo, interval_hi  the depth interval runs from the first sample
+ *                at which A >= interval_lo [0.25] to the first at which
+ *                A >= interval_hi [0.75], or to the last sample taken if A
+ *                never gets there; 0 < interval_lo <= interval_hi
  */
 typedef struct splat_march_opts {
     double step, alpha_scale, depth_alpha, stop_alpha;
+    double interval_lo, interval_hi;
 } splat_march_opts;
 
 /*
@@ -194,9 +199,14 @@ typedef struct splat_march_opts {
  *              input of splat_unproject
  *   out_depth  device float [height][width]: the depth t, +inf if A never
  *              reaches depth_alpha (no sample there)
+ *   out_interval  device float [height][width][2]: the depth interval
+ *              (t_lo, t_hi), both +inf if A never reaches interval_lo; or
+ *              NULL.  Sec. 7 suggests smearing samples whose depth is
+ *              uncertain over an interval along the ray; this is that
+ *              interval (splat_unproject_policy, SPLAT_RADIUS_INTERVAL)
  */
 int splat_raymarch(const splat_volume *vol, const splat_camera *cam, const splat_march_opts *opts, float *out_rgba,
-                   float *out_depth, void *stream);
+                   float *out_depth, float *out_interval, void *stream);
 
 /*
  * Sample codec of the wire format (Sec. 4.1: the quantised coordinate is
@@ -283,6 +293,41 @@ int splat_accumulate(const splat_spheres *frame, const splat_spheres *history, c
  */
 int splat_unproject(const splat_camera *src, const float *rgba_premul, const float *depth, float radius_scale,
                     const splat_spheres *out, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Radius policies of the unprojection (Sec. 7 suggests varying the radius
+ * with the sample's opacity, or smearing a sample whose depth is uncertain
+ * over an interval along the ray; the rules are this library's readings).
+ * fp(t) = 2 t tan_half_fov_y / height is the source pixel's footprint at t.
+ *   SPLAT_RADIUS_FOOTPRINT  r = radius_scale fp(t) (splat_unproject)
+ *   SPLAT_RADIUS_OPACITY    r = radius_scale fp(t) sqrt(max(A, opacity_floor)):
+ *                           the disc area in proportion to the opacity
+ *   SPLAT_RADIUS_INTERVAL   with the depth interval (t_lo, t_hi) of the pixel:
+ *                           the centre at t_c = (t_lo + t_hi) / 2 on the ray,
+ *                           r = max(radius_scale fp(t_c), interval_scale (t_hi - t_lo) / 2);
+ *                           a pixel then also needs 0 < t_lo <= t_hi, both finite
+ * All in double, each output rounded once to float.
+ */
+#define SPLAT_RADIUS_FOOTPRINT 0
+#define SPLAT_RADIUS_OPACITY 1
+#define SPLAT_RADIUS_INTERVAL 2
+
+typedef struct splat_radius_policy {
+    int32_t mode;           /* SPLAT_RADIUS_* */
+    float radius_scale;     /* >= 0 */
+    float opacity_floor;    /* (0, 1], SPLAT_RADIUS_OPACITY */
+    float interval_scale;   /* >= 0, SPLAT_RADIUS_INTERVAL */
+} splat_radius_policy;
+
+/*
+ * Unprojection with a radius policy: as splat_unproject (validity, colour,
+ * compaction, order), with the centre and radius of the policy.
+ *   interval  device float [height][width][2] (t_lo, t_hi), as written by
+ *             splat_raymarch; needed by SPLAT_RADIUS_INTERVAL, else ignored
+ */
+int splat_unproject_policy(const splat_camera *src, const float *rgba_premul, const float *depth,
+                           const float *interval, const splat_radius_policy *policy, const splat_spheres *out,
+                           void *ws, size_t ws_bytes, void *stream);
 
 /*
  * LBVH build (Sec. 4.1): scene bounds, 30-bit Morton codes of the centres,

@@ -11,11 +11,12 @@ SPLAT_OK, SPLAT_EINVAL, SPLAT_ENOSPC, SPLAT_ENODEV, SPLAT_EHIP, SPLAT_EUNSUPPORT
 SPLAT_F32, SPLAT_F16 = 0, 1
 SPLAT_ALPHA_CONSTANT, SPLAT_ALPHA_SOFT = 0, 1
 SPLAT_WALK_LANE, SPLAT_WALK_PACKET = 0, 1
+SPLAT_RADIUS_FOOTPRINT, SPLAT_RADIUS_OPACITY, SPLAT_RADIUS_INTERVAL = 0, 1, 2
 SPLAT_OP_UNPROJECT, SPLAT_OP_BUILD, SPLAT_OP_TRACE, SPLAT_OP_BACKWARD, SPLAT_OP_BATCHED, SPLAT_OP_ACCUMULATE = range(6)
 
 # every symbol include/splat.h declares
 EXPORTS = ["splat_workspace_bytes", "splat_bvh_bytes", "splat_raymarch", "splat_encode_samples",
-           "splat_decode_samples", "splat_accumulate", "splat_unproject", "splat_build_bvh", "splat_trace", "splat_trace_backward",
+           "splat_decode_samples", "splat_accumulate", "splat_unproject", "splat_unproject_policy", "splat_build_bvh", "splat_trace", "splat_trace_backward",
            "splat_trace_batched", "splat_last_error", "splat_version"]
 
 _P = ctypes.c_void_p
@@ -48,7 +49,12 @@ class splat_volume(ctypes.Structure):
 
 class splat_march_opts(ctypes.Structure):
     _fields_ = [("step", ctypes.c_double), ("alpha_scale", ctypes.c_double), ("depth_alpha", ctypes.c_double),
-                ("stop_alpha", ctypes.c_double)]
+                ("stop_alpha", ctypes.c_double), ("interval_lo", ctypes.c_double), ("interval_hi", ctypes.c_double)]
+
+
+class splat_radius_policy(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("radius_scale", ctypes.c_float), ("opacity_floor", ctypes.c_float),
+                ("interval_scale", ctypes.c_float)]
 
 
 class splat_codec(ctypes.Structure):
@@ -106,7 +112,10 @@ def load() -> ctypes.CDLL:
         lib.splat_version.argtypes = []
         lib.splat_version.restype = ctypes.c_int
         lib.splat_raymarch.argtypes = [ctypes.POINTER(splat_volume), ctypes.POINTER(splat_camera),
-                                       ctypes.POINTER(splat_march_opts), _P, _P, _P]
+                                       ctypes.POINTER(splat_march_opts), _P, _P, _P, _P]
+        lib.splat_unproject_policy.argtypes = [ctypes.POINTER(splat_camera), _P, _P, _P,
+                                               ctypes.POINTER(splat_radius_policy), ctypes.POINTER(splat_spheres), _P,
+                                               ctypes.c_size_t, _P]
         lib.splat_encode_samples.argtypes = [ctypes.POINTER(splat_spheres), ctypes.POINTER(splat_codec), _P, _P, _P]
         lib.splat_decode_samples.argtypes = [_P, _P, _P, ctypes.POINTER(splat_codec), ctypes.POINTER(splat_spheres),
                                              _P]
@@ -114,7 +123,8 @@ def load() -> ctypes.CDLL:
                                          ctypes.POINTER(splat_accum_opts), ctypes.POINTER(splat_spheres), _P, _P,
                                          ctypes.c_size_t, _P]
         for name in ("splat_raymarch", "splat_encode_samples", "splat_decode_samples", "splat_accumulate",
-                     "splat_unproject", "splat_build_bvh", "splat_trace", "splat_trace_backward",
+                     "splat_unproject", "splat_unproject_policy", "splat_build_bvh", "splat_trace",
+                     "splat_trace_backward",
                      "splat_trace_batched"):
             getattr(lib, name).restype = ctypes.c_int
         _lib = lib

@@ -118,7 +118,7 @@ int hip_status(hipError_t e, const char *what)
 
 extern "C" {
 
-int splat_version(void) { return 103; }
+int splat_version(void) { return 104; }
 
 const char *splat_last_error(void) { return g_err; }
 
@@ -152,7 +152,7 @@ size_t splat_workspace_bytes(int32_t op, uint32_t capacity, int32_t width, int32
 }
 
 int splat_raymarch(const splat_volume *vol, const splat_camera *cam, const splat_march_opts *opts, float *out_rgba,
-                   float *out_depth, void *stream)
+                   float *out_depth, float *out_interval, void *stream)
 {
     int rc;
     if (!vol || !vol->data) return fail(SPLAT_EINVAL, "volume is NULL");
@@ -161,13 +161,18 @@ int splat_raymarch(const splat_volume *vol, const splat_camera *cam, const splat
         return fail(SPLAT_EINVAL, "volume box must be finite with box_size > 0");
     if ((rc = check_camera(cam, "source"))) return rc;
     if (!out_rgba || !out_depth) return fail(SPLAT_EINVAL, "out_rgba/out_depth is NULL");
-    splat_march_opts o = {0.5, 0.05, 0.5, 0.999};
+    splat_march_opts o = {0.5, 0.05, 0.5, 0.999, 0.25, 0.75};
     if (opts) {
         if (opts->step != 0) o.step = opts->step;
         if (opts->alpha_scale != 0) o.alpha_scale = opts->alpha_scale;
         if (opts->depth_alpha != 0) o.depth_alpha = opts->depth_alpha;
         if (opts->stop_alpha != 0) o.stop_alpha = opts->stop_alpha;
+        if (opts->interval_lo != 0) o.interval_lo = opts->interval_lo;
+        if (opts->interval_hi != 0) o.interval_hi = opts->interval_hi;
     }
+    if (!std::isfinite(o.interval_lo) || !std::isfinite(o.interval_hi) || !(o.interval_lo > 0) ||
+        o.interval_hi < o.interval_lo)
+        return fail(SPLAT_EINVAL, "march interval alphas must satisfy 0 < interval_lo <= interval_hi");
     // the sample count per ray is at most sqrt(3) n / step
     if (!std::isfinite(o.step) || o.step < 0.01) return fail(SPLAT_EINVAL, "march step must be >= 0.01 voxel");
     if (!std::isfinite(o.alpha_scale) || o.alpha_scale < 0 || !std::isfinite(o.depth_alpha) ||
@@ -175,7 +180,7 @@ int splat_raymarch(const splat_volume *vol, const splat_camera *cam, const splat
         return fail(SPLAT_EINVAL, "march alpha options must be finite, alpha_scale >= 0");
     if ((rc = check_device())) return rc;
     return hip_status(launch_raymarch(vol->data, vol->n, vol->box_lo, vol->box_size, make_cam(*cam), o, out_rgba,
-                                      out_depth, static_cast<hipStream_t>(stream)),
+                                      out_depth, out_interval, static_cast<hipStream_t>(stream)),
                       "raymarch launch");
 }
 
@@ -276,23 +281,43 @@ int splat_accumulate(const splat_spheres *frame, const splat_spheres *history, c
                       "accumulate launch");
 }
 
-int splat_unproject(const splat_camera *src, const float *rgba_premul, const float *depth, float radius_scale,
-                    const splat_spheres *out, void *ws, size_t ws_bytes, void *stream)
+int splat_unproject_policy(const splat_camera *src, const float *rgba_premul, const float *depth,
+                           const float *interval, const splat_radius_policy *policy, const splat_spheres *out,
+                           void *ws, size_t ws_bytes, void *stream)
 {
     int rc;
     if ((rc = check_camera(src, "source"))) return rc;
     if (!rgba_premul || !depth) return fail(SPLAT_EINVAL, "rgba_premul/depth is NULL");
     if ((rc = check_spheres(out, true))) return rc;
-    if (!std::isfinite(radius_scale) || radius_scale < 0) return fail(SPLAT_EINVAL, "radius_scale must be >= 0");
+    if (!policy) return fail(SPLAT_EINVAL, "radius policy is NULL");
+    if (policy->mode != SPLAT_RADIUS_FOOTPRINT && policy->mode != SPLAT_RADIUS_OPACITY &&
+        policy->mode != SPLAT_RADIUS_INTERVAL)
+        return fail(SPLAT_EUNSUPPORTED, "unknown radius policy %d", policy->mode);
+    if (!std::isfinite(policy->radius_scale) || policy->radius_scale < 0)
+        return fail(SPLAT_EINVAL, "radius_scale must be >= 0");
+    if (policy->mode == SPLAT_RADIUS_OPACITY && !(policy->opacity_floor > 0 && policy->opacity_floor <= 1))
+        return fail(SPLAT_EINVAL, "opacity_floor must be in (0, 1]");
+    if (policy->mode == SPLAT_RADIUS_INTERVAL) {
+        if (!interval) return fail(SPLAT_EINVAL, "the interval policy needs the depth interval");
+        if (!std::isfinite(policy->interval_scale) || policy->interval_scale < 0)
+            return fail(SPLAT_EINVAL, "interval_scale must be >= 0");
+    }
     const int64_t pixels = (int64_t)src->width * src->height;
     if ((int64_t)out->capacity < pixels)
         return fail(SPLAT_ENOSPC, "sphere capacity %u < %lld source pixels", out->capacity, (long long)pixels);
     const size_t need = unproject_ws_bytes(pixels);
     if (!ws || ws_bytes < need) return fail(SPLAT_ENOSPC, "unproject workspace needs %zu bytes", need);
     if ((rc = check_device())) return rc;
-    return hip_status(launch_unproject(make_cam(*src), rgba_premul, depth, radius_scale, *out, ws,
+    return hip_status(launch_unproject(make_cam(*src), rgba_premul, depth, interval, *policy, *out, ws,
                                        static_cast<hipStream_t>(stream)),
                       "unproject launch");
+}
+
+int splat_unproject(const splat_camera *src, const float *rgba_premul, const float *depth, float radius_scale,
+                    const splat_spheres *out, void *ws, size_t ws_bytes, void *stream)
+{
+    const splat_radius_policy policy = {SPLAT_RADIUS_FOOTPRINT, radius_scale, 1.0f, 0.0f};
+    return splat_unproject_policy(src, rgba_premul, depth, nullptr, &policy, out, ws, ws_bytes, stream);
 }
 
 int splat_build_bvh(const splat_spheres *sph, const splat_bvh *bvh, int32_t refit_only, void *ws, size_t ws_bytes,

@@ -29,7 +29,8 @@ struct TraceArgs {
 };
 
 hipError_t launch_raymarch(const float *vol, int32_t n, double lo, double size, const Cam &cam,
-                           const splat_march_opts &o, float *out_rgba, float *out_depth, hipStream_t s);
+                           const splat_march_opts &o, float *out_rgba, float *out_depth, float *out_interval,
+                           hipStream_t s);
 
 hipError_t launch_encode(const splat_spheres &sph, const splat_codec &c, uint64_t *pos, uint32_t *col,
                          hipStream_t s);
@@ -44,8 +45,8 @@ hipError_t launch_accumulate(const splat_spheres &frame, const splat_spheres *hi
                              const splat_accum_opts &o, const splat_spheres &out, uint8_t *out_age, void *ws,
                              hipStream_t s);
 
-hipError_t launch_unproject(const Cam &cam, const float *rgba, const float *depth, float radius_scale,
-                            const splat_spheres &out, void *ws, hipStream_t s);
+hipError_t launch_unproject(const Cam &cam, const float *rgba, const float *depth, const float *interval,
+                            const splat_radius_policy &policy, const splat_spheres &out, void *ws, hipStream_t s);
 
 hipError_t launch_build(const splat_spheres &sph, const splat_bvh &bvh, bool refit_only, void *ws,
                         hipStream_t s);

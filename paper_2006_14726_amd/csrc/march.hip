@@ -1,7 +1,9 @@
 // Server stage before the client path (Sec. 4.1): a volume ray marcher
 // that writes, per source pixel, the front-to-back composited colour and one
 // representative depth t (the first sample at which the accumulated alpha
-// reaches depth_alpha), the image that splat_unproject turns into spheres.
+// reaches depth_alpha), the image that splat_unproject turns into spheres;
+// optionally also the depth interval [t_lo, t_hi] over which the alpha
+// climbs from interval_lo to interval_hi (for the interval radius policy).
 //
 // One thread per pixel, 16 x 16 pixels per workgroup (four 8 x 8 waves, so a
 // wave's rays stay close and its trilinear gathers hit the same cache
@@ -19,8 +21,8 @@ __device__ inline double clamp01(double v) { return v < 0.0 ? 0.0 : (v > 1.0 ? 1
 
 __global__ void __launch_bounds__(kMarchTile * kMarchTile)
 k_raymarch(const float *__restrict__ vol, int32_t n, double lo, double size, Cam cam, double step,
-           double alpha_scale, double depth_alpha, double stop_alpha, float4 *__restrict__ out_rgba,
-           float *__restrict__ out_depth)
+           double alpha_scale, double depth_alpha, double stop_alpha, double interval_lo, double interval_hi,
+           float4 *__restrict__ out_rgba, float *__restrict__ out_depth, float2 *__restrict__ out_interval)
 {
     const int lx = threadIdx.x & 7, ly = (threadIdx.x >> 3) & 7, w = threadIdx.x >> 6;
     const int px = blockIdx.x * kMarchTile + (w & 1) * 8 + lx;
@@ -45,7 +47,8 @@ k_raymarch(const float *__restrict__ vol, int32_t n, double lo, double size, Cam
         t_in = fmax(t_in, ta);
         t_out = fmin(t_out, tb);
     }
-    double C0 = 0.0, C1 = 0.0, C2 = 0.0, A = 0.0, depth = INFINITY;
+    double C0 = 0.0, C1 = 0.0, C2 = 0.0, A = 0.0, depth = INFINITY, t_lo = INFINITY, t_hi = INFINITY,
+           t_last = INFINITY;
     if (t_in < t_out) {
         const double dt = step * size / (double)n;
         // position in voxel-centre units, g = (eye + t d - lo) n / size - 1/2, as base + t slope
@@ -87,21 +90,29 @@ k_raymarch(const float *__restrict__ vol, int32_t n, double lo, double size, Cam
             C1 += wgt * (4.0 * u * (1.0 - u));
             C2 += wgt * (1.0 - u);
             A += wgt;
+            t_last = t;
             if (depth == INFINITY && A >= depth_alpha) depth = t;
+            if (t_lo == INFINITY && A >= interval_lo) t_lo = t;
+            if (t_hi == INFINITY && A >= interval_hi) t_hi = t;
             if (A >= stop_alpha) break;
         }
     }
+    // an interval that opened but never reached interval_hi closes at the last sample
+    if (t_lo != INFINITY && t_hi == INFINITY) t_hi = t_last;
     const size_t o = (size_t)py * cam.w + px;
     out_rgba[o] = make_float4((float)C0, (float)C1, (float)C2, (float)A);
     out_depth[o] = (float)depth;
+    if (out_interval) out_interval[o] = make_float2((float)t_lo, (float)t_hi);
 }
 
 hipError_t launch_raymarch(const float *vol, int32_t n, double lo, double size, const Cam &cam,
-                           const splat_march_opts &o, float *out_rgba, float *out_depth, hipStream_t s)
+                           const splat_march_opts &o, float *out_rgba, float *out_depth, float *out_interval,
+                           hipStream_t s)
 {
     const dim3 grid((cam.w + kMarchTile - 1) / kMarchTile, (cam.h + kMarchTile - 1) / kMarchTile);
     hipLaunchKernelGGL(k_raymarch, grid, dim3(kMarchTile * kMarchTile), 0, s, vol, n, lo, size, cam, o.step,
-                       o.alpha_scale, o.depth_alpha, o.stop_alpha, reinterpret_cast<float4 *>(out_rgba), out_depth);
+                       o.alpha_scale, o.depth_alpha, o.stop_alpha, o.interval_lo, o.interval_hi,
+                       reinterpret_cast<float4 *>(out_rgba), out_depth, reinterpret_cast<float2 *>(out_interval));
     return hipGetLastError();
 }
 

@@ -11,23 +11,28 @@
 
 namespace splat {
 
-__device__ inline bool pixel_valid(const float *__restrict__ rgba, const float *__restrict__ depth, int64_t p)
+// With a depth interval (interval policy) a pixel also needs 0 < t_lo <= t_hi, both finite.
+__device__ inline bool pixel_valid(const float *__restrict__ rgba, const float *__restrict__ depth,
+                                   const float *__restrict__ interval, int64_t p)
 {
     const float t = depth[p];
     const float A = rgba[4 * p + 3];
-    return isfinite(t) && t > 0.0f && A > 0.0f;
+    if (!(isfinite(t) && t > 0.0f && A > 0.0f)) return false;
+    if (!interval) return true;
+    const float2 iv = reinterpret_cast<const float2 *>(interval)[p];
+    return isfinite(iv.x) && isfinite(iv.y) && iv.x > 0.0f && iv.y >= iv.x;
 }
 
 __global__ void __launch_bounds__(kUnprojBlock)
-k_unproject_count(const float *__restrict__ rgba, const float *__restrict__ depth, int64_t pixels,
-                  uint32_t *__restrict__ tile_counts)
+k_unproject_count(const float *__restrict__ rgba, const float *__restrict__ depth, const float *__restrict__ interval,
+                  int64_t pixels, uint32_t *__restrict__ tile_counts)
 {
     const int64_t base = (int64_t)blockIdx.x * kUnprojTile;
     int c = 0;
 #pragma unroll
     for (int i = 0; i < kUnprojItems; ++i) {
         const int64_t p = base + i * kUnprojBlock + threadIdx.x;
-        if (p < pixels && pixel_valid(rgba, depth, p)) ++c;
+        if (p < pixels && pixel_valid(rgba, depth, interval, p)) ++c;
     }
     // wave reduction, then across the 4 waves of the block
     for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, kWave);
@@ -68,10 +73,12 @@ __global__ void __launch_bounds__(1024) k_unproject_scan(uint32_t *__restrict__ 
     if (threadIdx.x == 1023) *count = part[1023];
 }
 
-template <bool HALF>
+// MODE: SPLAT_RADIUS_FOOTPRINT, SPLAT_RADIUS_OPACITY or SPLAT_RADIUS_INTERVAL
+template <bool HALF, int MODE>
 __global__ void __launch_bounds__(kUnprojBlock)
-k_unproject_write(Cam cam, const float *__restrict__ rgba, const float *__restrict__ depth, int64_t pixels,
-                  double radius_scale, const uint32_t *__restrict__ tile_offsets, float4 *__restrict__ centre_radius,
+k_unproject_write(Cam cam, const float *__restrict__ rgba, const float *__restrict__ depth,
+                  const float *__restrict__ interval, int64_t pixels, double radius_scale, double a_floor,
+                  double kappa, const uint32_t *__restrict__ tile_offsets, float4 *__restrict__ centre_radius,
                   void *__restrict__ colour, uint32_t *__restrict__ src_index)
 {
     __shared__ uint32_t wcount[kUnprojItems][kUnprojBlock / kWave];
@@ -82,7 +89,7 @@ k_unproject_write(Cam cam, const float *__restrict__ rgba, const float *__restri
 #pragma unroll
     for (int i = 0; i < kUnprojItems; ++i) {
         const int64_t p = base + i * kUnprojBlock + threadIdx.x;
-        valid[i] = p < pixels && pixel_valid(rgba, depth, p);
+        valid[i] = p < pixels && pixel_valid(rgba, depth, MODE == SPLAT_RADIUS_INTERVAL ? interval : nullptr, p);
         const uint64_t m = __ballot(valid[i]);
         rank_in_wave[i] = (uint32_t)__popcll(m & ((1ull << lane) - 1));
         if (lane == 0) wcount[i][wave] = (uint32_t)__popcll(m);
@@ -101,13 +108,26 @@ k_unproject_write(Cam cam, const float *__restrict__ rgba, const float *__restri
         const int x = (int)(p % cam.w), y = (int)(p / cam.w);
         double d[3];
         pixel_ray(cam, x, y, d);
-        const double t = (double)depth[p];
+        double t = (double)depth[p], half_len = 0.0;
+        if (MODE == SPLAT_RADIUS_INTERVAL) {
+            // the interval's midpoint replaces the depth; the sphere covers kappa times its half length
+            const float2 iv = reinterpret_cast<const float2 *>(interval)[p];
+            t = 0.5 * ((double)iv.x + (double)iv.y);
+            half_len = 0.5 * ((double)iv.y - (double)iv.x);
+        }
         const float4 src = reinterpret_cast<const float4 *>(rgba)[p];
         float4 cr;
         cr.x = (float)(cam.eye[0] + d[0] * t);
         cr.y = (float)(cam.eye[1] + d[1] * t);
         cr.z = (float)(cam.eye[2] + d[2] * t);
-        cr.w = (float)(radius_scale * (2.0 * t * cam.tan_half / (double)cam.h));
+        double r = radius_scale * (2.0 * t * cam.tan_half / (double)cam.h);
+        if (MODE == SPLAT_RADIUS_OPACITY) {
+            // disc area in proportion to the opacity
+            const double A = (double)src.w;
+            r = r * sqrt(A > a_floor ? A : a_floor);
+        }
+        if (MODE == SPLAT_RADIUS_INTERVAL && kappa * half_len > r) r = kappa * half_len;
+        cr.w = (float)r;
         centre_radius[j] = cr;
         const double A = (double)src.w;
         double k[3] = {(double)src.x / A, (double)src.y / A, (double)src.z / A};
@@ -133,22 +153,42 @@ hipError_t launch_tile_scan(uint32_t *counts, uint32_t n, uint32_t *total, hipSt
     return hipGetLastError();
 }
 
-hipError_t launch_unproject(const Cam &cam, const float *rgba, const float *depth, float radius_scale,
-                            const splat_spheres &out, void *ws, hipStream_t s)
+template <int MODE>
+static void launch_write(const Cam &cam, const float *rgba, const float *depth, const float *interval, int64_t pixels,
+                         uint32_t tiles, const splat_radius_policy &pol, const uint32_t *tile_counts,
+                         const splat_spheres &out, hipStream_t s)
+{
+    const double rs = pol.radius_scale, fl = pol.opacity_floor, ka = pol.interval_scale;
+    if (out.rgba_dtype == SPLAT_F16)
+        hipLaunchKernelGGL((k_unproject_write<true, MODE>), dim3(tiles), dim3(kUnprojBlock), 0, s, cam, rgba, depth,
+                           interval, pixels, rs, fl, ka, tile_counts, reinterpret_cast<float4 *>(out.centre_radius),
+                           out.rgba, out.src_index);
+    else
+        hipLaunchKernelGGL((k_unproject_write<false, MODE>), dim3(tiles), dim3(kUnprojBlock), 0, s, cam, rgba, depth,
+                           interval, pixels, rs, fl, ka, tile_counts, reinterpret_cast<float4 *>(out.centre_radius),
+                           out.rgba, out.src_index);
+}
+
+hipError_t launch_unproject(const Cam &cam, const float *rgba, const float *depth, const float *interval,
+                            const splat_radius_policy &policy, const splat_spheres &out, void *ws, hipStream_t s)
 {
     const int64_t pixels = (int64_t)cam.w * cam.h;
     const uint32_t tiles = (uint32_t)((pixels + kUnprojTile - 1) / kUnprojTile);
     uint32_t *tile_counts = static_cast<uint32_t *>(ws);
-    hipLaunchKernelGGL(k_unproject_count, dim3(tiles), dim3(kUnprojBlock), 0, s, rgba, depth, pixels, tile_counts);
+    const float *itv = policy.mode == SPLAT_RADIUS_INTERVAL ? interval : nullptr;
+    hipLaunchKernelGGL(k_unproject_count, dim3(tiles), dim3(kUnprojBlock), 0, s, rgba, depth, itv, pixels,
+                       tile_counts);
     hipLaunchKernelGGL(k_unproject_scan, dim3(1), dim3(1024), 0, s, tile_counts, tiles, out.count);
-    if (out.rgba_dtype == SPLAT_F16)
-        hipLaunchKernelGGL(k_unproject_write<true>, dim3(tiles), dim3(kUnprojBlock), 0, s, cam, rgba, depth, pixels,
-                           (double)radius_scale, tile_counts, reinterpret_cast<float4 *>(out.centre_radius),
-                           out.rgba, out.src_index);
-    else
-        hipLaunchKernelGGL(k_unproject_write<false>, dim3(tiles), dim3(kUnprojBlock), 0, s, cam, rgba, depth, pixels,
-                           (double)radius_scale, tile_counts, reinterpret_cast<float4 *>(out.centre_radius),
-                           out.rgba, out.src_index);
+    switch (policy.mode) {
+    case SPLAT_RADIUS_OPACITY:
+        launch_write<SPLAT_RADIUS_OPACITY>(cam, rgba, depth, itv, pixels, tiles, policy, tile_counts, out, s);
+        break;
+    case SPLAT_RADIUS_INTERVAL:
+        launch_write<SPLAT_RADIUS_INTERVAL>(cam, rgba, depth, itv, pixels, tiles, policy, tile_counts, out, s);
+        break;
+    default:
+        launch_write<SPLAT_RADIUS_FOOTPRINT>(cam, rgba, depth, itv, pixels, tiles, policy, tile_counts, out, s);
+    }
     return hipGetLastError();
 }
 

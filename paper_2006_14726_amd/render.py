@@ -98,10 +98,12 @@ def alloc_spheres(capacity: int, device, half: bool = True) -> Spheres:
 
 def raymarch(volume: torch.Tensor, box_lo: float, box_size: float, cam, step: float = 0.5,
              alpha_scale: float = 0.05, depth_alpha: float = 0.5, stop_alpha: float = 0.999,
-             out_rgba: torch.Tensor | None = None, out_depth: torch.Tensor | None = None):
+             out_rgba: torch.Tensor | None = None, out_depth: torch.Tensor | None = None,
+             with_interval: bool = False, interval_lo: float = 0.25, interval_hi: float = 0.75,
+             out_interval: torch.Tensor | None = None):
     """Server stage (splat_raymarch): ray-march the float32 volume [n, n, n] (z, y, x) filling the cube
     [box_lo, box_lo + box_size]^3.  Returns (premultiplied rgba [H, W, 4], depth [H, W]), the input of
-    `unproject`."""
+    `unproject`, and with `with_interval` also the depth interval [H, W, 2] (t_lo, t_hi)."""
     _require_cuda(volume, "volume", torch.float32)
     n = int(volume.shape[0])
     if tuple(volume.shape) != (n, n, n):
@@ -120,9 +122,18 @@ def raymarch(volume: torch.Tensor, box_lo: float, box_size: float, cam, step: fl
     o = _lib.splat_march_opts()
     o.step, o.alpha_scale, o.depth_alpha, o.stop_alpha = float(step), float(alpha_scale), float(depth_alpha), \
         float(stop_alpha)
+    o.interval_lo, o.interval_hi = float(interval_lo), float(interval_hi)
+    if with_interval and out_interval is None:
+        out_interval = torch.empty((H, W, 2), dtype=torch.float32, device=volume.device)
+    if out_interval is not None:
+        _require_cuda(out_interval, "out_interval", torch.float32)
+        if tuple(out_interval.shape) != (H, W, 2):
+            raise ValueError(f"out_interval must be [{H}, {W}, 2]")
     c = _lib.camera_struct(cam)
     _lib.check(_lib.load().splat_raymarch(ctypes.byref(v), ctypes.byref(c), ctypes.byref(o), _ptr(out_rgba),
-                                          _ptr(out_depth), _stream()))
+                                          _ptr(out_depth), _ptr(out_interval), _stream()))
+    if with_interval or out_interval is not None:
+        return out_rgba, out_depth, out_interval
     return out_rgba, out_depth
 
 
@@ -207,6 +218,35 @@ def unproject(src_cam, rgba: torch.Tensor, depth: torch.Tensor, radius_scale: fl
     s = out.struct()
     _lib.check(lib.splat_unproject(ctypes.byref(cam), _ptr(rgba), _ptr(depth), float(radius_scale), ctypes.byref(s),
                                    _ptr(ws), ws.numel(), _stream()))
+    return out
+
+
+def unproject_policy(src_cam, rgba: torch.Tensor, depth: torch.Tensor, mode: int, radius_scale: float = 1.0,
+                     opacity_floor: float = 0.05, interval_scale: float = 1.0, interval: torch.Tensor | None = None,
+                     half: bool = True, out: Spheres | None = None) -> Spheres:
+    """Unprojection with a radius policy (splat_unproject_policy): SPLAT_RADIUS_FOOTPRINT, _OPACITY
+    (r = s fp sqrt(max(A, floor))) or _INTERVAL (centre at the depth interval's midpoint,
+    r = max(s fp, interval_scale half-length); needs `interval` [H, W, 2] from `raymarch`)."""
+    H, W = int(src_cam.height), int(src_cam.width)
+    _require_cuda(rgba, "rgba", torch.float32)
+    _require_cuda(depth, "depth", torch.float32)
+    if tuple(rgba.shape) != (H, W, 4) or tuple(depth.shape) != (H, W):
+        raise ValueError(f"rgba must be [{H}, {W}, 4] and depth [{H}, {W}]")
+    if interval is not None:
+        _require_cuda(interval, "interval", torch.float32)
+        if tuple(interval.shape) != (H, W, 2):
+            raise ValueError(f"interval must be [{H}, {W}, 2]")
+    if out is None:
+        out = alloc_spheres(H * W, rgba.device, half)
+    lib = _lib.load()
+    ws = workspace(lib.splat_workspace_bytes(_lib.SPLAT_OP_UNPROJECT, 0, W, H), rgba.device, "unproject")
+    pol = _lib.splat_radius_policy()
+    pol.mode, pol.radius_scale = int(mode), float(radius_scale)
+    pol.opacity_floor, pol.interval_scale = float(opacity_floor), float(interval_scale)
+    cam = _lib.camera_struct(src_cam)
+    s = out.struct()
+    _lib.check(lib.splat_unproject_policy(ctypes.byref(cam), _ptr(rgba), _ptr(depth), _ptr(interval),
+                                          ctypes.byref(pol), ctypes.byref(s), _ptr(ws), ws.numel(), _stream()))
     return out
 
 

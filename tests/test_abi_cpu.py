@@ -27,7 +27,7 @@ def test_library_exports_every_declared_symbol():
     lib = _lib.load()
     for name in declared_functions():
         assert hasattr(lib, name), name
-    assert lib.splat_version() == 103
+    assert lib.splat_version() == 104
 
 
 def test_sizes_are_pure_host_functions():
@@ -50,7 +50,8 @@ def test_struct_layouts_match_the_header():
     assert ctypes.sizeof(_lib.splat_spheres) == 8 + 8 + 4 + 4 + 8 + 8 + 8
     assert ctypes.sizeof(_lib.splat_trace_opts) == 40
     assert ctypes.sizeof(_lib.splat_volume) == 32
-    assert ctypes.sizeof(_lib.splat_march_opts) == 32
+    assert ctypes.sizeof(_lib.splat_march_opts) == 48
+    assert ctypes.sizeof(_lib.splat_radius_policy) == 16
     assert ctypes.sizeof(_lib.splat_codec) == 40
     assert ctypes.sizeof(_lib.splat_accum_opts) == 40
     assert ctypes.sizeof(_lib.splat_batch_job) == 3 * 8 + 2 * 4 + 112 + 2 * 8
@@ -149,7 +150,10 @@ def test_raymarch_option_validation():
                                  ({"box_size": 0.0}, {}, _lib.SPLAT_EINVAL),
                                  ({"box_lo": math.nan}, {}, _lib.SPLAT_EINVAL),
                                  ({}, {"step": 0.001}, _lib.SPLAT_EINVAL),
-                                 ({}, {"alpha_scale": -1.0}, _lib.SPLAT_EINVAL)]:
+                                 ({}, {"alpha_scale": -1.0}, _lib.SPLAT_EINVAL),
+                                 ({}, {"interval_lo": -0.1}, _lib.SPLAT_EINVAL),
+                                 ({}, {"interval_lo": 0.8, "interval_hi": 0.6}, _lib.SPLAT_EINVAL),
+                                 ({}, {"interval_hi": math.inf}, _lib.SPLAT_EINVAL)]:
         v = _lib.splat_volume()
         v.data, v.n, v.box_lo, v.box_size = 4096, 8, -0.25, 1.5
         for k, val in vol_kw.items():
@@ -157,7 +161,8 @@ def test_raymarch_option_validation():
         o = _lib.splat_march_opts()
         for k, val in opt_kw.items():
             setattr(o, k, val)
-        got, msg = _err(lib.splat_raymarch(ctypes.byref(v), ctypes.byref(cam), ctypes.byref(o), out, out, None))
+        got, msg = _err(lib.splat_raymarch(ctypes.byref(v), ctypes.byref(cam), ctypes.byref(o), out, out, None,
+                                           None))
         assert got == code, (vol_kw, opt_kw, msg)
 
 
@@ -214,3 +219,31 @@ def test_accumulate_validation():
         # no history: the workspace for capacity 0 suffices
         need0 = lib.splat_workspace_bytes(_lib.SPLAT_OP_ACCUMULATE, 0, 64, 0)
         assert call(h=None, ha=None, wb=need0)[0] == _lib.SPLAT_ENODEV
+
+
+def test_unproject_policy_validation():
+    import torch
+    lib = _lib.load()
+    cam = _lib.camera_struct(_Cam())
+    sph = _fake_set(1 << 30, cap=64)
+    fake = ctypes.c_void_p(4096)
+    need = lib.splat_workspace_bytes(_lib.SPLAT_OP_UNPROJECT, 0, 8, 8)
+
+    def call(mode=_lib.SPLAT_RADIUS_FOOTPRINT, scale=1.0, floor=0.05, kappa=1.0, interval=fake, pol=True):
+        p = _lib.splat_radius_policy()
+        p.mode, p.radius_scale, p.opacity_floor, p.interval_scale = mode, scale, floor, kappa
+        return _err(lib.splat_unproject_policy(ctypes.byref(cam), fake, fake, interval,
+                                               ctypes.byref(p) if pol else None, ctypes.byref(sph), fake, need, None))
+
+    assert call(pol=False)[0] == _lib.SPLAT_EINVAL
+    assert call(mode=3)[0] == _lib.SPLAT_EUNSUPPORTED
+    assert call(scale=-1.0)[0] == _lib.SPLAT_EINVAL
+    assert call(mode=_lib.SPLAT_RADIUS_OPACITY, floor=0.0)[0] == _lib.SPLAT_EINVAL
+    assert call(mode=_lib.SPLAT_RADIUS_OPACITY, floor=1.5)[0] == _lib.SPLAT_EINVAL
+    assert call(mode=_lib.SPLAT_RADIUS_INTERVAL, interval=None)[0] == _lib.SPLAT_EINVAL
+    assert call(mode=_lib.SPLAT_RADIUS_INTERVAL, kappa=-1.0)[0] == _lib.SPLAT_EINVAL
+    if not torch.cuda.is_available():
+        for mode in (0, 1, 2):
+            assert call(mode=mode)[0] == _lib.SPLAT_ENODEV
+        # the footprint and opacity policies do not need the interval
+        assert call(mode=_lib.SPLAT_RADIUS_OPACITY, interval=None)[0] == _lib.SPLAT_ENODEV
