@@ -6,8 +6,9 @@
 //
 // Five launches, all sized by capacities so they can be graph-captured:
 //   clear    zero the occupancy bitmap (a fill kernel, not a memset node)
-//   frame    one thread per frame sample: set its cell's bit (one atomic per
-//            distinct bitmap word of the wave) and copy it to the front of out
+//   frame    one thread per frame sample: set its cell's bit (a lane skips
+//            the atomic when its left neighbour has the same cell) and copy
+//            the sample to the front of out
 //   count    one block per 1024 history samples: survivors per tile
 //   scan     one block: exclusive prefix of the tile counts, total to ws
 //   scatter  one block per tile: rank of each survivor, copy with age + 1,
@@ -64,32 +65,27 @@ k_accum_frame(const float4 *__restrict__ cr, const void *__restrict__ rgba, cons
     const uint32_t n = min(*count, cap);
     const uint32_t i = blockIdx.x * kUnprojBlock + threadIdx.x;
     const bool valid = i < n;
-    uint32_t word = 0, bit = 0;
-    if (valid) {
-        const float4 c = cr[i];
-        const uint32_t cell = accum_cell(c, g);
-        word = cell >> 5;
-        bit = 1u << (cell & 31u);
-        if (i < out_cap) {
-            out_cr[i] = c;
-            reinterpret_cast<RowT *>(out_rgba)[i] = reinterpret_cast<const RowT *>(rgba)[i];
-            if (out_src) out_src[i] = src[i];
-            out_age[i] = 0;
-        }
+    const bool copy = valid && i < out_cap;
+    // all loads first, so that the cell and its atomic do not wait for the copy's stores
+    float4 c = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    RowT row{};
+    uint32_t s = 0;
+    if (valid) c = cr[i];
+    if (copy) {
+        row = reinterpret_cast<const RowT *>(rgba)[i];
+        if (out_src) s = src[i];
     }
-    // one atomic per distinct word of the wave: the lowest pending lane ORs
-    // in the bits of every pending lane with its word; each round retires at
-    // least that lane, so the loop ends within 64 rounds
-    bool pending = valid;
-    for (uint64_t pend = __ballot(pending); pend != 0; pend = __ballot(pending)) {
-        const int leader = __ffsll((unsigned long long)pend) - 1;
-        const uint32_t first = __shfl(word, leader, kWave);
-        const bool mine = pending && word == first;
-        uint32_t m = mine ? bit : 0u;
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) m |= __shfl_xor(m, off, kWave);
-        if ((int)__lane_id() == leader) atomicOr(&bits[first], m);
-        if (mine) pending = false;
+    const uint32_t cell = valid ? accum_cell(c, g) : 0xffffffffu;
+    // neighbouring samples often share a cell: a lane whose left neighbour
+    // has the same cell leaves the bit to it (cells are < 2^30, so the
+    // sentinel of an invalid lane never matches)
+    const uint32_t left = __shfl_up(cell, 1, kWave);
+    if (valid && (__lane_id() == 0 || left != cell)) atomicOr(&bits[cell >> 5], 1u << (cell & 31u));
+    if (copy) {
+        out_cr[i] = c;
+        reinterpret_cast<RowT *>(out_rgba)[i] = row;
+        if (out_src) out_src[i] = s;
+        out_age[i] = 0;
     }
 }
 
