@@ -433,7 +433,7 @@ def accumulate(sp, torch, synth, dev, src, sph, reps, grid=256, max_age=8):
     Algorithmic bytes: the frame read (28 B: centre + radius, half colour,
     source index) and written with its age (29 B); per history sample the
     centre and age read once (17 B); per survivor the colour and index read
-    (12 B) and 29 B written; the cell bitmap cleared (grid^3 / 8 B)."""
+    (12 B) and 29 B written; the cell map cleared (grid^3 B)."""
     vol = synth.volume_of(synth.CLIENT_FRAME)
     src1 = synth.rotated_camera(src, 10.0, 0.0)
     rgba1, depth1 = synth.raycast(vol, src1)
@@ -458,7 +458,7 @@ def accumulate(sp, torch, synth, dev, src, sph, reps, grid=256, max_age=8):
                               for _ in range(max(reps // 4, 3))]))
     nf, nh, nm = frame.n(), sph.n(), out.n()
     kept = nm - nf
-    alg = nf * (28 + 29) + nh * 17 + kept * (12 + 29) + grid ** 3 // 8
+    alg = nf * (28 + 29) + nh * 17 + kept * (12 + 29) + grid ** 3
     return {"frame_samples": nf, "history_samples": nh, "merged": nm, "grid": grid, "max_age": max_age,
             "call_ms": round(float(np.median(t)), 4), "device_ms": round(dev_ms, 4), "algorithmic_bytes": int(alg),
             "gb_s": round(alg / (dev_ms * 1e-3) / 1e9, 1), "frac_of_hbm_peak": round(alg / (dev_ms * 1e-3) / 8e12, 4)}

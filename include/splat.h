@@ -271,8 +271,9 @@ typedef struct splat_accum_opts {
  *   out_age      device uint8 [out->capacity]
  *   ws           device, >= splat_workspace_bytes(SPLAT_OP_ACCUMULATE,
  *                history capacity (0 without history), grid, 0): the cell
- *                bitmap (grid^3 / 8 bytes) and per-tile survivor counts.
- *                Calls that overlap on one workspace race.
+ *                map (one byte per cell: 16 MiB at grid 256, 1 GiB at 1024,
+ *                cleared by every call) and per-tile survivor counts;
+ *                16-byte aligned.  Calls that overlap on one workspace race.
  */
 int splat_accumulate(const splat_spheres *frame, const splat_spheres *history, const uint8_t *history_age,
                      const splat_accum_opts *opts, const splat_spheres *out, uint8_t *out_age, void *ws,

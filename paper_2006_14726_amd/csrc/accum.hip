@@ -5,10 +5,12 @@
 // new frame, each with age + 1.
 //
 // Five launches, all sized by capacities so they can be graph-captured:
-//   clear    zero the occupancy bitmap (a fill kernel, not a memset node)
-//   frame    one thread per frame sample: set its cell's bit (a lane skips
-//            the atomic when its left neighbour has the same cell) and copy
-//            the sample to the front of out
+//   clear    zero the occupancy map, one byte per cell (a fill kernel, not a
+//            memset node)
+//   frame    one thread per frame sample: store 1 in its cell's byte (all
+//            writers store the same value, so plain stores suffice; a bit
+//            map would need device-scope atomics, which cost several times
+//            more here) and copy the sample to the front of out
 //   count    one block per 1024 history samples: survivors per tile
 //   scan     one block: exclusive prefix of the tile counts, total to ws
 //   scatter  one block per tile: rank of each survivor, copy with age + 1,
@@ -43,9 +45,10 @@ __device__ inline uint32_t accum_cell(const float4 c, const AccumGrid &g)
     return (q3[2] * n + q3[1]) * n + q3[0];  // < 2^30 for grid <= 1024
 }
 
-__global__ void __launch_bounds__(kUnprojBlock) k_accum_clear(uint32_t *__restrict__ bits, uint32_t words)
+__global__ void __launch_bounds__(kUnprojBlock) k_accum_clear(uint4 *__restrict__ map, uint32_t chunks)
 {
-    for (uint32_t i = blockIdx.x * kUnprojBlock + threadIdx.x; i < words; i += gridDim.x * kUnprojBlock) bits[i] = 0u;
+    for (uint32_t i = blockIdx.x * kUnprojBlock + threadIdx.x; i < chunks; i += gridDim.x * kUnprojBlock)
+        map[i] = make_uint4(0u, 0u, 0u, 0u);
 }
 
 // Colour rows are copied as raw bits: 8 bytes (half4) or 16 bytes (float4).
@@ -57,7 +60,7 @@ struct Row {
 template <bool HALF>
 __global__ void __launch_bounds__(kUnprojBlock)
 k_accum_frame(const float4 *__restrict__ cr, const void *__restrict__ rgba, const uint32_t *__restrict__ src,
-              const uint32_t *__restrict__ count, uint32_t cap, AccumGrid g, uint32_t *__restrict__ bits,
+              const uint32_t *__restrict__ count, uint32_t cap, AccumGrid g, uint8_t *__restrict__ map,
               float4 *__restrict__ out_cr, void *__restrict__ out_rgba, uint32_t *__restrict__ out_src,
               uint8_t *__restrict__ out_age, uint32_t out_cap)
 {
@@ -75,12 +78,8 @@ k_accum_frame(const float4 *__restrict__ cr, const void *__restrict__ rgba, cons
         row = reinterpret_cast<const RowT *>(rgba)[i];
         if (out_src) s = src[i];
     }
-    const uint32_t cell = valid ? accum_cell(c, g) : 0xffffffffu;
-    // neighbouring samples often share a cell: a lane whose left neighbour
-    // has the same cell leaves the bit to it (cells are < 2^30, so the
-    // sentinel of an invalid lane never matches)
-    const uint32_t left = __shfl_up(cell, 1, kWave);
-    if (valid && (__lane_id() == 0 || left != cell)) atomicOr(&bits[cell >> 5], 1u << (cell & 31u));
+    // one byte per cell: every writer stores the same 1, so no atomic is needed
+    if (valid) map[accum_cell(c, g)] = 1u;
     if (copy) {
         out_cr[i] = c;
         reinterpret_cast<RowT *>(out_rgba)[i] = row;
@@ -90,16 +89,15 @@ k_accum_frame(const float4 *__restrict__ cr, const void *__restrict__ rgba, cons
 }
 
 __device__ inline bool accum_survives(const float4 *__restrict__ cr, const uint8_t *__restrict__ age, uint32_t i,
-                                      const AccumGrid &g, int max_age, const uint32_t *__restrict__ bits)
+                                      const AccumGrid &g, int max_age, const uint8_t *__restrict__ map)
 {
     if ((int)age[i] + 1 > max_age) return false;
-    const uint32_t cell = accum_cell(cr[i], g);
-    return ((bits[cell >> 5] >> (cell & 31u)) & 1u) == 0u;
+    return map[accum_cell(cr[i], g)] == 0u;
 }
 
 __global__ void __launch_bounds__(kUnprojBlock)
 k_accum_count(const float4 *__restrict__ cr, const uint8_t *__restrict__ age, const uint32_t *__restrict__ count,
-              uint32_t cap, AccumGrid g, int max_age, const uint32_t *__restrict__ bits,
+              uint32_t cap, AccumGrid g, int max_age, const uint8_t *__restrict__ map,
               uint32_t *__restrict__ tile_counts)
 {
     const uint32_t n = count ? min(*count, cap) : 0u;
@@ -108,7 +106,7 @@ k_accum_count(const float4 *__restrict__ cr, const uint8_t *__restrict__ age, co
 #pragma unroll
     for (int k = 0; k < kUnprojItems; ++k) {
         const uint32_t i = base + k * kUnprojBlock + threadIdx.x;
-        if (i < n && accum_survives(cr, age, i, g, max_age, bits)) ++c;
+        if (i < n && accum_survives(cr, age, i, g, max_age, map)) ++c;
     }
     for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, kWave);
     __shared__ int wsum[kUnprojBlock / kWave];
@@ -125,7 +123,7 @@ template <bool HALF>
 __global__ void __launch_bounds__(kUnprojBlock)
 k_accum_scatter(const float4 *__restrict__ cr, const void *__restrict__ rgba, const uint32_t *__restrict__ src,
                 const uint8_t *__restrict__ age, const uint32_t *__restrict__ count, uint32_t cap, AccumGrid g,
-                int max_age, const uint32_t *__restrict__ bits, const uint32_t *__restrict__ tile_offsets,
+                int max_age, const uint8_t *__restrict__ map, const uint32_t *__restrict__ tile_offsets,
                 const uint32_t *__restrict__ total, const uint32_t *__restrict__ frame_count, uint32_t frame_cap,
                 float4 *__restrict__ out_cr, void *__restrict__ out_rgba, uint32_t *__restrict__ out_src,
                 uint8_t *__restrict__ out_age, uint32_t out_cap, uint32_t *__restrict__ out_count)
@@ -145,7 +143,7 @@ k_accum_scatter(const float4 *__restrict__ cr, const void *__restrict__ rgba, co
 #pragma unroll
     for (int k = 0; k < kUnprojItems; ++k) {
         const uint32_t i = base + k * kUnprojBlock + threadIdx.x;
-        keep[k] = i < n && accum_survives(cr, age, i, g, max_age, bits);
+        keep[k] = i < n && accum_survives(cr, age, i, g, max_age, map);
         const uint64_t m = __ballot(keep[k]);
         rank_in_wave[k] = (uint32_t)__popcll(m & ((1ull << lane) - 1));
         if (lane == 0) wcount[k][wave] = (uint32_t)__popcll(m);
@@ -174,15 +172,16 @@ static hipError_t accumulate_launches(const splat_spheres &frame, const splat_sp
                                 const AccumGrid &g, int max_age, const splat_spheres &out, uint8_t *out_age,
                                 const AccumLayout &L, char *w, hipStream_t s)
 {
-    uint32_t *bits = reinterpret_cast<uint32_t *>(w + L.bits);
+    uint8_t *map = reinterpret_cast<uint8_t *>(w + L.map);
     uint32_t *tile_counts = reinterpret_cast<uint32_t *>(w + L.tile_counts);
     uint32_t *total = reinterpret_cast<uint32_t *>(w + L.total_slot);
-    const uint32_t clear_blocks = min((L.words + kUnprojBlock - 1) / kUnprojBlock, 4096u);
-    hipLaunchKernelGGL(k_accum_clear, dim3(clear_blocks), dim3(kUnprojBlock), 0, s, bits, L.words);
+    const uint32_t clear_blocks = min((L.chunks + kUnprojBlock - 1) / kUnprojBlock, 8192u);
+    hipLaunchKernelGGL(k_accum_clear, dim3(clear_blocks), dim3(kUnprojBlock), 0, s, reinterpret_cast<uint4 *>(map),
+                       L.chunks);
     const uint32_t frame_blocks = (frame.capacity + kUnprojBlock - 1) / kUnprojBlock;
     hipLaunchKernelGGL(k_accum_frame<HALF>, dim3(frame_blocks), dim3(kUnprojBlock), 0, s,
                        reinterpret_cast<const float4 *>(frame.centre_radius), frame.rgba, frame.src_index, frame.count,
-                       frame.capacity, g, bits, reinterpret_cast<float4 *>(out.centre_radius), out.rgba,
+                       frame.capacity, g, map, reinterpret_cast<float4 *>(out.centre_radius), out.rgba,
                        out.src_index, out_age, out.capacity);
     const float4 *hcr = history ? reinterpret_cast<const float4 *>(history->centre_radius) : nullptr;
     const void *hrgba = history ? history->rgba : nullptr;
@@ -190,11 +189,11 @@ static hipError_t accumulate_launches(const splat_spheres &frame, const splat_sp
     const uint32_t *hcount = history ? history->count : nullptr;
     const uint32_t hcap = history ? history->capacity : 0u;
     hipLaunchKernelGGL(k_accum_count, dim3(L.tiles), dim3(kUnprojBlock), 0, s, hcr, history_age, hcount, hcap, g,
-                       max_age, bits, tile_counts);
+                       max_age, map, tile_counts);
     const hipError_t e = launch_tile_scan(tile_counts, L.tiles, total, s);  // also reports the launches above
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_accum_scatter<HALF>, dim3(L.tiles), dim3(kUnprojBlock), 0, s, hcr, hrgba, hsrc, history_age,
-                       hcount, hcap, g, max_age, bits, tile_counts, total, frame.count, frame.capacity,
+                       hcount, hcap, g, max_age, map, tile_counts, total, frame.count, frame.capacity,
                        reinterpret_cast<float4 *>(out.centre_radius), out.rgba, out.src_index, out_age, out.capacity,
                        out.count);
     return hipGetLastError();

@@ -275,6 +275,7 @@ int splat_accumulate(const splat_spheres *frame, const splat_spheres *history, c
             if (overlaps(o, i)) return fail(SPLAT_EINVAL, "an output array of the accumulation overlaps an input");
     const size_t need = AccumLayout(opts->grid, hcap).total;
     if (!ws || ws_bytes < need) return fail(SPLAT_ENOSPC, "accumulation workspace needs %zu bytes", need);
+    if (reinterpret_cast<uintptr_t>(ws) % 16) return fail(SPLAT_EINVAL, "accumulation workspace must be 16-byte aligned");
     if ((rc = check_device())) return rc;
     return hip_status(launch_accumulate(*frame, history, history_age, *opts, *out, out_age, ws,
                                         static_cast<hipStream_t>(stream)),

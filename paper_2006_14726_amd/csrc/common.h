@@ -214,19 +214,20 @@ __host__ __device__ inline size_t unproject_ws_bytes(int64_t pixels)
     return align256((blocks + 1) * 4);
 }
 
-// Temporal accumulation workspace: the occupancy bitmap of the grid (one bit
-// per cell), the per-tile survivor counts of the history and their scan, and
-// the survivor total.  Tiles are kUnprojTile history samples.
+// Temporal accumulation workspace: the occupancy map of the grid (one byte
+// per cell, cleared in 16-byte chunks), the per-tile survivor counts of the
+// history and their scan, and the survivor total.  Tiles are kUnprojTile
+// history samples.
 struct AccumLayout {
-    size_t bits, tile_counts, total_slot, total;
-    uint32_t words, tiles;
+    size_t map, tile_counts, total_slot, total;
+    uint32_t chunks, tiles;
     __host__ __device__ AccumLayout(int32_t grid, uint32_t history_capacity)
     {
         const uint64_t cells = (uint64_t)grid * (uint64_t)grid * (uint64_t)grid;
-        words = (uint32_t)((cells + 31) / 32);
+        chunks = (uint32_t)((cells + 15) / 16);
         tiles = history_capacity ? (history_capacity + kUnprojTile - 1) / kUnprojTile : 1;
-        bits = 0;
-        tile_counts = align256(bits + (size_t)words * 4);
+        map = 0;
+        tile_counts = align256(map + (size_t)chunks * 16);
         total_slot = align256(tile_counts + (size_t)tiles * 4);
         total = align256(total_slot + 4);
     }

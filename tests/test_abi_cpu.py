@@ -38,9 +38,9 @@ def test_sizes_are_pure_host_functions():
     assert lib.splat_workspace_bytes(_lib.SPLAT_OP_BUILD, 1 << 20, 0, 0) >= (1 << 20) * 16
     assert lib.splat_workspace_bytes(_lib.SPLAT_OP_BATCHED, 4, 0, 0) >= 4
     assert lib.splat_workspace_bytes(99, 1, 1, 1) == 0
-    # accumulation: the cell bitmap (grid^3 bits) and the tile counts of the history
-    assert lib.splat_workspace_bytes(_lib.SPLAT_OP_ACCUMULATE, 1 << 20, 256, 0) >= (256 ** 3) // 8 + 1024 * 4
-    assert lib.splat_workspace_bytes(_lib.SPLAT_OP_ACCUMULATE, 0, 1024, 0) >= (1024 ** 3) // 8
+    # accumulation: the cell map (one byte per cell) and the tile counts of the history
+    assert lib.splat_workspace_bytes(_lib.SPLAT_OP_ACCUMULATE, 1 << 20, 256, 0) >= 256 ** 3 + 1024 * 4
+    assert lib.splat_workspace_bytes(_lib.SPLAT_OP_ACCUMULATE, 0, 1024, 0) >= 1024 ** 3
     assert lib.splat_workspace_bytes(_lib.SPLAT_OP_ACCUMULATE, 10, 0, 0) == 0
     assert lib.splat_workspace_bytes(_lib.SPLAT_OP_ACCUMULATE, 10, 1025, 0) == 0
 
@@ -214,6 +214,7 @@ def test_accumulate_validation():
     assert call(ra=ctypes.c_void_p(hage.value + 8))[0] == _lib.SPLAT_EINVAL  # out_age inside history_age
     assert call(wb=need - 1)[0] == _lib.SPLAT_ENOSPC
     assert call(w=None)[0] == _lib.SPLAT_ENOSPC
+    assert call(w=ctypes.c_void_p(ws.value + 8))[0] == _lib.SPLAT_EINVAL  # misaligned
     if not torch.cuda.is_available():
         assert call()[0] == _lib.SPLAT_ENODEV
         # no history: the workspace for capacity 0 suffices
