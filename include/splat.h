@@ -119,6 +119,11 @@ typedef struct splat_bvh {
  *   walk        SPLAT_WALK_LANE (each ray on its own path; default) or
  *               SPLAT_WALK_PACKET (a wavefront's rays as one packet); the
  *               result does not depend on it
+ *   event_begin, event_end
+ *               hipEvent_t or NULL: recorded on the stream immediately
+ *               before and after the trace kernel itself (after the tile
+ *               ordering of schedule 2), to time that kernel alone.  Only
+ *               splat_trace and splat_trace_backward record them
  */
 typedef struct splat_trace_opts {
     float alpha_stop;
@@ -129,6 +134,9 @@ typedef struct splat_trace_opts {
     int32_t tile_h;
     int32_t schedule;
     int32_t walk;
+    int32_t reserved;              /* 0 */
+    void *event_begin;
+    void *event_end;
 } splat_trace_opts;
 
 /* Per-sphere gradients, device float arrays indexed by sphere id; accumulated into (+=). */

@@ -40,7 +40,8 @@ class splat_bvh(ctypes.Structure):
 class splat_trace_opts(ctypes.Structure):
     _fields_ = [("alpha_stop", ctypes.c_float), ("mode", ctypes.c_int32), ("t_max", ctypes.c_double),
                 ("kbuf", ctypes.c_int32), ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
-                ("schedule", ctypes.c_int32), ("walk", ctypes.c_int32)]
+                ("schedule", ctypes.c_int32), ("walk", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("event_begin", _P), ("event_end", _P)]
 
 
 class splat_volume(ctypes.Structure):

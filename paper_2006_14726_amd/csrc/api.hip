@@ -118,7 +118,7 @@ int hip_status(hipError_t e, const char *what)
 
 extern "C" {
 
-int splat_version(void) { return 104; }
+int splat_version(void) { return 105; }
 
 const char *splat_last_error(void) { return g_err; }
 
@@ -387,7 +387,9 @@ int splat_trace(const splat_bvh *bvh, const splat_spheres *sph, const splat_came
     a.out = reinterpret_cast<float4 *>(out_rgba);
     a.hits = out_hits;
     if ((rc = check_device())) return rc;
-    return hip_status(launch_trace(a, false, ws, static_cast<hipStream_t>(stream)), "trace launch");
+    return hip_status(launch_trace(a, false, ws, static_cast<hipStream_t>(stream),
+                                   static_cast<hipEvent_t>(opts->event_begin), static_cast<hipEvent_t>(opts->event_end)),
+                      "trace launch");
 }
 
 int splat_trace_backward(const splat_bvh *bvh, const splat_spheres *sph, const splat_camera *cam,
@@ -408,7 +410,9 @@ int splat_trace_backward(const splat_bvh *bvh, const splat_spheres *sph, const s
     a.d_radius = grads->d_radius;
     a.d_centre = grads->d_centre;
     if ((rc = check_device())) return rc;
-    return hip_status(launch_trace(a, true, ws, static_cast<hipStream_t>(stream)), "backward launch");
+    return hip_status(launch_trace(a, true, ws, static_cast<hipStream_t>(stream),
+                                   static_cast<hipEvent_t>(opts->event_begin), static_cast<hipEvent_t>(opts->event_end)),
+                      "backward launch");
 }
 
 int splat_trace_batched(const splat_batch_job *jobs, const uint32_t *tile_offsets, int32_t n_jobs,

@@ -51,7 +51,8 @@ hipError_t launch_unproject(const Cam &cam, const float *rgba, const float *dept
 hipError_t launch_build(const splat_spheres &sph, const splat_bvh &bvh, bool refit_only, void *ws,
                         hipStream_t s);
 
-hipError_t launch_trace(const TraceArgs &a, bool backward, void *ws, hipStream_t s);
+hipError_t launch_trace(const TraceArgs &a, bool backward, void *ws, hipStream_t s, hipEvent_t ev_begin,
+                        hipEvent_t ev_end);
 
 // Schedule 2: computes the heaviest-first tile order into the workspace.
 hipError_t launch_tile_order(const TraceArgs &a, int tiles_x, int tiles_y, void *ws, hipStream_t s,

@@ -723,7 +723,8 @@ static hipError_t launch_k(const TraceArgs &a, int K, dim3 grid, int tiles_x, in
     return hipGetLastError();
 }
 
-hipError_t launch_trace(const TraceArgs &args, bool backward, void *ws, hipStream_t s)
+hipError_t launch_trace(const TraceArgs &args, bool backward, void *ws, hipStream_t s, hipEvent_t ev_begin,
+                        hipEvent_t ev_end)
 {
     TraceArgs a = args;
     const int tiles_x = (a.cam.w + a.tile_w - 1) / a.tile_w;
@@ -737,11 +738,20 @@ hipError_t launch_trace(const TraceArgs &args, bool backward, void *ws, hipStrea
         if (e != hipSuccess) return e;
     }
     const dim3 grid(a.order ? (uint32_t)(tiles_x * tiles_y) : blocks_for(tiles_x, tiles_y, a.schedule));
+    // optional events bracketing the trace kernel alone (not the tile ordering)
+    if (ev_begin) {
+        const hipError_t e = hipEventRecord(ev_begin, s);
+        if (e != hipSuccess) return e;
+    }
+    hipError_t e;
     if (a.walk == SPLAT_WALK_PACKET)
-        return backward ? launch_k<true, false>(a, a.kbuf, grid, tiles_x, tiles_y, s)
-                        : launch_k<false, false>(a, a.kbuf, grid, tiles_x, tiles_y, s);
-    return backward ? launch_k<true, true>(a, a.kbuf, grid, tiles_x, tiles_y, s)
-                    : launch_k<false, true>(a, a.kbuf, grid, tiles_x, tiles_y, s);
+        e = backward ? launch_k<true, false>(a, a.kbuf, grid, tiles_x, tiles_y, s)
+                     : launch_k<false, false>(a, a.kbuf, grid, tiles_x, tiles_y, s);
+    else
+        e = backward ? launch_k<true, true>(a, a.kbuf, grid, tiles_x, tiles_y, s)
+                     : launch_k<false, true>(a, a.kbuf, grid, tiles_x, tiles_y, s);
+    if (e == hipSuccess && ev_end) e = hipEventRecord(ev_end, s);
+    return e;
 }
 
 hipError_t launch_trace_batched(const splat_batch_job *jobs, const uint32_t *tile_offsets, int32_t n_jobs,

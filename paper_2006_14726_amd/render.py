@@ -289,6 +289,9 @@ class TraceOptions:
     tile: tuple = field(default=(8, 8))
     schedule: int = 2  # 0 super-tiles per XCD, 1 bands, 2 heaviest tiles first
     walk: int = 0  # SPLAT_WALK_LANE (0) or SPLAT_WALK_PACKET (1)
+    # raw hipEvent_t handles (torch.cuda.Event.cuda_event, after a first record) recorded around the trace
+    # kernel alone; (0, 0) for none
+    events: tuple = field(default=(0, 0))
 
     def struct(self) -> _lib.splat_trace_opts:
         o = _lib.splat_trace_opts()
@@ -299,6 +302,8 @@ class TraceOptions:
         o.tile_w, o.tile_h = int(self.tile[0]), int(self.tile[1])
         o.schedule = int(self.schedule)
         o.walk = int(self.walk)
+        o.event_begin = int(self.events[0]) or None
+        o.event_end = int(self.events[1]) or None
         return o
 
 

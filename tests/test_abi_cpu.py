@@ -27,7 +27,7 @@ def test_library_exports_every_declared_symbol():
     lib = _lib.load()
     for name in declared_functions():
         assert hasattr(lib, name), name
-    assert lib.splat_version() == 104
+    assert lib.splat_version() == 105
 
 
 def test_sizes_are_pure_host_functions():
@@ -48,7 +48,7 @@ def test_sizes_are_pure_host_functions():
 def test_struct_layouts_match_the_header():
     assert ctypes.sizeof(_lib.splat_camera) == 13 * 8 + 2 * 4
     assert ctypes.sizeof(_lib.splat_spheres) == 8 + 8 + 4 + 4 + 8 + 8 + 8
-    assert ctypes.sizeof(_lib.splat_trace_opts) == 40
+    assert ctypes.sizeof(_lib.splat_trace_opts) == 56
     assert ctypes.sizeof(_lib.splat_volume) == 32
     assert ctypes.sizeof(_lib.splat_march_opts) == 48
     assert ctypes.sizeof(_lib.splat_radius_policy) == 16

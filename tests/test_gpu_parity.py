@@ -318,3 +318,21 @@ def test_errors_on_device(sp):
     with pytest.raises(sp.SplatError) as e:
         sp.unproject(cam, up(np.zeros((8, 8, 4), np.float32)), up(np.zeros((8, 8), np.float32)), 1.0, out=s)
     assert e.value.code == 2
+
+
+def test_trace_kernel_events(sp):
+    """Events passed in the options bracket the trace kernel alone: they time
+    it (after the tile ordering) and change nothing in the result."""
+    cr, col = synth.random_spheres(6000, seed=31, r_lo=0.004, r_hi=0.03)
+    cam = synth.rotated_camera(synth.source_camera(1024, 768), 9.0, 4.0)
+    sph = sp.spheres_from_tensors(up(cr), up(col))
+    bvh = sp.build_bvh(sph)
+    img0, hits0 = sp.trace(bvh, sph, cam)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    b.record()
+    torch.cuda.synchronize()
+    img1, hits1 = sp.trace(bvh, sph, cam, sp.TraceOptions(events=(a.cuda_event, b.cuda_event)))
+    torch.cuda.synchronize()
+    assert torch.equal(img0, img1) and torch.equal(hits0, hits1)
+    assert 0.0 < a.elapsed_time(b) < 1000.0
