@@ -323,7 +323,7 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
                 const float t1z = fmaf(s[2], ray.inv[2], -ray.oPi[2]), t2z = fmaf(s[5], ray.inv[2], -ray.oMi[2]);
                 const float tn = fmaxf(fmaxf(fminf(t1x, t2x), fminf(t1y, t2y)), fminf(t1z, t2z));
                 const float tf = fminf(fminf(fmaxf(t1x, t2x), fmaxf(t1y, t2y)), fmaxf(t1z, t2z)) * 1.0000005f;
-                hits |= ((tn <= tf) & (tf >= lo_f) & (tn <= pf)) ? 1u << side : 0u;
+                hits |= (fmaxf(tn, lo_f) <= fminf(tf, pf)) ? 1u << side : 0u;
             }
             return hits;
         };
@@ -352,15 +352,19 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
                 const float t1z = fmaf(s[2], ray.inv[2], -ray.oPi[2]), t2z = fmaf(s[5], ray.inv[2], -ray.oMi[2]);
                 const float tn = fmaxf(fmaxf(fminf(t1x, t2x), fminf(t1y, t2y)), fminf(t1z, t2z));
                 const float tf = fminf(fminf(fmaxf(t1x, t2x), fmaxf(t1y, t2y)), fmaxf(t1z, t2z)) * 1.0000005f;
-                const bool h = (tn <= tf) & (tf >= lo_f) & (tn <= pf);
+                // tn <= tf, tf >= lo_f and tn <= pf in one comparison (lo_f <= pf for a lane
+                // taking part; pf = -inf for one that does not)
+                const bool h = fmaxf(tn, lo_f) <= fminf(tf, pf);
                 hits |= h ? 1u << side : 0u;
                 tn_out[side] = h ? tn : INFINITY;
             }
             return hits;
         };
         auto slot_ref = [](const float *f, uint32_t o) -> uint32_t {
-            return o == 0 ? __float_as_uint(f[24]) : o == 1 ? __float_as_uint(f[25])
-                 : o == 2 ? __float_as_uint(f[26]) : __float_as_uint(f[27]);
+            // two levels of selects on the slot's bits (no branches for a per-lane slot)
+            const uint32_t r01 = (o & 1u) ? __float_as_uint(f[25]) : __float_as_uint(f[24]);
+            const uint32_t r23 = (o & 1u) ? __float_as_uint(f[27]) : __float_as_uint(f[26]);
+            return (o & 2u) ? r23 : r01;
         };
 
         bool overflow = false;  // the lane's own stack dropped entries
@@ -372,7 +376,11 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
             // the union of their paths.
             uint32_t node = 0, top = 0, depth = 0, steps = 0;
             bool walking = active;
+            // steps run in an inner loop that ends when some lane's queue may
+            // overflow; the flush (which rewrites the hit buffer) stays out of
+            // it, so the buffer's registers are not copied at every step
             while (__ballot(walking)) {
+              do {
                 if (walking) {
                     const float4 *np = reinterpret_cast<const float4 *>(nodes + node);
                     float f[32];
@@ -427,6 +435,7 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
                     node = min(node, n_nodes - 1);
                     if (++steps > n_nodes) walking = false;
                 }
+              } while (__ballot(walking) && !__ballot(nc > (uint32_t)kQueue - 4u));
                 if (__ballot(nc > (uint32_t)kQueue - 4u)) flush();
             }
             redo = overflow;
