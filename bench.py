@@ -67,6 +67,31 @@ def measured_traffic(args):
     return int(float(rec["traffic_bytes_per_dispatch"]))
 
 
+def valu_issue(args, kernel_ms: float):
+    """Vector-issue occupancy of the trace kernel from the committed SQ counter summary: wave64 vector
+    instructions x 4 cycles / 1024 SIMDs, over the kernel's duration at 2.4 GHz; None when the kernel
+    source or the launch configuration differs from the one profiled."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "trace_client_frame_sq_counters.txt")
+    if not os.path.exists(path) or (args.kbuf, args.tile, args.scale, args.walk, args.schedule) != (6, "8x8", 1.0, 0, 2):
+        return None
+    rec = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            rec[k.strip()] = v.strip()
+    h = hashlib.sha256()
+    for f in ("trace.hip", "common.h", "kernels.h"):
+        with open(os.path.join(ROOT, "paper_2006_14726_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if rec.get("trace_source_sha256_16") != h.hexdigest()[:16]:
+        return None
+    valu = float(rec["sq_insts_valu_per_dispatch"])
+    busy = valu * 4 / 1024 / (kernel_ms * 1e-3 * 2.4e9)
+    return {"valu_insts_per_launch": int(valu), "valu_busy_frac": round(busy, 3),
+            "note": "vector-instruction issue: the bound of this kernel (4 cycles per wave64 instruction, 1024 SIMDs, 2.4 GHz)"}
+
+
 def trace_bytes(n: int, pixels: int, half: bool) -> int:
     """Compulsory bytes of one trace: sphere geometry + colour, hierarchy, output image and hit counts."""
     cb = 8 if half else 16
@@ -205,7 +230,8 @@ def main():
                      "kernel": f"k_trace<{args.kbuf}, false, {'true' if args.walk == 0 else 'false'}>",
                      "algorithmic_bytes": tb, "avg_launch_ms": round(trace_ms, 4),
                      "note": "avg_launch_ms is the trace kernel alone, between events the library records around "
-                             "it; trace_call_ms adds the tile-ordering kernels of schedule 2"},
+                             "it; trace_call_ms adds the tile-ordering kernels of schedule 2",
+                     "issue": valu_issue(args, trace_ms)},
     }
 
     if not args.no_extra:
