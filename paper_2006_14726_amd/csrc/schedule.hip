@@ -14,8 +14,9 @@
 //   count    one thread per kSample-th sphere: project the centre (float;
 //            only a ranking) and count it in its tile; neighbouring spheres
 //            share tiles, so a wave adds once per distinct tile
-//   keys     one thread per tile: neighbourhood maximum -> log bucket
-//            (bucket 0 = heaviest) and the bucket histogram
+//   keys     one thread per tile, 16 x 16 tiles per block through LDS:
+//            neighbourhood maximum (separable) -> log bucket (bucket 0 =
+//            heaviest) and the bucket histogram
 //   scatter  one thread per tile: its slot in the order, buckets ascending
 #include "common.h"
 #include "kernels.h"
@@ -24,7 +25,7 @@ namespace splat {
 
 constexpr int kOrderBlock = 256;
 constexpr int kReach = 3;   // neighbourhood: (2 kReach + 1)^2 tiles
-constexpr int kSample = 4;  // every kSample-th sphere is counted (log-scale keys do not need all)
+constexpr int kSample = 8;  // every kSample-th sphere is counted (log-scale keys do not need all)
 
 __global__ void __launch_bounds__(kOrderBlock)
 k_tile_zero(uint32_t *__restrict__ counts, uint32_t tiles, uint32_t *__restrict__ hist)
@@ -69,25 +70,44 @@ k_tile_count(const float4 *__restrict__ cr, const uint32_t *__restrict__ count, 
     }
 }
 
+// A block keys a kKeyTile x kKeyTile patch of tiles: the counts of the patch
+// and its kReach halo go to LDS, the neighbourhood maximum is taken along x
+// (into LDS), then along y.
+constexpr int kKeyTile = 16;
+constexpr int kKeyHalo = kKeyTile + 2 * kReach;
+
 __global__ void __launch_bounds__(kOrderBlock)
 k_tile_keys(const uint32_t *__restrict__ counts, int tiles_x, int tiles_y, uint32_t *__restrict__ bucket,
             uint32_t *__restrict__ hist)
 {
+    static_assert(kKeyTile * kKeyTile == kOrderBlock, "one thread per tile of the patch");
     __shared__ uint32_t h[kOrderBuckets];
+    __shared__ uint32_t c[kKeyHalo][kKeyHalo];   // counts of the patch and its halo (0 outside the image)
+    __shared__ uint32_t rx[kKeyHalo][kKeyTile];  // maximum along x over 2 kReach + 1 tiles
     if (threadIdx.x < (unsigned)kOrderBuckets) h[threadIdx.x] = 0u;
+    const int x0 = (int)blockIdx.x * kKeyTile - kReach, y0 = (int)blockIdx.y * kKeyTile - kReach;
+    for (int i = threadIdx.x; i < kKeyHalo * kKeyHalo; i += kOrderBlock) {
+        const int x = x0 + i % kKeyHalo, y = y0 + i / kKeyHalo;
+        c[i / kKeyHalo][i % kKeyHalo] =
+            (x >= 0 && y >= 0 && x < tiles_x && y < tiles_y) ? counts[(size_t)y * tiles_x + x] : 0u;
+    }
     __syncthreads();
-    const uint32_t tiles = (uint32_t)tiles_x * (uint32_t)tiles_y;
-    const uint32_t t = blockIdx.x * kOrderBlock + threadIdx.x;
-    if (t < tiles) {
-        const int tx = (int)(t % (uint32_t)tiles_x), ty = (int)(t / (uint32_t)tiles_x);
+    for (int i = threadIdx.x; i < kKeyHalo * kKeyTile; i += kOrderBlock) {
+        const int row = i / kKeyTile, col = i % kKeyTile;
+        uint32_t m = 0;
+        for (int k = 0; k <= 2 * kReach; ++k) m = max(m, c[row][col + k]);
+        rx[row][col] = m;
+    }
+    __syncthreads();
+    const int lx = threadIdx.x % kKeyTile, ly = threadIdx.x / kKeyTile;
+    const int tx = (int)blockIdx.x * kKeyTile + lx, ty = (int)blockIdx.y * kKeyTile + ly;
+    if (tx < tiles_x && ty < tiles_y) {
         uint32_t key = 0;
-        for (int y = max(ty - kReach, 0); y <= min(ty + kReach, tiles_y - 1); ++y)
-            for (int x = max(tx - kReach, 0); x <= min(tx + kReach, tiles_x - 1); ++x)
-                key = max(key, counts[(size_t)y * tiles_x + x]);
+        for (int k = 0; k <= 2 * kReach; ++k) key = max(key, rx[ly + k][lx]);
         // four buckets per octave of the key, heaviest first
         const int level = (int)(4.0f * log2f(1.0f + (float)key));
         const uint32_t b = (uint32_t)(kOrderBuckets - 1 - min(level, kOrderBuckets - 1));
-        bucket[t] = b;
+        bucket[(size_t)ty * tiles_x + tx] = b;
         atomicAdd(&h[b], 1u);
     }
     __syncthreads();
@@ -149,8 +169,8 @@ hipError_t launch_tile_order(const TraceArgs &a, int tiles_x, int tiles_y, void 
                        hist);
     hipLaunchKernelGGL(k_tile_count, dim3(sphere_blocks), dim3(kOrderBlock), 0, s, a.centre_radius, n, cap, a.cam,
                        a.tile_w, a.tile_h, tiles_x, tiles_y, counts);
-    hipLaunchKernelGGL(k_tile_keys, dim3(tile_blocks), dim3(kOrderBlock), 0, s, counts, tiles_x, tiles_y, bucket,
-                       hist);
+    const dim3 key_grid((tiles_x + kKeyTile - 1) / kKeyTile, (tiles_y + kKeyTile - 1) / kKeyTile);
+    hipLaunchKernelGGL(k_tile_keys, key_grid, dim3(kOrderBlock), 0, s, counts, tiles_x, tiles_y, bucket, hist);
     hipLaunchKernelGGL(k_tile_scatter, dim3(tile_blocks), dim3(kOrderBlock), 0, s, bucket, tiles, hist, order);
     *order_out = order;
     return hipGetLastError();
