@@ -161,8 +161,8 @@ struct BvhLayout {
 // Radix-sort layout in the build workspace.
 constexpr int kSortBits = 8;
 constexpr int kSortBins = 1 << kSortBits;
-constexpr int kSortBlock = 256;                  // threads per sort block
-constexpr int kSortItems = 8;                    // keys per thread
+constexpr int kSortBlock = 1024;                 // threads per sort block
+constexpr int kSortItems = 2;                    // keys per thread
 constexpr int kSortTile = kSortBlock * kSortItems;
 constexpr int kMortonBits = 30;
 
