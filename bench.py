@@ -272,8 +272,7 @@ def fwd_bwd(sp, torch, synth, dev, steps):
         sp.trace(bvh, s, dst, opts, out=out, want_hits=False)
     ev[1].record()
     for _ in range(reps):
-        for g in grads.values():
-            g.zero_()
+        sp.zero_grads(grads)
         sp.trace(bvh, s, dst, opts, out=out, want_hits=False)
         sp.trace_backward(bvh, s, dst, opts, out, grad, grads)
     ev[2].record()

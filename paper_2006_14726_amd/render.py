@@ -331,16 +331,35 @@ def trace(bvh: BVH, sph: Spheres, cam, opts: TraceOptions | None = None, out: to
     return out, hits
 
 
+def alloc_grads(capacity: int, device) -> dict:
+    """Zeroed per-sphere gradients: rgb [cap, 3], alpha [cap], radius [cap], centre [cap, 3], as views of one
+    buffer, so that `zero_grads` clears them with one fill."""
+    flat = torch.zeros((8 * capacity,), dtype=torch.float32, device=device)
+    return {"rgb": flat[:3 * capacity].view(capacity, 3), "alpha": flat[3 * capacity:4 * capacity],
+            "radius": flat[4 * capacity:5 * capacity], "centre": flat[5 * capacity:].view(capacity, 3)}
+
+
+def zero_grads(grads: dict) -> None:
+    """Clear gradients for the next accumulation: one fill when they are the views of one buffer that
+    alloc_grads makes, else one fill each."""
+    rgb = grads["rgb"]
+    n = sum(g.numel() for g in grads.values())
+    base = rgb.untyped_storage()
+    shared = all(g.untyped_storage().data_ptr() == base.data_ptr() for g in grads.values())
+    if shared and rgb.storage_offset() == 0 and base.nbytes() == 4 * n:
+        rgb.as_strided((n,), (1,), 0).zero_()
+    else:
+        for g in grads.values():
+            g.zero_()
+
+
 def trace_backward(bvh: BVH, sph: Spheres, cam, opts: TraceOptions, out_rgba: torch.Tensor, grad_rgba: torch.Tensor,
                    grads: dict | None = None) -> dict:
     """Accumulate dL/d(rgb, alpha, radius, centre) per sphere (splat_trace_backward)."""
     dev = sph.centre_radius.device
     cap = sph.capacity
     if grads is None:
-        grads = {"rgb": torch.zeros((cap, 3), dtype=torch.float32, device=dev),
-                 "alpha": torch.zeros((cap,), dtype=torch.float32, device=dev),
-                 "radius": torch.zeros((cap,), dtype=torch.float32, device=dev),
-                 "centre": torch.zeros((cap, 3), dtype=torch.float32, device=dev)}
+        grads = alloc_grads(cap, dev)
     _require_cuda(out_rgba, "out_rgba", torch.float32)
     _require_cuda(grad_rgba, "grad_rgba", torch.float32)
     H, W = int(cam.height), int(cam.width)

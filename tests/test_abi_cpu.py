@@ -248,3 +248,21 @@ def test_unproject_policy_validation():
             assert call(mode=mode)[0] == _lib.SPLAT_ENODEV
         # the footprint and opacity policies do not need the interval
         assert call(mode=_lib.SPLAT_RADIUS_OPACITY, interval=None)[0] == _lib.SPLAT_ENODEV
+
+
+def test_gradient_buffers_clear_in_one_fill():
+    """alloc_grads lays the four gradient arrays out in one buffer; zero_grads clears them all, and
+    falls back to one fill per array for separately allocated ones."""
+    import torch
+    import paper_2006_14726_amd as sp
+    g = sp.alloc_grads(7, "cpu")
+    assert g["rgb"].shape == (7, 3) and g["centre"].shape == (7, 3)
+    assert g["alpha"].shape == (7,) and g["radius"].shape == (7,)
+    for v in g.values():
+        v.fill_(2.0)
+    g["alpha"][3] = 5.0
+    sp.zero_grads(g)
+    assert all(float(v.abs().sum()) == 0.0 for v in g.values())
+    loose = {"rgb": torch.ones(4, 3), "alpha": torch.ones(4), "radius": torch.ones(4), "centre": torch.ones(4, 3)}
+    sp.zero_grads(loose)
+    assert all(float(v.abs().sum()) == 0.0 for v in loose.values())
