@@ -560,7 +560,7 @@ int64_t orc_pixels_near(const orc_camera *cam, const double centre[3], double ra
  * the volume and writes, per pixel, the composited colour and one
  * representative depth t).  The paper names only a standard ray marcher and
  * a depth heuristic from earlier work; the rules written out here are the
- * reading this build uses:
+ * reading used here:
  *   - volume v[z][y][x] of n^3 floats filling the cube [lo, lo + size]^3,
  *     voxel (i, j, k) centred at lo + (i + 1/2, j + 1/2, k + 1/2) size / n;
  *     reconstruction is trilinear with clamp-to-edge;
