@@ -162,7 +162,8 @@ typedef struct splat_batch_job {
     uint32_t *out_hits;            /* uint32 [height][width] or NULL */
 } splat_batch_job;
 
-/* Bytes of workspace that `op` (SPLAT_OP_*) needs for the given capacity and image size. */
+/* Bytes of workspace that `op` (SPLAT_OP_*) needs for the given capacity and image size
+ * (SPLAT_OP_ACCUMULATE: capacity = the history's, width = the grid, height unused). */
 size_t splat_workspace_bytes(int32_t op, uint32_t capacity, int32_t width, int32_t height);
 
 /* Bytes of the BVH allocation for `capacity` spheres. */
