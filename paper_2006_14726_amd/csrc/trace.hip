@@ -339,13 +339,15 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
             const uint32_t o0 = 2u * cn + gn, o2 = 2u * (1u - cn) + gf;
             return o0 | ((o0 ^ 1u) << 2) | (o2 << 4) | ((o2 ^ 1u) << 6);
         };
-        // per lane: hit mask and entry distance of each slot
+        // per lane: hit mask and entry distance of each slot.  Nearly every
+        // step has an internal slot at every position in some lane, so the
+        // four tests run unconditionally and the slot kinds mask the result
+        // once (a sphere slot's words make a meaningless box, never used;
+        // its entry distance only reorders slots that are not pushed)
         auto box_hits_tn = [&](const float *f, uint32_t kinds, float pf, float tn_out[4]) -> uint32_t {
             uint32_t hits = 0;
 #pragma unroll
             for (int side = 0; side < 4; ++side) {
-                tn_out[side] = INFINITY;
-                if (!((kinds >> (4 + side)) & 1u)) continue;
                 const float *s = f + 6 * side;
                 const float t1x = fmaf(s[0], ray.inv[0], -ray.oPi[0]), t2x = fmaf(s[3], ray.inv[0], -ray.oMi[0]);
                 const float t1y = fmaf(s[1], ray.inv[1], -ray.oPi[1]), t2y = fmaf(s[4], ray.inv[1], -ray.oMi[1]);
@@ -358,7 +360,7 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
                 hits |= h ? 1u << side : 0u;
                 tn_out[side] = h ? tn : INFINITY;
             }
-            return hits;
+            return hits & (kinds >> 4) & 0xfu;
         };
         auto slot_ref = [](const float *f, uint32_t o) -> uint32_t {
             // two levels of selects on the slot's bits (no branches for a per-lane slot)
