@@ -3,8 +3,9 @@
 //
 //   bounds   block partial min/max of the centres
 //   morton   every block folds the partials; 30-bit Morton code per centre
+//            and the tile histogram of the first digit
 //   sort     stable LSD radix sort of (code, id), 8-bit digits, 4 passes:
-//            tile histograms -> one-block scan -> stable LDS scatter
+//            tile histograms -> per-digit scans -> stable LDS scatter
 //   karras   radix-tree hierarchy: one thread per internal node finds its
 //            key range and split from common-prefix lengths of the sorted
 //            codes (ties broken by the sorted position)
@@ -34,11 +35,17 @@ __device__ inline float wave_max(float v)
     return v;
 }
 
+// Block partials of the centre box.  The first thread also sets the header's
+// sphere count and empties the list of refit entries of the new hierarchy.
 __global__ void __launch_bounds__(256)
 k_bounds_partial(const float4 *__restrict__ cr, const uint32_t *__restrict__ count, uint32_t cap,
-                 float *__restrict__ partial)
+                 float *__restrict__ partial, BvhHeader *__restrict__ hdr)
 {
     const uint32_t n = min(*count, cap);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        hdr->n = n;
+        hdr->n_entry = 0u;
+    }
     float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
         const float4 c = cr[i];
@@ -70,55 +77,70 @@ __device__ inline uint32_t expand_bits10(uint32_t v)
     return v;
 }
 
-// Fold the block partials into the centre box of the header (one block).
-__global__ void __launch_bounds__(256)
-k_bounds_final(const float *__restrict__ partial, BvhHeader *__restrict__ hdr)
+// Morton codes of one sort tile.  Every block folds the block partials into
+// the centre box itself (block 0 also stores it in the header), quantises its
+// kSortTile centres to 10 bits per axis and interleaves them (bit 3k+2 of a
+// code is x, 3k+1 is y, 3k is z), and writes the tile's histogram of the
+// first digit, so the first sort pass needs no histogram launch.
+static_assert(kBoundsBlocks <= kSortBlock, "one bound partial per thread");
+
+__global__ void __launch_bounds__(kSortBlock)
+k_morton(const float4 *__restrict__ cr, const uint32_t *__restrict__ count, uint32_t cap,
+         const float *__restrict__ partial, BvhHeader *__restrict__ hdr, uint32_t *__restrict__ keys,
+         uint32_t *__restrict__ vals, uint32_t *__restrict__ hist, uint32_t tiles)
 {
-    __shared__ float s[4][6];
+    constexpr int kWaves = kSortBlock / kWave;
+    __shared__ float s[kWaves][6];
+    __shared__ float box[6];
+    __shared__ uint32_t h[kSortBins];
+    for (int d = threadIdx.x; d < kSortBins; d += kSortBlock) h[d] = 0;
     float v[6];
-    for (int k = 0; k < 6; ++k) v[k] = partial[threadIdx.x * 8 + k];  // one partial per thread
+    if (threadIdx.x < kBoundsBlocks) {
+        for (int k = 0; k < 6; ++k) v[k] = partial[threadIdx.x * 8 + k];
+    } else {
+        for (int k = 0; k < 3; ++k) { v[k] = INFINITY; v[3 + k] = -INFINITY; }
+    }
     for (int k = 0; k < 3; ++k) {
         v[k] = wave_min(v[k]);
         v[3 + k] = wave_max(v[3 + k]);
     }
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     if (lane == 0)
         for (int k = 0; k < 6; ++k) s[w][k] = v[k];
     __syncthreads();
     if (threadIdx.x < 6) {
         float r = s[0][threadIdx.x];
-        for (int q = 1; q < 4; ++q) r = threadIdx.x < 3 ? fminf(r, s[q][threadIdx.x]) : fmaxf(r, s[q][threadIdx.x]);
-        if (threadIdx.x < 3) hdr->cen_lo[threadIdx.x] = r;
-        else hdr->cen_hi[threadIdx.x - 3] = r;
-    }
-}
-
-// Bit 3k+2 of a code is x, 3k+1 is y, 3k is z.
-__global__ void __launch_bounds__(256)
-k_morton(const float4 *__restrict__ cr, const uint32_t *__restrict__ count, uint32_t cap,
-         const BvhHeader *__restrict__ hdr, uint32_t *__restrict__ keys, uint32_t *__restrict__ vals)
-{
-    __shared__ float box[6];
-    if (threadIdx.x < 3) {
-        box[threadIdx.x] = hdr->cen_lo[threadIdx.x];
-        box[3 + threadIdx.x] = hdr->cen_hi[threadIdx.x];
+        for (int q = 1; q < kWaves; ++q) r = threadIdx.x < 3 ? fminf(r, s[q][threadIdx.x]) : fmaxf(r, s[q][threadIdx.x]);
+        box[threadIdx.x] = r;
+        if (blockIdx.x == 0) {
+            if (threadIdx.x < 3) hdr->cen_lo[threadIdx.x] = r;
+            else hdr->cen_hi[threadIdx.x - 3] = r;
+        }
     }
     __syncthreads();
     const uint32_t n = min(*count, cap);
-    const uint32_t i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= n) return;
-    const float4 c = cr[i];
-    const float p[3] = {c.x, c.y, c.z};
-    uint32_t q[3];
+    const uint32_t base = blockIdx.x * kSortTile;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const float ext = box[3 + a] - box[a];
-        const float u = ext > 0.0f ? (p[a] - box[a]) / ext : 0.0f;
-        int v = (int)(u * 1024.0f);
-        q[a] = (uint32_t)(v < 0 ? 0 : (v > 1023 ? 1023 : v));
+    for (int it = 0; it < kSortItems; ++it) {
+        const uint32_t i = base + it * kSortBlock + threadIdx.x;
+        if (i >= n) continue;
+        const float4 c = cr[i];
+        const float p[3] = {c.x, c.y, c.z};
+        uint32_t q[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const float ext = box[3 + a] - box[a];
+            const float u = ext > 0.0f ? (p[a] - box[a]) / ext : 0.0f;
+            int vq = (int)(u * 1024.0f);
+            q[a] = (uint32_t)(vq < 0 ? 0 : (vq > 1023 ? 1023 : vq));
+        }
+        const uint32_t code = (expand_bits10(q[0]) << 2) | (expand_bits10(q[1]) << 1) | expand_bits10(q[2]);
+        keys[i] = code;
+        vals[i] = i;
+        atomicAdd(&h[code & (kSortBins - 1)], 1u);
     }
-    keys[i] = (expand_bits10(q[0]) << 2) | (expand_bits10(q[1]) << 1) | expand_bits10(q[2]);
-    vals[i] = i;
+    __syncthreads();
+    for (int d = threadIdx.x; d < kSortBins; d += kSortBlock) hist[(size_t)d * tiles + blockIdx.x] = h[d];
 }
 
 // ---------------------------------------------------------------- radix sort
@@ -599,14 +621,11 @@ k_gather_wide(const uint32_t *__restrict__ count, uint32_t cap, const Node *__re
     for (int k = 0; k < 8; ++k) dst[k] = make_float4(w[4 * k], w[4 * k + 1], w[4 * k + 2], w[4 * k + 3]);
 }
 
-// Header count (an empty sphere set traces as background) and the refit list reset.
-__global__ void k_header_count(const uint32_t *__restrict__ count, uint32_t cap, int new_hierarchy,
-                               BvhHeader *__restrict__ hdr)
+// Header count of a refit (an empty sphere set traces as background); the
+// refit entries of the hierarchy stay.  A build sets it in k_bounds_partial.
+__global__ void k_header_count(const uint32_t *__restrict__ count, uint32_t cap, BvhHeader *__restrict__ hdr)
 {
-    if (threadIdx.x == 0) {
-        hdr->n = min(*count, cap);
-        if (new_hierarchy) hdr->n_entry = 0u;
-    }
+    if (threadIdx.x == 0) hdr->n = min(*count, cap);
 }
 
 hipError_t launch_build(const splat_spheres &sph, const splat_bvh &bvh, bool refit_only, void *ws, hipStream_t s)
@@ -628,7 +647,6 @@ hipError_t launch_build(const splat_spheres &sph, const splat_bvh &bvh, bool ref
     // one refit workgroup per CU (its LDS takes most of the CU's); they share out the treelets
     const uint32_t refit_blocks = 256;
 
-    hipLaunchKernelGGL(k_header_count, dim3(1), dim3(64), 0, s, sph.count, cap, refit_only ? 0 : 1, hdr);
     if (!refit_only) {
         const BuildLayout B(cap);
         char *w = static_cast<char *>(ws);
@@ -637,12 +655,13 @@ hipError_t launch_build(const splat_spheres &sph, const splat_bvh &bvh, bool ref
         uint32_t *hist = reinterpret_cast<uint32_t *>(w + B.hist);
         uint32_t *totals = reinterpret_cast<uint32_t *>(w + B.totals);
         float *partial = reinterpret_cast<float *>(w + B.partial);
-        hipLaunchKernelGGL(k_bounds_partial, dim3(kBoundsBlocks), dim3(256), 0, s, cr, sph.count, cap, partial);
-        hipLaunchKernelGGL(k_bounds_final, dim3(1), dim3(kBoundsBlocks), 0, s, partial, hdr);
-        hipLaunchKernelGGL(k_morton, dim3(blocks), dim3(256), 0, s, cr, sph.count, cap, hdr, ka, va);
+        hipLaunchKernelGGL(k_bounds_partial, dim3(kBoundsBlocks), dim3(256), 0, s, cr, sph.count, cap, partial, hdr);
+        hipLaunchKernelGGL(k_morton, dim3(B.tiles), dim3(kSortBlock), 0, s, cr, sph.count, cap, partial, hdr, ka, va,
+                           hist, B.tiles);
         for (int shift = 0; shift < kMortonBits; shift += kSortBits) {
-            hipLaunchKernelGGL(k_sort_hist, dim3(B.tiles), dim3(kSortBlock), 0, s, ka, sph.count, cap, shift, hist,
-                               B.tiles);
+            if (shift > 0)  // the first digit's histogram comes from k_morton
+                hipLaunchKernelGGL(k_sort_hist, dim3(B.tiles), dim3(kSortBlock), 0, s, ka, sph.count, cap, shift,
+                                   hist, B.tiles);
             hipLaunchKernelGGL(k_scan_digits, dim3(kSortBins), dim3(256), 0, s, hist, B.tiles, totals);
             hipLaunchKernelGGL(k_sort_scatter, dim3(B.tiles), dim3(kSortBlock), 0, s, ka, va, kb, vb, sph.count, cap,
                                shift, hist, totals, B.tiles);
@@ -652,6 +671,7 @@ hipError_t launch_build(const splat_spheres &sph, const splat_bvh &bvh, bool ref
         hipLaunchKernelGGL(k_karras, dim3(blocks), dim3(256), 0, s, ka, va, sph.count, cap, nodes, leaf_parent,
                            node_parent, leaf_ids, flags, ranges, entries, hdr);
     } else {
+        hipLaunchKernelGGL(k_header_count, dim3(1), dim3(64), 0, s, sph.count, cap, hdr);
         hipLaunchKernelGGL(k_zero_flags, dim3(blocks), dim3(256), 0, s, flags, sph.count, cap);
     }
     hipLaunchKernelGGL(k_refit_local, dim3(refit_blocks), dim3(kRefitThreads), 0, s, cr, sph.rgba, half, sph.count,
