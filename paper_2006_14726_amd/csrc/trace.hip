@@ -31,6 +31,15 @@ namespace splat {
 
 // ---------------------------------------------------------------- helpers
 
+// Direction signs shared by every tracing lane of a wave: bit k set when the
+// rays run towards -k.  kMixedSigns: the lanes differ (or a direction is
+// too close to an axis plane for the shortcut below).
+template <int S>
+struct SignTag {
+    static constexpr int value = S;
+};
+constexpr int kMixedSigns = 8;
+
 __device__ inline uint32_t ufirst(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
 __device__ inline bool key_less(double ta, uint32_t ia, double tb, uint32_t ib)
@@ -160,6 +169,22 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
     // near-first order per split axis, from the first lane's ray
     const uint32_t neg_mask = ufirst((ray.d[0] < 0.0 ? 1u : 0u) | (ray.d[1] < 0.0 ? 2u : 0u) |
                                      (ray.d[2] < 0.0 ? 4u : 0u));
+    // signs of 1/d shared by every lane that traces (lanes outside the image
+    // carry a stand-in ray and take no part), for the per-lane walk's box
+    // test; a 1/d beyond 2^40 could overflow the slab products, so such a
+    // wave keeps the general test
+    uint32_t sign_pattern = kMixedSigns;
+    if (LANE && K <= 8) {
+        const bool part = inside && n_spheres > 0;
+        uint32_t neg = 0, pos = 0;
+        bool tame = true;
+        for (int k = 0; k < 3; ++k) {
+            neg |= __ballot(part && ray.inv[k] < 0.0f) ? 1u << k : 0u;
+            pos |= __ballot(part && !(ray.inv[k] < 0.0f)) ? 1u << k : 0u;
+            tame &= __ballot(part && !(fabsf(ray.inv[k]) <= 0x1p40f)) == 0;
+        }
+        if ((neg & pos) == 0 && tame) sign_pattern = neg;
+    }
 
     // ---- compositing state
     float C[3] = {0.0f, 0.0f, 0.0f}, A = 0.0f, T = 1.0f;
@@ -343,8 +368,13 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
         // step has an internal slot at every position in some lane, so the
         // four tests run unconditionally and the slot kinds mask the result
         // once (a sphere slot's words make a meaningless box, never used;
-        // its entry distance only reorders slots that are not pushed)
-        auto box_hits_tn = [&](const float *f, uint32_t kinds, float pf, float tn_out[4]) -> uint32_t {
+        // its entry distance only reorders slots that are not pushed).
+        // With the direction signs known for the wave, the near and far plane
+        // of each axis are known too: for a box with lo <= hi and a positive
+        // 1/d, fma(lo, 1/d, -(o+m)/d) <= fma(hi, 1/d, -(o-m)/d) by monotone
+        // rounding, so the per-axis min and max give exactly these values.
+        auto box_hits_tn = [&](auto sign, const float *f, uint32_t kinds, float pf, float tn_out[4]) -> uint32_t {
+            constexpr int S = decltype(sign)::value;
             uint32_t hits = 0;
 #pragma unroll
             for (int side = 0; side < 4; ++side) {
@@ -352,8 +382,14 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
                 const float t1x = fmaf(s[0], ray.inv[0], -ray.oPi[0]), t2x = fmaf(s[3], ray.inv[0], -ray.oMi[0]);
                 const float t1y = fmaf(s[1], ray.inv[1], -ray.oPi[1]), t2y = fmaf(s[4], ray.inv[1], -ray.oMi[1]);
                 const float t1z = fmaf(s[2], ray.inv[2], -ray.oPi[2]), t2z = fmaf(s[5], ray.inv[2], -ray.oMi[2]);
-                const float tn = fmaxf(fmaxf(fminf(t1x, t2x), fminf(t1y, t2y)), fminf(t1z, t2z));
-                const float tf = fminf(fminf(fmaxf(t1x, t2x), fmaxf(t1y, t2y)), fmaxf(t1z, t2z)) * 1.0000005f;
+                float tn, tf;
+                if constexpr (S == kMixedSigns) {
+                    tn = fmaxf(fmaxf(fminf(t1x, t2x), fminf(t1y, t2y)), fminf(t1z, t2z));
+                    tf = fminf(fminf(fmaxf(t1x, t2x), fmaxf(t1y, t2y)), fmaxf(t1z, t2z)) * 1.0000005f;
+                } else {
+                    tn = fmaxf(fmaxf((S & 1) ? t2x : t1x, (S & 2) ? t2y : t1y), (S & 4) ? t2z : t1z);
+                    tf = fminf(fminf((S & 1) ? t1x : t2x, (S & 2) ? t1y : t2y), (S & 4) ? t1z : t2z) * 1.0000005f;
+                }
                 // tn <= tf, tf >= lo_f and tn <= pf in one comparison (lo_f <= pf for a lane
                 // taking part; pf = -inf for one that does not)
                 const bool h = fmaxf(tn, lo_f) <= fminf(tf, pf);
@@ -370,12 +406,12 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
         };
 
         bool overflow = false;  // the lane's own stack dropped entries
-        if (LANE) {
-            // Per-lane walk: every lane follows its own ray through the tree
-            // (vector loads of its node; stack in its own LDS column, a ring
-            // of kLaneStack entries; children entered nearest box entry
-            // first).  A wave costs the longest path of its lanes rather than
-            // the union of their paths.
+        // Per-lane walk: every lane follows its own ray through the tree
+        // (vector loads of its node; stack in its own LDS column, a ring of
+        // kLaneStack entries; children entered nearest box entry first).  A
+        // wave costs the longest path of its lanes rather than the union of
+        // their paths.  One copy per sign pattern of the wave.
+        auto lane_walk = [&](auto sign) {
             uint32_t node = 0, top = 0, depth = 0, steps = 0;
             bool walking = active;
             // steps run in an inner loop that ends when some lane's queue may
@@ -397,7 +433,7 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
                     const uint32_t kinds = __float_as_uint(f[31]);
                     queue_leaves(f, node, kinds, pr_f);
                     float tn[4];
-                    const uint32_t boxes = box_hits_tn(f, kinds, pr_f, tn);
+                    const uint32_t boxes = box_hits_tn(sign, f, kinds, pr_f, tn);
                     if (boxes) {
                         // sort the slots by entry distance (misses last)
                         uint32_t sl[4] = {0u, 1u, 2u, 3u};
@@ -439,6 +475,23 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
                 }
               } while (__ballot(walking) && !__ballot(nc > (uint32_t)kQueue - 4u));
                 if (__ballot(nc > (uint32_t)kQueue - 4u)) flush();
+            }
+        };
+        if constexpr (LANE && K > 8) {
+            // a large buffer leaves no registers for copies of the walk
+            lane_walk(SignTag<kMixedSigns>{});
+            redo = overflow;
+        } else if (LANE) {
+            switch (sign_pattern) {
+            case 0: lane_walk(SignTag<0>{}); break;
+            case 1: lane_walk(SignTag<1>{}); break;
+            case 2: lane_walk(SignTag<2>{}); break;
+            case 3: lane_walk(SignTag<3>{}); break;
+            case 4: lane_walk(SignTag<4>{}); break;
+            case 5: lane_walk(SignTag<5>{}); break;
+            case 6: lane_walk(SignTag<6>{}); break;
+            case 7: lane_walk(SignTag<7>{}); break;
+            default: lane_walk(SignTag<kMixedSigns>{}); break;
             }
             redo = overflow;
         }

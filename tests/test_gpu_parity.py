@@ -160,6 +160,30 @@ def test_trace_adversarial_scene(sp, half, walk):
         assert_parity(st, exempt_frac=None, context=f"adversarial stop={stop}")
 
 
+@pytest.mark.parametrize("yaw", [0.0, 180.0])
+def test_every_direction_sign_pattern(sp, yaw):
+    """A 90-degree view along -z (yaw 0) or +z (yaw 180) of odd size: its four
+    quadrants give four of the eight sign patterns of the ray directions, so
+    the two views give all eight to the per-lane walk's box test, and the
+    tiles on the middle row and column mix signs, or (the middle column,
+    x + 1/2 = W/2) hold a direction component of exactly 0.  The per-lane walk
+    must match the packet walk bit for bit, and the oracle on every pixel."""
+    cr, col = synth.random_spheres(1500, seed=7, r_lo=0.01, r_hi=0.05)
+    # the eye 0.45 from the centre, outside every sphere (centres within 0.2 of it, radii below 0.05)
+    cam = synth.rotated_camera(synth.source_camera(67, 53, fov_y_deg=90.0, distance=0.45), yaw, 0.0)
+    f = np.array(cam.forward)
+    assert abs(abs(f[2]) - 1.0) < 1e-12
+    print(f"sign patterns yaw={yaw}", flush=True)
+    out = {}
+    for walk in (0, 1):
+        out[walk] = gpu_trace(sp, cr, col, cam, walk=walk)[:2]
+    assert np.array_equal(out[0][0].view(np.uint32), out[1][0].view(np.uint32))
+    assert np.array_equal(out[0][1], out[1][1])
+    st = compare(out[0][0], out[0][1], oracle.render(cr, col, cam))
+    assert_parity(st, exempt_frac=None, context=f"sign patterns yaw={yaw}")
+    assert st["hits_checked"] > 3000
+
+
 @pytest.mark.parametrize("stop", [0.99, NEVER])
 def test_column_along_the_view_ray(sp, stop):
     """16384 spheres strung along the central ray of a 15x15 view: every box on
