@@ -57,7 +57,12 @@ def bvh_layout(cap: int) -> dict:
     leaf_parent = _align(nodes + c * 64)
     node_parent = _align(leaf_parent + c * 4)
     leaf_ids = _align(node_parent + c * 4)
-    return {"nodes": nodes, "leaf_parent": leaf_parent, "node_parent": node_parent, "leaf_ids": leaf_ids}
+    flags = _align(leaf_ids + c * 4)
+    ranges = _align(flags + c * 4)
+    entries = _align(ranges + c * 8)
+    wide = _align(entries + c * 8)
+    return {"nodes": nodes, "leaf_parent": leaf_parent, "node_parent": node_parent, "leaf_ids": leaf_ids,
+            "wide": wide}
 
 
 LEAF = 0x80000000
@@ -121,4 +126,41 @@ def check_bvh(mem: np.ndarray, cap: int, cr: np.ndarray, alpha: np.ndarray) -> d
     assert np.all(seen_leaf == 1), "a sphere is missing or duplicated"
     assert np.all(seen_node == 1), "an internal node is unreachable or shared"
     assert max_depth < 64
+    check_wide(mem, cap, n, f)
     return {"n": n, "depth": max_depth, "leaf_ids": leaf_ids.copy()}
+
+
+def check_wide(mem: np.ndarray, cap: int, n: int, f: np.ndarray):
+    """The 4-wide node of every internal node X, bit for bit, rebuilt here from
+    the binary nodes: per child c of X, an internal child C gives its two slots
+    (words 12c..12c+11), its two refs (24+2c, 25+2c) and its split axis (29+c);
+    a leaf or empty child keeps X's slot, zeros, its ref (an out-of-range
+    internal ref becomes EMPTY), EMPTY and axis 3.  Word 28 is X's axis; word 31
+    the slot kinds: bit s for a leaf ref below n, bit 4+s for an internal ref
+    below the node count."""
+    n_nodes = max(n - 1, 1)
+    u = f.view(np.uint32)
+    w = np.zeros((n_nodes, 32), dtype=np.uint32)
+    w[:, 28] = u[:, 14]
+    for c in range(2):
+        ref = u[:, 12 + c]
+        internal = (ref != EMPTY) & ((ref & LEAF) == 0) & (ref < n_nodes)
+        C = u[np.where(internal, ref, 0)]
+        own = np.concatenate([u[:, 6 * c: 6 * c + 6], np.zeros((n_nodes, 6), np.uint32)], axis=1)
+        w[:, 12 * c: 12 * c + 12] = np.where(internal[:, None], C[:, :12], own)
+        keep = (ref == EMPTY) | ((ref & LEAF) != 0)
+        w[:, 24 + 2 * c] = np.where(internal, C[:, 12], np.where(keep, ref, EMPTY))
+        w[:, 25 + 2 * c] = np.where(internal, C[:, 13], EMPTY)
+        w[:, 29 + c] = np.where(internal, C[:, 14], 3)
+    kinds = np.zeros(n_nodes, dtype=np.uint32)
+    for sl in range(4):
+        r = w[:, 24 + sl]
+        leaf = (r != EMPTY) & ((r & LEAF) != 0)
+        inner = (r != EMPTY) & ((r & LEAF) == 0)
+        kinds |= np.where(leaf & ((r & ~np.uint32(LEAF)) < n), 1 << sl, 0).astype(np.uint32)
+        kinds |= np.where(inner & (r < n_nodes), 1 << (4 + sl), 0).astype(np.uint32)
+    w[:, 31] = kinds
+    off = bvh_layout(cap)["wide"]
+    got = mem[off: off + n_nodes * 128].view(np.uint32).reshape(n_nodes, 32)
+    bad = np.nonzero((got != w).any(axis=1))[0]
+    assert bad.size == 0, f"{bad.size} wide nodes differ from the gather of their binary nodes, first {bad[:8].tolist()}"

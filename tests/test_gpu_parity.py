@@ -11,7 +11,7 @@ import torch
 
 import oracle
 import synth
-from helpers import assert_parity, bvh_core, check_bvh, compare
+from helpers import assert_parity, bvh_core, bvh_layout, check_bvh, compare
 
 pytestmark = pytest.mark.gpu
 
@@ -128,6 +128,11 @@ def test_refit_matches_full_build(sp):
     fresh = sp.build_bvh(sph)
     torch.cuda.synchronize()
     assert torch.equal(bvh_core(bvh.mem, bvh.capacity), bvh_core(fresh.mem, fresh.capacity))
+    # the refit rewrites the 4-wide nodes the trace reads
+    w0 = bvh_layout(bvh.capacity)["wide"]
+    w1 = w0 + (3000 - 1) * 128
+    assert torch.equal(bvh.mem[w0:w1], fresh.mem[w0:w1])
+    check_bvh(bvh.mem.cpu().numpy(), bvh.capacity, sph.centre_radius.cpu().numpy(), sph.rgba[:, 3].cpu().numpy())
 
 
 # ---------------------------------------------------------------- trace
