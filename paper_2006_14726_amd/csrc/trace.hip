@@ -705,7 +705,10 @@ __global__ void __launch_bounds__(64) k_trace(TraceArgs a, int tiles_x, int tile
 }
 
 // Persistent batched trace: waves pull tiles from one atomic counter until
-// the batch is drained; every wave reaches the exit test.
+// the batch is drained.  A wave claims its next tile before it traces the
+// current one, so the atomic's round trip overlaps the tile's first node
+// loads; every claimed tile below the total is traced by the wave that
+// claimed it, and a wave exits at its first claim at or past the total.
 template <int K, bool LANE>
 __global__ void __launch_bounds__(64)
 k_trace_batched(const splat_batch_job *__restrict__ jobs, const uint32_t *__restrict__ tile_offsets, int n_jobs,
@@ -713,20 +716,17 @@ k_trace_batched(const splat_batch_job *__restrict__ jobs, const uint32_t *__rest
                 uint32_t *__restrict__ counter)
 {
     __shared__ WaveLds lds;
-    __shared__ uint32_t item_s;
+    uint32_t claim = 0;
+    if (threadIdx.x == 0) claim = atomicAdd(counter, 1u);
+    uint32_t item = ufirst(claim);
+    int lo = 0;  // job of the wave's last tile
     for (;;) {
-        if (threadIdx.x == 0) item_s = atomicAdd(counter, 1u);
-        __syncthreads();
-        const uint32_t item = ufirst(item_s);
-        __syncthreads();
         if (item >= total_tiles) break;
-        // job of this tile: last offset <= item (binary search, uniform)
-        int lo = 0, hi = n_jobs - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (tile_offsets[mid] <= item) lo = mid;
-            else hi = mid - 1;
-        }
+        claim = 0;
+        if (threadIdx.x == 0) claim = atomicAdd(counter, 1u);
+        // job of this tile: the last offset <= item.  A wave's claims only
+        // grow, so the scan starts at the job of its previous tile
+        while (lo + 1 < n_jobs && tile_offsets[lo + 1] <= item) ++lo;
         const splat_batch_job &j = jobs[lo];
         TraceArgs a;
         a.bvh_mem = j.bvh_mem;
@@ -764,6 +764,7 @@ k_trace_batched(const splat_batch_job *__restrict__ jobs, const uint32_t *__rest
         const char *mem = static_cast<const char *>(j.bvh_mem);
         trace_tile<K, false, LANE>(a, reinterpret_cast<const WideNode *>(mem + L.wide), reinterpret_cast<const BvhHeader *>(mem),
                              t % tiles_x, t / tiles_x, lds);
+        item = ufirst(claim);
     }
 }
 
