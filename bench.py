@@ -41,16 +41,32 @@ def parse():
     p.add_argument("--no-extra", action="store_true",
                    help="skip the radius-scale sweep, the large-frame orbit and the copy bandwidth")
     p.add_argument("--orbit-frames", type=int, default=30, help="frames of the large-frame orbit (0 skips it)")
+    p.add_argument("--workload", choices=("client", "large"), default="client",
+                   help="client: 1024^2 source -> 1920x1080 (the headline); large: 3840x2160 -> 3840x2160 at yaw 15 "
+                        "(for the counter report of the large frame)")
     p.add_argument("--calib-copy-mib", type=int, default=0,
                    help="run one plain device copy of this many MiB first (scales the HBM byte counters)")
     return p.parse_args()
 
 
-def measured_traffic(args):
-    """HBM bytes per trace launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None
-    when the trace kernel source or the launch configuration differs from the one profiled."""
+def source_hash(files) -> str:
+    """sha256[:16] of kernel sources, as recorded in the profile summaries they were measured from."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "trace_client_frame_hbm_traffic.txt")
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, "paper_2006_14726_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+TRACE_SOURCES = ("trace.hip", "common.h", "kernels.h")
+BUILD_SOURCES = ("bvh.hip", "common.h", "kernels.h")
+
+
+def profile_record(name: str, args, sources=TRACE_SOURCES, key="trace_source_sha256_16"):
+    """key = value lines of a committed profile summary, or None when the file is missing, the kernel
+    sources differ from the ones profiled or the launch configuration is not the profiled one."""
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path) or (args.kbuf, args.tile, args.scale, args.walk, args.schedule) != (6, "8x8", 1.0, 0, 2):
         return None
     rec = {}
@@ -58,38 +74,50 @@ def measured_traffic(args):
         if "=" in line and not line.startswith("#"):
             k, v = line.split("=", 1)
             rec[k.strip()] = v.strip()
-    h = hashlib.sha256()
-    for f in ("trace.hip", "common.h", "kernels.h"):
-        with open(os.path.join(ROOT, "paper_2006_14726_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    if rec.get("trace_source_sha256_16") != h.hexdigest()[:16]:
+    if rec.get(key) != source_hash(sources):
         return None
-    return int(float(rec["traffic_bytes_per_dispatch"]))
+    return rec
 
 
-def valu_issue(args, kernel_ms: float):
+def measured_traffic(args, workload="client_frame"):
+    """HBM bytes per trace launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None."""
+    rec = profile_record(f"trace_{workload}_hbm_traffic.txt", args)
+    return None if rec is None else int(float(rec["traffic_bytes_per_dispatch"]))
+
+
+def l2_hit_rate(args, workload="client_frame"):
+    """L2 (TCC) hit rate of the trace kernel from the committed TCC_HIT/TCC_MISS summary, or None."""
+    rec = profile_record(f"trace_{workload}_l2.txt", args)
+    return None if rec is None else float(rec["l2_hit_rate"])
+
+
+def valu_issue(args, kernel_ms: float, workload="client_frame"):
     """Vector-issue occupancy of the trace kernel from the committed SQ counter summary: wave64 vector
     instructions x 4 cycles / 1024 SIMDs, over the kernel's duration at 2.4 GHz; None when the kernel
     source or the launch configuration differs from the one profiled."""
-    import hashlib
-    path = os.path.join(ROOT, "profiles", "trace_client_frame_sq_counters.txt")
-    if not os.path.exists(path) or (args.kbuf, args.tile, args.scale, args.walk, args.schedule) != (6, "8x8", 1.0, 0, 2):
-        return None
-    rec = {}
-    for line in open(path):
-        if "=" in line and not line.startswith("#"):
-            k, v = line.split("=", 1)
-            rec[k.strip()] = v.strip()
-    h = hashlib.sha256()
-    for f in ("trace.hip", "common.h", "kernels.h"):
-        with open(os.path.join(ROOT, "paper_2006_14726_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    if rec.get("trace_source_sha256_16") != h.hexdigest()[:16]:
+    rec = profile_record(f"trace_{workload}_sq_counters.txt", args)
+    if rec is None:
         return None
     valu = float(rec["sq_insts_valu_per_dispatch"])
     busy = valu * 4 / 1024 / (kernel_ms * 1e-3 * 2.4e9)
-    return {"valu_insts_per_launch": int(valu), "valu_busy_frac": round(busy, 3),
+    return {"valu_insts_per_launch": int(valu), "valu_insts_per_wave": float(rec["sq_insts_valu_per_wave"]),
+            "valu_busy_frac": round(busy, 3),
             "note": "vector-instruction issue: the bound of this kernel (4 cycles per wave64 instruction, 1024 SIMDs, 2.4 GHz)"}
+
+
+# Build bytes per sphere as implemented (30-bit codes, four 8-bit radix passes):
+#   bounds 16 (centres) + Morton 24 (centres in, key and id out) + sort 4 x 16 (key and id in and out)
+#   + 12 (three digit histograms read the keys) + Karras 44 (sorted key and id in; per node two
+#   references and the axis, parent, key range and arrival flag; per leaf its parent and id)
+#   + refit 92 (centre, radius and colour word in, leaf id and parent, node parent and range; 48 B
+#   of child slots out)
+# and per internal node the 4-wide node: 3 x 64 B of binary nodes in, 128 B out.
+BUILD_BYTES_PER_SPHERE = 16 + 24 + 4 * 16 + 12 + 44 + 92
+BUILD_BYTES_PER_NODE = 3 * 64 + 128
+
+
+def build_bytes(n: int) -> int:
+    return n * BUILD_BYTES_PER_SPHERE + max(n - 1, 0) * BUILD_BYTES_PER_NODE
 
 
 def trace_bytes(n: int, pixels: int, half: bool) -> int:
@@ -120,7 +148,7 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-    work = synth.CLIENT_FRAME
+    work = synth.CLIENT_FRAME if args.workload == "client" else synth.LARGE
     rgba_np, depth_np, src, dst = synth.source_image(work)
     rgba = torch.from_numpy(rgba_np).to(dev)
     depth = torch.from_numpy(depth_np).to(dev)
@@ -186,6 +214,9 @@ def main():
     trace_ms = float(np.mean([a.elapsed_time(b) for a, b in pairs]))
     tb = trace_bytes(n, P, True)
     achieved = tb / (trace_ms * 1e-3) / 1e9
+    wl = "client_frame" if args.workload == "client" else "large_frame"
+    build_ms = float(np.median(stage[:, 1]))
+    bb = build_bytes(n)
 
     # cold: L2 and MALL flushed by writing a 512 MiB buffer before each trace
     flush = torch.empty(1 << 27, dtype=torch.float32, device=dev)
@@ -210,8 +241,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f64 ray/sphere tests, f32 boxes+compositing, f16 colours",
         "data": "synthetic seeded blob volume, CPU ray-cast 2.5D source image",
-        "config": {"workload": f"client frame: {src.width}x{src.height} source ({n} spheres, radius scale "
-                               f"{args.scale}) -> {dst.width}x{dst.height} target, yaw {work.yaw} pitch {work.pitch}",
+        "config": {"workload": f"{'client' if args.workload == 'client' else 'large'} frame: {src.width}x{src.height} "
+                               f"source ({n} spheres, radius scale {args.scale}) -> {dst.width}x{dst.height} target, "
+                               f"yaw {work.yaw} pitch {work.pitch}",
                    "rays": P, "spheres": n, "kbuf": args.kbuf, "tile": args.tile,
                    "walk": "per-lane" if args.walk == 0 else "packet",
                    "schedule": ["xcd super-tiles", "xcd bands", "heaviest first"][args.schedule], "alpha_stop": 0.99},
@@ -226,20 +258,28 @@ def main():
         "trace_cold_ms": round(float(np.median(cold)), 4),
         "mean_hits_per_ray": round(float(hit_stats.mean()), 3),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": measured_traffic(args),
+                     "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": measured_traffic(args, wl),
                      "kernel": f"k_trace<{args.kbuf}, false, {'true' if args.walk == 0 else 'false'}>",
                      "algorithmic_bytes": tb, "avg_launch_ms": round(trace_ms, 4),
+                     "l2_hit_rate": l2_hit_rate(args, wl),
                      "note": "avg_launch_ms is the trace kernel alone, between events the library records around "
                              "it; trace_call_ms adds the tile-ordering kernels of schedule 2",
-                     "issue": valu_issue(args, trace_ms)},
+                     "issue": valu_issue(args, trace_ms, wl)},
+        "build_roofline": {"bound": "hbm", "achieved": round(bb / (build_ms * 1e-3) / 1e9, 2), "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": round(bb / (build_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5),
+                           "algorithmic_bytes": bb, "build_ms": round(build_ms, 4),
+                           "bytes_per_sphere": BUILD_BYTES_PER_SPHERE, "bytes_per_internal_node": BUILD_BYTES_PER_NODE,
+                           "note": "the whole splat_build_bvh call (every build kernel) between events; bytes as "
+                                   "implemented: four 8-bit radix passes and the 4-wide node gather"},
     }
+    result["l2_hit_rate"] = result["roofline"]["l2_hit_rate"]
 
     if not args.no_extra:
         result["copy_gbs"] = copy_bandwidth(torch, dev)
         result["roofline"]["frac_of_copy"] = round(achieved / result["copy_gbs"], 5)
         result["scale_sweep"] = scale_sweep(sp, torch, src, rgba, depth, dst, opts, max(args.steps, 20))
         if args.orbit_frames > 0:
-            result["large_orbit"] = large_orbit(sp, torch, synth, dev, opts, args.orbit_frames)
+            result["large_orbit"] = large_orbit(sp, torch, synth, dev, opts, args.orbit_frames, args)
         result["server_stage"] = server_stage(sp, torch, synth, dev, src, dst, opts, max(args.steps, 10))
         result["codec"] = codec(sp, torch, synth, sph, bvh, src, dst, opts, max(args.steps, 10))
         result["accumulate"] = accumulate(sp, torch, synth, dev, src, sph, max(args.steps, 10))
@@ -249,8 +289,56 @@ def main():
     if args.batch_frames > 0:
         result["batched"] = batched(sp, torch, synth, dev, args.batch_frames)
     if not args.no_cpu:
-        result["cpu_baseline"] = cpu_baseline(rgba_np, depth_np, src, dst)
+        result["cpu_baseline"], orc = cpu_baseline(rgba_np, depth_np, src, dst, args.scale)
+        result["parity"] = parity(sp, torch, dev, orc, sph, dst, opts)
     print(json.dumps(result), flush=True)
+
+
+def _compare(g, n, orc, tol=1e-4):
+    """GPU pixels against the oracle's (same rules as the parity tests): a pixel passes within `tol` per
+    channel with the same composited hit count, on the oracle's main result or, at a knife-edge, on its
+    alternate; a pixel where a sphere grazes the ray (or with two knife-edges) is exempt."""
+    import oracle
+    g = np.asarray(g, dtype=np.float64).reshape(-1, 4)
+    n = np.asarray(n).reshape(-1).astype(np.int64)
+    flags = orc["flags"]
+    exempt = (flags & (oracle.FLAG_GRAZE | oracle.FLAG_MULTI_KNIFE)) != 0
+    err = np.abs(g - orc["rgba"]).max(axis=1)
+    err_alt = np.abs(g - orc["alt_rgba"]).max(axis=1)
+    ok_alt = (err_alt <= tol) & (n == orc["alt_n"]) & ((flags & oracle.FLAG_KNIFE) != 0)
+    ok = ((err <= tol) & (n == orc["n"])) | ok_alt | exempt
+    strict = ~exempt
+    e = np.where(strict, np.where(ok_alt, np.minimum(err, err_alt), err), 0.0)
+    return {"pixels": int(g.shape[0]), "max_err": float(e.max()) if e.size else 0.0,
+            "mismatches": int((~ok).sum()), "exempt": int(exempt.sum()),
+            "knife": int(((flags & oracle.FLAG_KNIFE) != 0).sum()), "hits_checked": int(n[strict].sum())}
+
+
+def parity(sp, torch, dev, orc, sph, dst, opts):
+    """The timed configuration against the FP64 oracle, on the pixels the CPU baseline rendered.
+    Unprojection: the timed GPU sphere set against the oracle's own unprojection of the same image
+    (count and order exact, centre and radius within 1 ulp, colours bit-exact).  Trace: the oracle's
+    sphere set uploaded, built and traced with the timed options, compared pixel by pixel (<= 1e-4 per
+    RGBA channel, exact hit counts; grazing pixels exempt up to 1e-4 of the pixels)."""
+    cr, col, idx = orc["spheres"]
+    n = sph.n()
+    g_cr = sph.centre_radius[:n].cpu().numpy()
+    unp = {"count_equal": bool(n == cr.shape[0])}
+    if unp["count_equal"]:
+        unp["order_equal"] = bool(np.array_equal(sph.src_index[:n].cpu().numpy().view(np.uint32), idx))
+        unp["max_ulp"] = int(np.abs(g_cr.view(np.int32).astype(np.int64) - cr.view(np.int32)).max())
+        unp["colours_equal"] = bool(np.array_equal(sph.rgba[:n].cpu().numpy().view(np.uint16), col.view(np.uint16)))
+    s2 = sp.spheres_from_tensors(torch.from_numpy(cr).to(dev), torch.from_numpy(col).to(dev))
+    img, hits = sp.trace(sp.build_bvh(s2), s2, dst, opts)
+    torch.cuda.synchronize()
+    pix = orc["pixels"]
+    st = _compare(img.cpu().numpy().reshape(-1, 4)[pix], hits.cpu().numpy().reshape(-1)[pix], orc["render"])
+    st["exempt_budget"] = max(1, int(1e-4 * st["pixels"]))
+    st["ok"] = bool(st["mismatches"] == 0 and st["exempt"] <= st["exempt_budget"] and unp.get("max_ulp", 9) <= 1
+                    and unp.get("order_equal") and unp.get("colours_equal"))
+    st["unproject"] = unp
+    st["tolerance"] = "max abs 1e-4 per RGBA channel, exact hit counts, FP64 oracle on the same sphere arrays"
+    return st
 
 
 def fwd_bwd(sp, torch, synth, dev, steps):
@@ -361,7 +449,7 @@ def scale_sweep(sp, torch, src, rgba, depth, dst, opts, reps):
     return out
 
 
-def large_orbit(sp, torch, synth, dev, opts, frames):
+def large_orbit(sp, torch, synth, dev, opts, frames, args):
     """Large frame: 3840x2160 source -> 3840x2160 targets at yaw 15 + k deg, k = 0..frames-1;
     unproject, rebuild and trace every frame."""
     rgba_np, depth_np, src, dst0 = synth.source_image(synth.LARGE)
@@ -378,6 +466,18 @@ def large_orbit(sp, torch, synth, dev, opts, frames):
     t = np.array([_events(torch, [lambda: sp.unproject(src, rgba, depth, 1.0, True, out=sph),
                                   lambda: sp.build_bvh(sph, bvh),
                                   lambda c=c: sp.trace(bvh, sph, c, opts, out=img, hits=hits)]) for c in cams])
+    # the trace kernel alone per pose (events the library records around it)
+    pairs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in cams]
+    for a, b in pairs:
+        a.record()
+        b.record()
+    torch.cuda.synchronize()
+    for (a, b), c in zip(pairs, cams):
+        o_ev = copy.copy(opts)
+        o_ev.events = (a.cuda_event, b.cuda_event)
+        sp.trace(bvh, sph, c, o_ev, out=img, hits=hits)
+    torch.cuda.synchronize()
+    kern = np.array([a.elapsed_time(b) for a, b in pairs])
     rays = dst0.width * dst0.height
     frame = t.sum(axis=1)
     res = {"workload": f"{src.width}x{src.height} source ({sph.n()} spheres) -> {dst0.width}x{dst0.height}, "
@@ -387,6 +487,19 @@ def large_orbit(sp, torch, synth, dev, opts, frames):
     for i, k in enumerate(("unproject", "build", "trace")):
         res[k + "_ms"] = [round(float(t[:, i].mean()), 4), round(float(t[:, i].min()), 4), round(float(t[:, i].max()), 4)]
     res["format"] = "stage_ms: [mean, min, max] over the frames"
+    n = sph.n()
+    tb = trace_bytes(n, rays, True)
+    ach = tb / (float(kern.mean()) * 1e-3) / 1e9
+    res["roofline"] = {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": round(ach / HBM_PEAK_GBS, 5), "algorithmic_bytes": tb,
+                       "avg_launch_ms": round(float(kern.mean()), 4), "kernel": "trace kernel alone, mean over the poses",
+                       "traffic": measured_traffic(args, "large_frame"),
+                       "l2_hit_rate": l2_hit_rate(args, "large_frame")}
+    bb = build_bytes(n)
+    bms = float(t[:, 1].mean())
+    res["build_roofline"] = {"bound": "hbm", "achieved": round(bb / (bms * 1e-3) / 1e9, 2), "peak": HBM_PEAK_GBS,
+                             "unit": "GB/s", "frac": round(bb / (bms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5),
+                             "algorithmic_bytes": bb, "build_ms": round(bms, 4)}
     del sph, bvh, img, hits
     return res
 
@@ -513,30 +626,34 @@ def _cpu_model() -> str:
     return "unknown"
 
 
-def cpu_baseline(rgba_np, depth_np, src, dst):
+def cpu_baseline(rgba_np, depth_np, src, dst, scale):
     """The FP64 brute-force oracle on a bounded pixel sample of the same frame, on the host cores.
-    Its spheres come from its own unprojection of the source image."""
+    Its spheres come from its own unprojection of the source image at the timed radius scale.  Returns
+    the baseline record and what the oracle rendered (for the parity check of the timed frame)."""
     import oracle
-    cr, col, _ = oracle.unproject(src, rgba_np, depth_np, 1.0, True)
+    cr, col, idx = oracle.unproject(src, rgba_np, depth_np, scale, True)
     n = cr.shape[0]
     rng = np.random.default_rng(0)
     table = oracle.sphere_table(cr, col)
     oracle.render_table(table, dst, pixels=rng.integers(0, dst.width * dst.height, 64))  # warm
-    # batches of random pixels until at least 10 s of oracle time
-    count, dt, batch = 0, 0.0, 2048
+    # batches of distinct random pixels until at least 10 s of oracle time
+    perm = rng.permutation(dst.width * dst.height)
+    count, dt, batch, parts = 0, 0.0, 2048, []
     while dt < 10.0 and count < 400000:
-        pix = rng.integers(0, dst.width * dst.height, batch)
+        pix = perm[count:count + batch]
         t0 = time.perf_counter()
-        oracle.render_table(table, dst, pixels=pix)
+        parts.append((pix, oracle.render_table(table, dst, pixels=pix)))
         step = time.perf_counter() - t0
         dt += step
-        count += batch
+        count += pix.size
         batch = int(min(max(batch, batch * (10.0 - dt) / max(step, 1e-3)), 100000)) if dt < 10.0 else batch
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": round(count / dt / 1e6, 6), "unit": "Mrays/s", "cores": cores, "kind": "oracle",
-            "nproc": os.cpu_count(), "cpu_model": _cpu_model(),
-            "sample": f"{count} random pixels of the same 1920x1080 frame, all {n} spheres tested per ray "
-                      f"(brute force, FP64), {dt:.1f} s"}
+    rec = {"value": round(count / dt / 1e6, 6), "unit": "Mrays/s", "cores": cores, "kind": "oracle",
+           "nproc": os.cpu_count(), "cpu_model": _cpu_model(),
+           "sample": f"{count} distinct random pixels of the same {dst.width}x{dst.height} frame (radius scale "
+                     f"{scale}), all {n} spheres tested per ray (brute force, FP64), {dt:.1f} s"}
+    render = {k: np.concatenate([r[k] for _, r in parts]) for k in ("rgba", "n", "flags", "alt_rgba", "alt_n")}
+    return rec, {"pixels": np.concatenate([p for p, _ in parts]), "render": render, "spheres": (cr, col, idx)}
 
 
 if __name__ == "__main__":

@@ -16,7 +16,7 @@ import torch
 
 from . import _lib
 from .render import (BVH, Spheres, TraceOptions, _ptr, _stream, alloc_bvh, alloc_spheres, build_bvh, trace,
-                     unproject, workspace)
+                     unproject)
 
 
 @dataclass
@@ -56,11 +56,15 @@ class BatchedRenderer:
         self._build_jobs()
         self.ws = torch.zeros(lib.splat_workspace_bytes(_lib.SPLAT_OP_BATCHED, self.n_jobs, 0, 0), dtype=torch.uint8,
                               device=dev)
-        # grow the shared workspaces now so that nothing allocates during capture
-        for fr, s in zip(frames, self.spheres):
-            workspace(lib.splat_workspace_bytes(_lib.SPLAT_OP_UNPROJECT, 0, fr.src_cam.width, fr.src_cam.height),
-                      dev, "unproject")
-            workspace(lib.splat_workspace_bytes(_lib.SPLAT_OP_BUILD, s.capacity, 0, 0), dev, "build")
+        # workspaces of its own, sized for the largest frame: a captured graph
+        # keeps their addresses, so no other caller may replace or free them
+        self.ws_unproject = torch.empty(max(256, *(lib.splat_workspace_bytes(_lib.SPLAT_OP_UNPROJECT, 0, fr.src_cam.width,
+                                                                      fr.src_cam.height) for fr in frames)),
+                                        dtype=torch.uint8, device=dev)
+        self.ws_build = torch.empty(max(256, *(lib.splat_workspace_bytes(_lib.SPLAT_OP_BUILD, s.capacity, 0, 0)
+                                                 for s in self.spheres)), dtype=torch.uint8, device=dev)
+        self.ws_trace = torch.empty(max(256, *(lib.splat_workspace_bytes(_lib.SPLAT_OP_TRACE, 0, c.width, c.height)
+                                                 for fr in frames for c in fr.dst_cams)), dtype=torch.uint8, device=dev)
         self.graph = None
 
     def set_schedule(self, opts: TraceOptions, waves: int) -> None:
@@ -100,8 +104,8 @@ class BatchedRenderer:
     def prepare(self):
         """Unproject and build every frame (plain launches)."""
         for fr, s, b in zip(self.frames, self.spheres, self.bvhs):
-            unproject(fr.src_cam, fr.rgba, fr.depth, self.radius_scale, self.half, out=s)
-            build_bvh(s, b)
+            unproject(fr.src_cam, fr.rgba, fr.depth, self.radius_scale, self.half, out=s, ws=self.ws_unproject)
+            build_bvh(s, b, ws=self.ws_build)
 
     def trace_batched(self):
         """Every job in one persistent launch (splat_trace_batched)."""
@@ -120,7 +124,7 @@ class BatchedRenderer:
         for fi, fr in enumerate(self.frames):
             for vi, cam in enumerate(fr.dst_cams):
                 out, hits = self.outputs[fi][vi]
-                trace(self.bvhs[fi], self.spheres[fi], cam, self.opts, out=out, hits=hits)
+                trace(self.bvhs[fi], self.spheres[fi], cam, self.opts, out=out, hits=hits, ws=self.ws_trace)
 
     def capture(self):
         """Capture run() into a HIP graph (torch.cuda.CUDAGraph over hipGraph)."""

@@ -33,15 +33,33 @@ def _require_cuda(t: torch.Tensor, name: str, dtype=None, contiguous=True):
 
 
 _workspaces: dict = {}
+# Buffers a larger request replaced.  A captured HIP graph keeps the raw
+# address of the buffer it was recorded with, so a replaced buffer is never
+# freed: a replay then still writes memory that it owns.
+_retired: list = []
 
 
 def workspace(nbytes: int, device, tag: str) -> torch.Tensor:
-    """Grow-only scratch buffer per (device, tag)."""
+    """Grow-only scratch buffer per (device, tag), shared by the eager calls of
+    this process.  Calls on one stream run in order, so sharing is safe there;
+    a caller that needs a buffer of its own passes `ws=` to the wrappers."""
     key = (str(device), tag)
     ws = _workspaces.get(key)
     if ws is None or ws.numel() < nbytes:
+        if ws is not None:
+            _retired.append(ws)
         ws = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
         _workspaces[key] = ws
+    return ws
+
+
+def _own_ws(ws: torch.Tensor | None, nbytes: int, device, tag: str) -> torch.Tensor:
+    """The caller's workspace if given (checked for size), else the shared one."""
+    if ws is None:
+        return workspace(nbytes, device, tag)
+    _require_cuda(ws, "ws", torch.uint8)
+    if ws.numel() < nbytes:
+        raise ValueError(f"ws holds {ws.numel()} bytes, {tag} needs {nbytes}")
     return ws
 
 
@@ -171,7 +189,8 @@ def decode_samples(pos: torch.Tensor, col: torch.Tensor, count: torch.Tensor, bo
 
 
 def accumulate(frame: Spheres, history: Spheres | None, history_age: torch.Tensor | None, box_lo, box_size: float,
-               grid: int, max_age: int, out: Spheres | None = None, out_age: torch.Tensor | None = None):
+               grid: int, max_age: int, out: Spheres | None = None, out_age: torch.Tensor | None = None,
+               ws: torch.Tensor | None = None):
     """Temporal accumulation (splat_accumulate): the new frame's samples, then the history samples whose grid
     cell the frame leaves free and whose age + 1 <= max_age.  Returns (merged Spheres, uint8 ages)."""
     dev = frame.centre_radius.device
@@ -192,7 +211,7 @@ def accumulate(frame: Spheres, history: Spheres | None, history_age: torch.Tenso
     o.box_size, o.grid, o.max_age = float(box_size), int(grid), int(max_age)
     lib = _lib.load()
     hcap = history.capacity if history is not None else 0
-    ws = workspace(lib.splat_workspace_bytes(_lib.SPLAT_OP_ACCUMULATE, hcap, int(grid), 0), dev, "accumulate")
+    ws = _own_ws(ws, lib.splat_workspace_bytes(_lib.SPLAT_OP_ACCUMULATE, hcap, int(grid), 0), dev, "accumulate")
     f, r = frame.struct(), out.struct()
     h = history.struct() if history is not None else None
     _lib.check(lib.splat_accumulate(ctypes.byref(f), ctypes.byref(h) if h is not None else None,
@@ -202,7 +221,7 @@ def accumulate(frame: Spheres, history: Spheres | None, history_age: torch.Tenso
 
 
 def unproject(src_cam, rgba: torch.Tensor, depth: torch.Tensor, radius_scale: float = 1.0, half: bool = True,
-              out: Spheres | None = None) -> Spheres:
+              out: Spheres | None = None, ws: torch.Tensor | None = None) -> Spheres:
     """Eq. 1 unprojection of a premultiplied RGBA + depth image into spheres (splat_unproject)."""
     H, W = int(src_cam.height), int(src_cam.width)
     _require_cuda(rgba, "rgba", torch.float32)
@@ -213,7 +232,7 @@ def unproject(src_cam, rgba: torch.Tensor, depth: torch.Tensor, radius_scale: fl
         out = alloc_spheres(H * W, rgba.device, half)
     lib = _lib.load()
     need = lib.splat_workspace_bytes(_lib.SPLAT_OP_UNPROJECT, 0, W, H)
-    ws = workspace(need, rgba.device, "unproject")
+    ws = _own_ws(ws, need, rgba.device, "unproject")
     cam = _lib.camera_struct(src_cam)
     s = out.struct()
     _lib.check(lib.splat_unproject(ctypes.byref(cam), _ptr(rgba), _ptr(depth), float(radius_scale), ctypes.byref(s),
@@ -223,7 +242,7 @@ def unproject(src_cam, rgba: torch.Tensor, depth: torch.Tensor, radius_scale: fl
 
 def unproject_policy(src_cam, rgba: torch.Tensor, depth: torch.Tensor, mode: int, radius_scale: float = 1.0,
                      opacity_floor: float = 0.05, interval_scale: float = 1.0, interval: torch.Tensor | None = None,
-                     half: bool = True, out: Spheres | None = None) -> Spheres:
+                     half: bool = True, out: Spheres | None = None, ws: torch.Tensor | None = None) -> Spheres:
     """Unprojection with a radius policy (splat_unproject_policy): SPLAT_RADIUS_FOOTPRINT, _OPACITY
     (r = s fp sqrt(max(A, floor))) or _INTERVAL (centre at the depth interval's midpoint,
     r = max(s fp, interval_scale half-length); needs `interval` [H, W, 2] from `raymarch`)."""
@@ -239,7 +258,7 @@ def unproject_policy(src_cam, rgba: torch.Tensor, depth: torch.Tensor, mode: int
     if out is None:
         out = alloc_spheres(H * W, rgba.device, half)
     lib = _lib.load()
-    ws = workspace(lib.splat_workspace_bytes(_lib.SPLAT_OP_UNPROJECT, 0, W, H), rgba.device, "unproject")
+    ws = _own_ws(ws, lib.splat_workspace_bytes(_lib.SPLAT_OP_UNPROJECT, 0, W, H), rgba.device, "unproject")
     pol = _lib.splat_radius_policy()
     pol.mode, pol.radius_scale = int(mode), float(radius_scale)
     pol.opacity_floor, pol.interval_scale = float(opacity_floor), float(interval_scale)
@@ -267,13 +286,13 @@ def alloc_bvh(capacity: int, device) -> BVH:
     return BVH(torch.zeros(nbytes, dtype=torch.uint8, device=device), int(capacity))
 
 
-def build_bvh(sph: Spheres, bvh: BVH | None = None, refit_only: bool = False) -> BVH:
+def build_bvh(sph: Spheres, bvh: BVH | None = None, refit_only: bool = False, ws: torch.Tensor | None = None) -> BVH:
     """LBVH build (or refit of the previous hierarchy) over a sphere set (splat_build_bvh)."""
     if bvh is None:
         bvh = alloc_bvh(sph.capacity, sph.centre_radius.device)
     lib = _lib.load()
     need = lib.splat_workspace_bytes(_lib.SPLAT_OP_BUILD, sph.capacity, 0, 0)
-    ws = workspace(need, sph.centre_radius.device, "build")
+    ws = _own_ws(ws, need, sph.centre_radius.device, "build")
     s, b = sph.struct(), bvh.struct()
     _lib.check(lib.splat_build_bvh(ctypes.byref(s), ctypes.byref(b), int(bool(refit_only)), _ptr(ws), ws.numel(),
                                    _stream()))
@@ -308,7 +327,7 @@ class TraceOptions:
 
 
 def trace(bvh: BVH, sph: Spheres, cam, opts: TraceOptions | None = None, out: torch.Tensor | None = None,
-          hits: torch.Tensor | None = None, want_hits: bool = True):
+          hits: torch.Tensor | None = None, want_hits: bool = True, ws: torch.Tensor | None = None):
     """Trace and composite from `cam` (splat_trace).  Returns (rgba [H, W, 4] float32, hits [H, W] int32 or None)."""
     opts = opts or TraceOptions()
     H, W = int(cam.height), int(cam.width)
@@ -325,7 +344,7 @@ def trace(bvh: BVH, sph: Spheres, cam, opts: TraceOptions | None = None, out: to
     lib = _lib.load()
     c, o, s, b = _lib.camera_struct(cam), opts.struct(), sph.struct(), bvh.struct()
     need = lib.splat_workspace_bytes(_lib.SPLAT_OP_TRACE, 0, W, H)
-    ws = workspace(need, dev, "trace")
+    ws = _own_ws(ws, need, dev, "trace")
     _lib.check(lib.splat_trace(ctypes.byref(b), ctypes.byref(s), ctypes.byref(c), ctypes.byref(o), _ptr(out),
                                _ptr(hits), _ptr(ws), ws.numel(), _stream()))
     return out, hits
@@ -354,7 +373,7 @@ def zero_grads(grads: dict) -> None:
 
 
 def trace_backward(bvh: BVH, sph: Spheres, cam, opts: TraceOptions, out_rgba: torch.Tensor, grad_rgba: torch.Tensor,
-                   grads: dict | None = None) -> dict:
+                   grads: dict | None = None, ws: torch.Tensor | None = None) -> dict:
     """Accumulate dL/d(rgb, alpha, radius, centre) per sphere (splat_trace_backward)."""
     dev = sph.centre_radius.device
     cap = sph.capacity
@@ -371,7 +390,7 @@ def trace_backward(bvh: BVH, sph: Spheres, cam, opts: TraceOptions, out_rgba: to
     lib = _lib.load()
     c, o, s, b = _lib.camera_struct(cam), opts.struct(), sph.struct(), bvh.struct()
     need = lib.splat_workspace_bytes(_lib.SPLAT_OP_BACKWARD, 0, W, H)
-    ws = workspace(need, dev, "trace")
+    ws = _own_ws(ws, need, dev, "trace")
     _lib.check(lib.splat_trace_backward(ctypes.byref(b), ctypes.byref(s), ctypes.byref(c), ctypes.byref(o),
                                         _ptr(out_rgba), _ptr(grad_rgba), ctypes.byref(g), _ptr(ws), ws.numel(),
                                         _stream()))

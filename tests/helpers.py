@@ -164,3 +164,101 @@ def check_wide(mem: np.ndarray, cap: int, n: int, f: np.ndarray):
     got = mem[off: off + n_nodes * 128].view(np.uint32).reshape(n_nodes, 32)
     bad = np.nonzero((got != w).any(axis=1))[0]
     assert bad.size == 0, f"{bad.size} wide nodes differ from the gather of their binary nodes, first {bad[:8].tolist()}"
+
+
+# ---------------------------------------------------------------- sampling
+
+def tile_sample(width: int, height: int, tile: int, rng) -> np.ndarray:
+    """One random pixel in every tile x tile block of the image (row-major indices)."""
+    tx, ty = np.meshgrid(np.arange(0, width, tile), np.arange(0, height, tile))
+    px = np.minimum(tx + rng.integers(0, tile, tx.shape), width - 1)
+    py = np.minimum(ty + rng.integers(0, tile, ty.shape), height - 1)
+    return (py * width + px).ravel()
+
+
+def project_centres(cr: np.ndarray, cam) -> tuple[np.ndarray, np.ndarray]:
+    """Continuous pixel coordinates (x, y) of the sphere centres in `cam` (pinhole, row 0 at the top);
+    centres behind the camera get NaN.  Host geometry only: it picks which pixels to check."""
+    c = cr[:, :3].astype(np.float64) - np.asarray(cam.eye, dtype=np.float64)
+    z = c @ np.asarray(cam.forward, dtype=np.float64)
+    x = c @ np.asarray(cam.right, dtype=np.float64)
+    y = c @ np.asarray(cam.up, dtype=np.float64)
+    aspect = cam.width / cam.height
+    with np.errstate(divide="ignore", invalid="ignore"):
+        sx = np.where(z > 0, x / (z * cam.tan_half_fov_y * aspect), np.nan)
+        sy = np.where(z > 0, y / (z * cam.tan_half_fov_y), np.nan)
+    return (sx + 1.0) * 0.5 * cam.width, (1.0 - sy) * 0.5 * cam.height
+
+
+def silhouette_pixels(cr: np.ndarray, cam, rng, tile: int = 8, count: int = 16) -> np.ndarray:
+    """Every pixel of 2 x `count` tiles where the exact tests are hardest: the tiles with the most
+    projected sphere centres (the sheet of samples seen edge-on, where rays graze many spheres),
+    and tiles on the edge of coverage (centres in the tile, none in a neighbour: silhouettes and
+    disocclusion borders).  Chosen from the sphere set alone, never from a GPU result."""
+    W, H = cam.width, cam.height
+    tx_n, ty_n = (W + tile - 1) // tile, (H + tile - 1) // tile
+    x, y = project_centres(cr, cam)
+    ok = np.isfinite(x) & np.isfinite(y) & (x >= 0) & (y >= 0) & (x < W) & (y < H)
+    t = (y[ok] // tile).astype(np.int64) * tx_n + (x[ok] // tile).astype(np.int64)
+    cnt = np.bincount(t, minlength=tx_n * ty_n).reshape(ty_n, tx_n)
+    heavy = np.argsort(cnt.ravel(), kind="stable")[::-1][:count]
+    pad = np.pad(cnt, 1)
+    nb_min = np.min([pad[1 + dy:1 + dy + ty_n, 1 + dx:1 + dx + tx_n]
+                     for dy in (-1, 0, 1) for dx in (-1, 0, 1) if dy or dx], axis=0)
+    edge = np.nonzero(((cnt > 0) & (nb_min == 0)).ravel())[0]
+    if edge.size > count:
+        edge = rng.choice(edge, size=count, replace=False)
+    tiles = np.unique(np.concatenate([heavy, edge]))
+    ox, oy = np.meshgrid(np.arange(tile), np.arange(tile))
+    px = (tiles % tx_n)[:, None] * tile + ox.ravel()[None, :]
+    py = (tiles // tx_n)[:, None] * tile + oy.ravel()[None, :]
+    keep = (px < W) & (py < H)
+    return np.unique((py * W + px)[keep])
+
+
+# ---------------------------------------------------------------- build pins
+
+def morton30(cr: np.ndarray, lo: np.ndarray, hi: np.ndarray) -> np.ndarray:
+    """30-bit Morton codes of the centres in the box [lo, hi], float32 arithmetic: per axis
+    u = (p - lo) / (hi - lo) (0 for a flat axis), q = clamp(trunc(1024 u), 0, 1023); bit 3k+2
+    of the code is bit k of q_x, 3k+1 of q_y, 3k of q_z."""
+    p = cr[:, :3].astype(np.float32)
+    lo = np.asarray(lo, dtype=np.float32)
+    ext = np.asarray(hi, dtype=np.float32) - lo
+    with np.errstate(divide="ignore", invalid="ignore"):
+        u = np.where(ext > 0, (p - lo) / np.where(ext > 0, ext, np.float32(1)), np.float32(0)).astype(np.float32)
+    q = np.clip(np.trunc(u * np.float32(1024.0)), 0, 1023).astype(np.uint32)
+    code = np.zeros(p.shape[0], dtype=np.uint32)
+    for k in range(10):
+        for a, off in ((0, 2), (1, 1), (2, 0)):
+            code |= ((q[:, a] >> k) & 1) << (3 * k + off)
+    return code
+
+
+def karras_by_split(keys: np.ndarray, ids: np.ndarray) -> dict:
+    """Binary radix tree over sorted keys by recursive splitting: a range [lo, hi] of sorted
+    positions splits where the highest bit in which the (key, position) pairs of its two ends
+    differ turns from 0 to 1.  Node numbering as in the linear construction: the root is 0, a child
+    range [lo, g] is node g and [g + 1, hi] node g + 1, and a single position is a leaf
+    (LEAF | sphere id).  Returns {node: (left ref, right ref, split axis)}."""
+    n = keys.shape[0]
+    aug = [(int(k) << 32) | i for i, k in enumerate(keys)]
+    out = {}
+    stack = [(0, 0, n - 1)]
+    while stack:
+        node, lo, hi = stack.pop()
+        diff = aug[lo] ^ aug[hi]
+        bit = diff.bit_length() - 1
+        g = lo
+        while g + 1 <= hi and not ((aug[g + 1] >> bit) & 1):
+            g += 1
+        prefix = 63 - bit  # common leading bits of the 64-bit pair
+        axis = 2 - ((31 - prefix) % 3) if prefix < 32 else 3
+        left = (LEAF | int(ids[g])) if g == lo else g
+        right = (LEAF | int(ids[g + 1])) if g + 1 == hi else g + 1
+        out[node] = (left, right, axis)
+        if g != lo:
+            stack.append((g, lo, g))
+        if g + 1 != hi:
+            stack.append((g + 1, g + 1, hi))
+    return out

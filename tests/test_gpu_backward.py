@@ -43,6 +43,8 @@ def check_close(gpu, ref, rel=1e-3, floor_frac=1e-2, cols=range(8)):
         nz = np.abs(r[r != 0])
         tau = floor_frac * (np.median(nz) if nz.size else 1.0)
         bound = rel * np.maximum(np.abs(r), tau)
+        worst = float(np.max(np.abs(gpu[:, c] - r) / bound)) * rel if r.size else 0.0
+        print(f"  param {c}: max |g - ref| / max(|ref|, tau) = {worst:.2e}", flush=True)
         bad = np.nonzero(np.abs(gpu[:, c] - r) > bound)[0]
         assert bad.size == 0, f"param {c}: {bad.size} spheres off, e.g. {bad[:5]} gpu {gpu[bad[:5], c]} ref {r[bad[:5]]}"
 
@@ -76,7 +78,7 @@ def test_backward_with_restarts(sp):
         gr = sp.trace_backward(bvh, sph, cam, opts, out, up(g.reshape(cam.height, cam.width, 4).astype(np.float32)))
         gpu = np.concatenate([gr["centre"].cpu().numpy(), gr["radius"].cpu().numpy()[:, None],
                               gr["rgb"].cpu().numpy(), gr["alpha"].cpu().numpy()[:, None]], axis=1)
-        check_close(gpu.astype(np.float64), ref, rel=2e-3)
+        check_close(gpu.astype(np.float64), ref)
 
 
 def test_backward_matches_central_differences_on_differentiable_config(sp):
