@@ -494,7 +494,11 @@ def large_orbit(sp, torch, synth, dev, opts, frames, args):
                        "frac": round(ach / HBM_PEAK_GBS, 5), "algorithmic_bytes": tb,
                        "avg_launch_ms": round(float(kern.mean()), 4), "kernel": "trace kernel alone, mean over the poses",
                        "traffic": measured_traffic(args, "large_frame"),
-                       "l2_hit_rate": l2_hit_rate(args, "large_frame")}
+                       "l2_hit_rate": l2_hit_rate(args, "large_frame"),
+                       "pose0_launch_ms": round(float(kern[0]), 4),
+                       "issue": valu_issue(args, float(kern[0]), "large_frame"),
+                       "note": "traffic, l2_hit_rate and issue are the committed counter figures of pose k = 0 "
+                               "(yaw 15), the launch profiled with --workload large"}
     bb = build_bytes(n)
     bms = float(t[:, 1].mean())
     res["build_roofline"] = {"bound": "hbm", "achieved": round(bb / (bms * 1e-3) / 1e9, 2), "peak": HBM_PEAK_GBS,
