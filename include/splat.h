@@ -123,7 +123,8 @@ typedef struct splat_bvh {
  *               hipEvent_t or NULL: recorded on the stream immediately
  *               before and after the trace kernel itself (after the tile
  *               ordering of schedule 2), to time that kernel alone.  Only
- *               splat_trace and splat_trace_backward record them
+ *               splat_trace, splat_trace_noalloc and splat_trace_backward
+ *               record them
  */
 typedef struct splat_trace_opts {
     float alpha_stop;
@@ -371,6 +372,25 @@ int splat_build_bvh(const splat_spheres *sph, const splat_bvh *bvh, int32_t refi
  */
 int splat_trace(const splat_bvh *bvh, const splat_spheres *sph, const splat_camera *cam, const splat_trace_opts *opts,
                 float *out_rgba, uint32_t *out_hits, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * splat_trace without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, checks and result as splat_trace
+ * (bit for bit); the tile-order workspace of schedule 2 is a static device
+ * array of splat_trace_noalloc_max_bytes() bytes (4 MiB) that every device the
+ * library runs on holds until the process ends.  No call allocates.
+ *   SPLAT_ENOSPC  schedule 2 on an image whose tile order needs more than that
+ *                 (splat_workspace_bytes(SPLAT_OP_TRACE, ...) > 4 MiB, about
+ *                 22 M pixels); schedules 0 and 1 need no scratch
+ * All calls on one device share its array: calls that overlap on one device
+ * (two streams, two threads) race.  Every call clears what it reads first.
+ */
+int splat_trace_noalloc(const splat_bvh *bvh, const splat_spheres *sph, const splat_camera *cam,
+                        const splat_trace_opts *opts, float *out_rgba, uint32_t *out_hits, void *stream);
+
+/* Bytes of the static scratch of splat_trace_noalloc. */
+size_t splat_trace_noalloc_max_bytes(void);
 
 /*
  * Backward of splat_trace: given dL/d(out_rgba), accumulates dL/dk, dL/da,

@@ -17,7 +17,8 @@ SPLAT_OP_UNPROJECT, SPLAT_OP_BUILD, SPLAT_OP_TRACE, SPLAT_OP_BACKWARD, SPLAT_OP_
 # every symbol include/splat.h declares
 EXPORTS = ["splat_workspace_bytes", "splat_bvh_bytes", "splat_raymarch", "splat_encode_samples",
            "splat_decode_samples", "splat_accumulate", "splat_unproject", "splat_unproject_policy", "splat_build_bvh", "splat_trace", "splat_trace_backward",
-           "splat_trace_batched", "splat_last_error", "splat_version"]
+           "splat_trace_batched", "splat_last_error", "splat_version", "splat_trace_noalloc",
+           "splat_trace_noalloc_max_bytes"]
 
 _P = ctypes.c_void_p
 
@@ -103,6 +104,10 @@ def load() -> ctypes.CDLL:
         lib.splat_trace.argtypes = [ctypes.POINTER(splat_bvh), ctypes.POINTER(splat_spheres),
                                     ctypes.POINTER(splat_camera), ctypes.POINTER(splat_trace_opts), _P, _P, _P,
                                     ctypes.c_size_t, _P]
+        lib.splat_trace_noalloc.argtypes = [ctypes.POINTER(splat_bvh), ctypes.POINTER(splat_spheres),
+                                            ctypes.POINTER(splat_camera), ctypes.POINTER(splat_trace_opts), _P, _P, _P]
+        lib.splat_trace_noalloc_max_bytes.argtypes = []
+        lib.splat_trace_noalloc_max_bytes.restype = ctypes.c_size_t
         lib.splat_trace_backward.argtypes = [ctypes.POINTER(splat_bvh), ctypes.POINTER(splat_spheres),
                                              ctypes.POINTER(splat_camera), ctypes.POINTER(splat_trace_opts), _P, _P,
                                              ctypes.POINTER(splat_grads), _P, ctypes.c_size_t, _P]
@@ -124,7 +129,7 @@ def load() -> ctypes.CDLL:
                                          ctypes.POINTER(splat_accum_opts), ctypes.POINTER(splat_spheres), _P, _P,
                                          ctypes.c_size_t, _P]
         for name in ("splat_raymarch", "splat_encode_samples", "splat_decode_samples", "splat_accumulate",
-                     "splat_unproject", "splat_unproject_policy", "splat_build_bvh", "splat_trace",
+                     "splat_unproject", "splat_unproject_policy", "splat_build_bvh", "splat_trace", "splat_trace_noalloc",
                      "splat_trace_backward",
                      "splat_trace_batched"):
             getattr(lib, name).restype = ctypes.c_int

@@ -392,6 +392,56 @@ int splat_trace(const splat_bvh *bvh, const splat_spheres *sph, const splat_came
                       "trace launch");
 }
 
+// Scratch of splat_trace_noalloc: the tile-order workspace of the heaviest-first
+// schedule, in a device array instead of a caller's buffer.  Every device the
+// library runs on holds its own copy until the process ends.  In host code the
+// array's name is only a stand-in: the device address comes from
+// hipGetSymbolAddress, once per device, and only that address reaches a kernel.
+constexpr size_t kNoAllocScratchBytes = (size_t)4 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+static int scratch_address(void **out)
+{
+    static std::mutex mu;
+    static void *addr[64] = {nullptr};
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return fail(SPLAT_ENODEV, "no HIP device available");
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return fail(SPLAT_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        addr[dev] = p;
+    }
+    *out = addr[dev];
+    return SPLAT_OK;
+}
+
+size_t splat_trace_noalloc_max_bytes(void) { return kNoAllocScratchBytes; }
+
+int splat_trace_noalloc(const splat_bvh *bvh, const splat_spheres *sph, const splat_camera *cam,
+                        const splat_trace_opts *opts, float *out_rgba, uint32_t *out_hits, void *stream)
+{
+    TraceArgs a;
+    int rc;
+    if ((rc = trace_common(bvh, sph, cam, opts, a))) return rc;
+    if (!out_rgba) return fail(SPLAT_EINVAL, "out_rgba is NULL");
+    if (a.schedule == 2) {
+        const size_t need = trace_ws_bytes(a.cam.w, a.cam.h);
+        if (need > kNoAllocScratchBytes)
+            return fail(SPLAT_ENOSPC, "a %dx%d image needs %zu bytes of tile-order scratch; splat_trace_noalloc holds %zu",
+                        a.cam.w, a.cam.h, need, kNoAllocScratchBytes);
+    }
+    a.out = reinterpret_cast<float4 *>(out_rgba);
+    a.hits = out_hits;
+    if ((rc = check_device())) return rc;
+    void *ws = nullptr;
+    if ((rc = scratch_address(&ws))) return rc;
+    return hip_status(launch_trace(a, false, ws, static_cast<hipStream_t>(stream),
+                                   static_cast<hipEvent_t>(opts->event_begin), static_cast<hipEvent_t>(opts->event_end)),
+                      "trace launch");
+}
+
 int splat_trace_backward(const splat_bvh *bvh, const splat_spheres *sph, const splat_camera *cam,
                          const splat_trace_opts *opts, const float *out_rgba, const float *grad_rgba,
                          const splat_grads *grads, void *ws, size_t ws_bytes, void *stream)

@@ -350,6 +350,24 @@ def trace(bvh: BVH, sph: Spheres, cam, opts: TraceOptions | None = None, out: to
     return out, hits
 
 
+def trace_noalloc(bvh: BVH, sph: Spheres, cam, opts: TraceOptions | None = None, out: torch.Tensor | None = None,
+                  hits: torch.Tensor | None = None):
+    """splat_trace_noalloc: as `trace` with caller-given outputs, with no workspace (the library's static
+    device scratch holds the tile order).  Returns (out, hits)."""
+    opts = opts or TraceOptions()
+    H, W = int(cam.height), int(cam.width)
+    _require_cuda(out, "out", torch.float32)
+    if tuple(out.shape) != (H, W, 4):
+        raise ValueError("out must be [H, W, 4]")
+    if hits is not None and (tuple(hits.shape) != (H, W) or hits.dtype != torch.int32 or not hits.is_cuda):
+        raise ValueError("hits must be int32 [H, W] on the GPU")
+    lib = _lib.load()
+    c, o, s, b = _lib.camera_struct(cam), opts.struct(), sph.struct(), bvh.struct()
+    _lib.check(lib.splat_trace_noalloc(ctypes.byref(b), ctypes.byref(s), ctypes.byref(c), ctypes.byref(o),
+                                       _ptr(out), _ptr(hits), _stream()))
+    return out, hits
+
+
 def alloc_grads(capacity: int, device) -> dict:
     """Zeroed per-sphere gradients: rgb [cap, 3], alpha [cap], radius [cap], centre [cap, 3], as views of one
     buffer, so that `zero_grads` clears them with one fill."""

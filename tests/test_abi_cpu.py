@@ -128,6 +128,36 @@ def test_trace_option_validation():
     assert lib.splat_workspace_bytes(_lib.SPLAT_OP_BACKWARD, 0, w, h) == need
 
 
+def test_noalloc_trace_checks_on_the_host():
+    """splat_trace_noalloc: the options of splat_trace, and an image whose tile order needs more than its static
+    scratch is refused before anything touches a device."""
+    lib = _lib.load()
+    sph = _lib.splat_spheres()
+    sph.centre_radius, sph.rgba, sph.count, sph.capacity, sph.rgba_dtype = 4096, 4096, 4096, 64, _lib.SPLAT_F32
+    bvh = _lib.splat_bvh()
+    bvh.mem, bvh.capacity = 256 * 64, 64
+    out = ctypes.c_void_p(4096)
+    o = _lib.splat_trace_opts()
+    o.alpha_stop, o.t_max, o.schedule = 0.99, math.inf, 2
+    big = _Cam()
+    big.width = big.height = 8192
+    assert lib.splat_workspace_bytes(_lib.SPLAT_OP_TRACE, 0, 8192, 8192) > lib.splat_trace_noalloc_max_bytes()
+    cam = _lib.camera_struct(big)
+    code, msg = _err(lib.splat_trace_noalloc(ctypes.byref(bvh), ctypes.byref(sph), ctypes.byref(cam), ctypes.byref(o),
+                                             out, None, None))
+    assert code == _lib.SPLAT_ENOSPC and "scratch" in msg
+    o.kbuf = 3
+    code, _ = _err(lib.splat_trace_noalloc(ctypes.byref(bvh), ctypes.byref(sph), ctypes.byref(cam), ctypes.byref(o),
+                                           out, None, None))
+    assert code == _lib.SPLAT_EUNSUPPORTED
+    o.kbuf = 0
+    code, _ = _err(lib.splat_trace_noalloc(ctypes.byref(bvh), ctypes.byref(sph), ctypes.byref(cam), ctypes.byref(o),
+                                           None, None, None))
+    assert code == _lib.SPLAT_EINVAL
+    # the client frame fits the scratch
+    assert lib.splat_workspace_bytes(_lib.SPLAT_OP_TRACE, 0, 1920, 1080) <= lib.splat_trace_noalloc_max_bytes()
+
+
 def test_no_device_is_reported_not_crashed():
     """With valid arguments and no GPU in this container the call returns ENODEV."""
     import torch
