@@ -43,6 +43,8 @@ extern "C" {
 
 #define SPLAT_WALK_LANE 0      /* every lane walks the BVH on its own path */
 #define SPLAT_WALK_PACKET 1    /* the 64 lanes of a wavefront walk it together */
+#define SPLAT_WALK_FRUSTUM 2   /* a wavefront gathers its tile's candidate spheres once, breadth first
+                                  through the tile's frustum; each lane tests them against its ray */
 
 #define SPLAT_OP_UNPROJECT 0
 #define SPLAT_OP_BUILD 1
@@ -116,9 +118,12 @@ typedef struct splat_bvh {
  *               tiles, whose waves all fit on the GPU at once, run as 0);
  *               the result does not depend on it.  The batched launch
  *               ignores it (it has its own work queue)
- *   walk        SPLAT_WALK_LANE (each ray on its own path; default) or
- *               SPLAT_WALK_PACKET (a wavefront's rays as one packet); the
- *               result does not depend on it
+ *   walk        SPLAT_WALK_LANE (each ray on its own path; default),
+ *               SPLAT_WALK_PACKET (a wavefront's rays as one packet) or
+ *               SPLAT_WALK_FRUSTUM (the tile's candidates gathered once
+ *               through its frustum, then screened per ray; a tile with more
+ *               than 256 candidates, or a level of more than 128 nodes, takes
+ *               the per-lane walk); the result does not depend on it
  *   event_begin, event_end
  *               hipEvent_t or NULL: recorded on the stream immediately
  *               before and after the trace kernel itself (after the tile

@@ -101,7 +101,7 @@ int resolve_opts(const splat_trace_opts *o, splat_trace_opts *out)
         return fail(SPLAT_EUNSUPPORTED, "unknown alpha mode %d", out->mode);
     if (out->schedule != 0 && out->schedule != 1 && out->schedule != 2)
         return fail(SPLAT_EUNSUPPORTED, "unknown schedule %d", out->schedule);
-    if (out->walk != SPLAT_WALK_LANE && out->walk != SPLAT_WALK_PACKET)
+    if (out->walk != SPLAT_WALK_LANE && out->walk != SPLAT_WALK_PACKET && out->walk != SPLAT_WALK_FRUSTUM)
         return fail(SPLAT_EUNSUPPORTED, "unknown walk %d", out->walk);
     if (std::isnan(out->alpha_stop)) return fail(SPLAT_EINVAL, "alpha_stop is NaN");
     if (!(out->t_max > 0)) return fail(SPLAT_EINVAL, "t_max must be positive");

@@ -96,12 +96,30 @@ constexpr int kStack = 128;  // wave traversal stack (entries)
 constexpr int kQueue = 8;    // leaf candidates queued per lane (at least the 4 slots of one node)
 constexpr uint32_t kLaneStack = 16;  // per-lane walk: stack entries per lane (a power of 2)
 
+constexpr uint32_t kFront = 128;  // frustum walk: nodes of one level of the breadth-first walk
+constexpr uint32_t kTileCand = 256;  // frustum walk: candidate spheres of one tile
+
+// Frustum walk: the two levels of the breadth-first walk, and per candidate
+// sphere of the tile its screen disc (centre X, Y and squared radius in the
+// tangent units of the pixel grid), its depth range [tmin, tmax] along any
+// ray of the tile, and its slot, (wide node index << 2) | slot.
+struct FrustumLds {
+    uint32_t front[2][kFront];
+    float4 disc[kTileCand];   // X, Y, rho^2, tmin
+    float2 far_ref[kTileCand];  // tmax, slot (bits)
+};
+
 // LDS of one wave: the leaf candidates awaiting the exact test (a column per
-// lane) and the traversal stack.
+// lane) and the traversal stacks.  The per-lane stacks are only used by a
+// frustum-walk tile that fell back to the per-lane walk, when its candidate
+// lists are no longer needed, so the two share memory.
 struct WaveLds {
-    uint32_t cand[kQueue][kWave];        // (wide node index << 2) | slot
-    uint32_t lstack[kLaneStack][kWave];  // per-lane walk: a stack per lane
-    uint32_t stack[kStack];              // packet walk: one stack per wave
+    uint32_t cand[kQueue][kWave];          // (wide node index << 2) | slot
+    union {
+        uint32_t lstack[kLaneStack][kWave];  // per-lane walk: a stack per lane
+        FrustumLds fr;                       // frustum walk
+    };
+    uint32_t stack[kStack];                // packet walk: one stack per wave
 };
 
 // A lane's hits of one pass, sorted by key, in registers (every index is a
@@ -116,10 +134,14 @@ struct HitBuf {
 
 // ---------------------------------------------------------------- one tile
 
-template <int K, bool BWD, bool LANE>
+template <int K, bool BWD, int WALK>
 __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ nodes, const BvhHeader *__restrict__ hdr,
                            int tile_x, int tile_y, WaveLds &L)
 {
+    // the frustum walk falls back to the per-lane walk for a tile whose
+    // candidate lists overflow
+    constexpr bool FRUSTUM = WALK == SPLAT_WALK_FRUSTUM;
+    constexpr bool LANE = WALK == SPLAT_WALK_LANE || FRUSTUM;
     const int lane = threadIdx.x & (kWave - 1);
     const int px = tile_x * a.tile_w + (lane % a.tile_w);
     const int py = tile_y * a.tile_h + (lane / a.tile_w);
@@ -136,7 +158,7 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
     Ray ray;
     {
         double d[3];
-        pixel_ray(a.cam, inside ? px : 0, inside ? py : 0, d);
+        pixel_ray(a.cam, max(min(px, a.cam.w - 1), 0), max(min(py, a.cam.h - 1), 0), d);
         for (int k = 0; k < 3; ++k) {
             ray.d[k] = d[k];
             float f = (float)d[k];
@@ -174,7 +196,7 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
     // test; a 1/d beyond 2^40 could overflow the slab products, so such a
     // wave keeps the general test
     uint32_t sign_pattern = kMixedSigns;
-    if (LANE && K <= 8) {
+    if (WALK == SPLAT_WALK_LANE && K <= 8) {
         const bool part = inside && n_spheres > 0;
         uint32_t neg = 0, pos = 0;
         bool tame = true;
@@ -202,6 +224,132 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
     int phase = 0;
     double G64 = 0.0, P64 = 0.0, T64 = 1.0;
     if (BWD && inside) g = a.grad[(size_t)py * a.cam.w + px];
+
+    // ---- frustum walk, once per tile: the spheres that the tile's frustum
+    // may meet.  The four side planes pass through the eye and two adjacent
+    // corner rays of the tile; every pixel ray of the tile is a convex
+    // combination of the corner rays, so a box or sphere wholly outside one
+    // plane (by more than the float margin) meets none of them.  Levels of
+    // the 4-wide hierarchy are walked breadth first, 16 nodes per round (a
+    // lane per slot).  Each sphere that passes is entered in the tile's
+    // candidate list with its screen disc: a ray with screen coordinates
+    // (sx, sy) that hits the sphere satisfies |(sx, sy) - (X, Y)| <= rho with
+    // (X, Y) = (x, y) / z and rho = r sqrt(1 + X^2 + Y^2) / (z - r), where
+    // (x, y, z) is the centre in the camera basis (right, up, forward)
+    // relative to the eye, as long as z - r > 0.  If a level or the list
+    // overflows, the tile falls back to the per-lane walk.
+    uint32_t n_cand = 0;  // wave-uniform
+    bool fb = !FRUSTUM;   // wave-uniform: the tile uses the per-lane walk
+    float sxl = 0.0f, syl = 0.0f;
+    if constexpr (FRUSTUM) {
+        {
+            const double aspect = (double)a.cam.w / (double)a.cam.h;
+            const int cx = max(min(px, a.cam.w - 1), 0), cy = max(min(py, a.cam.h - 1), 0);
+            sxl = (float)(((2.0 * cx + 1.0) / (double)a.cam.w - 1.0) * a.cam.tan_half * aspect);
+            syl = (float)((1.0 - (2.0 * cy + 1.0) / (double)a.cam.h) * a.cam.tan_half);
+        }
+        const int corner[4] = {0, a.tile_w - 1, kWave - 1, kWave - a.tile_w};  // clockwise on the screen
+        double cd[4][3];
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) cd[c][k] = __shfl(ray.d[k], corner[c], kWave);
+        const double cen[3] = {cd[0][0] + cd[1][0] + cd[2][0] + cd[3][0], cd[0][1] + cd[1][1] + cd[2][1] + cd[3][1],
+                               cd[0][2] + cd[1][2] + cd[2][2] + cd[3][2]};
+        // plane i: pp[i] . x + pc[i] >= -slack, split into the positive and
+        // negative parts of the normal for the box test (the corner of the box
+        // farthest along the normal)
+        float pp[4][3], pn[4][3], pc[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const double *u = cd[i], *v = cd[(i + 1) & 3];
+            double n0 = u[1] * v[2] - u[2] * v[1], n1 = u[2] * v[0] - u[0] * v[2], n2 = u[0] * v[1] - u[1] * v[0];
+            const double len = sqrt(n0 * n0 + n1 * n1 + n2 * n2);
+            const double sg = (n0 * cen[0] + n1 * cen[1] + n2 * cen[2]) < 0.0 ? -1.0 : 1.0;
+            // two equal corners (a one-row tile) give no plane: it is left out
+            const double inv = len > 1e-300 ? sg / len : 0.0;
+            const float f0 = (float)(n0 * inv), f1 = (float)(n1 * inv), f2 = (float)(n2 * inv);
+            pp[i][0] = fmaxf(f0, 0.0f); pp[i][1] = fmaxf(f1, 0.0f); pp[i][2] = fmaxf(f2, 0.0f);
+            pn[i][0] = fminf(f0, 0.0f); pn[i][1] = fminf(f1, 0.0f); pn[i][2] = fminf(f2, 0.0f);
+            pc[i] = (float)(-((double)f0 * eye.o[0] + (double)f1 * eye.o[1] + (double)f2 * eye.o[2]));
+        }
+        // the margin bounds the float rounding of the plane tests
+        const float slack = 4.0f * eye.E;
+        const float bR[3] = {(float)a.cam.right[0], (float)a.cam.right[1], (float)a.cam.right[2]};
+        const float bU[3] = {(float)a.cam.up[0], (float)a.cam.up[1], (float)a.cam.up[2]};
+        const float bF[3] = {(float)a.cam.fwd[0], (float)a.cam.fwd[1], (float)a.cam.fwd[2]};
+        const bool any = __ballot(active) != 0;
+        uint32_t cur = 0, n_front = any ? 1u : 0u;
+        if (lane == 0) L.fr.front[0][0] = 0u;  // the root
+        fb = false;
+        // a hierarchy over 62-bit (code, position) keys is at most 64 binary
+        // levels deep; more levels only occur in a corrupt one
+        for (uint32_t level = 0; n_front > 0; ++level) {
+            __builtin_amdgcn_wave_barrier();
+            if (level > 40) {
+                fb = true;
+                break;
+            }
+            uint32_t n_next = 0;
+            for (uint32_t base = 0; base < n_front; base += kWave / 4) {
+                const uint32_t i = base + (uint32_t)lane / 4u, sl = (uint32_t)lane & 3u;
+                const bool valid = i < n_front;
+                const uint32_t node = valid ? min(L.fr.front[cur][i], n_nodes - 1) : 0u;
+                const float *f = nodes[node].f;
+                const uint32_t kinds = valid ? __float_as_uint(f[31]) : 0u;
+                const bool is_leaf = (kinds >> sl) & 1u, is_int = (kinds >> (4u + sl)) & 1u;
+                const float *q = f + 6 * sl;
+                const float q0 = q[0], q1 = q[1], q2 = q[2], q3 = q[3], q4 = q[4], q5 = q[5];
+                const uint32_t ref = __float_as_uint(f[24 + sl]);
+                bool pass = is_leaf || is_int;
+#pragma unroll
+                for (int pl = 0; pl < 4; ++pl) {
+                    // box: its corner farthest along the normal; sphere: its centre, moved r along it
+                    const float bx = fmaf(pp[pl][0], q3, fmaf(pn[pl][0], q0, pc[pl]));
+                    const float vb = fmaf(pp[pl][2], q5, fmaf(pn[pl][2], q2, fmaf(pp[pl][1], q4, fmaf(pn[pl][1], q1, bx))));
+                    const float vs = fmaf(pp[pl][0] + pn[pl][0], q0, fmaf(pp[pl][1] + pn[pl][1], q1,
+                                     fmaf(pp[pl][2] + pn[pl][2], q2, pc[pl]))) + q3;
+                    pass = pass && (is_leaf ? vs : vb) >= -slack;
+                }
+                const uint64_t mi = __ballot(pass && is_int), ml = __ballot(pass && is_leaf);
+                const uint32_t below_i = (uint32_t)__popcll(mi & ((1ull << lane) - 1ull));
+                const uint32_t below_l = (uint32_t)__popcll(ml & ((1ull << lane) - 1ull));
+                if (pass && is_int && n_next + below_i < kFront) L.fr.front[cur ^ 1u][n_next + below_i] = ref;
+                if (pass && is_leaf && n_cand + below_l < kTileCand) {
+                    // the candidate's screen disc and depth range, in float with
+                    // outward slack (relative 2^-12 on rho, 2^-18 absolute in tangent
+                    // units, 2^-20 relative on depths plus the margin)
+                    const float ox = q0 - eye.of[0], oy = q1 - eye.of[1], oz = q2 - eye.of[2];
+                    const float x = ox * bR[0] + oy * bR[1] + oz * bR[2];
+                    const float y = ox * bU[0] + oy * bU[1] + oz * bU[2];
+                    const float z = ox * bF[0] + oy * bF[1] + oz * bF[2];
+                    const float dist = sqrtf(ox * ox + oy * oy + oz * oz);
+                    const float zr = z - q3;
+                    float X = 0.0f, Y = 0.0f, rho2 = INFINITY;
+                    if (zr > 0x1p-10f * dist) {
+                        X = x / z;
+                        Y = y / z;
+                        const float rho = q3 * sqrtf(1.0f + X * X + Y * Y) / zr;
+                        const float rs = rho * (1.0f + 0x1p-12f) + 0x1p-18f * (1.0f + fabsf(X) + fabsf(Y));
+                        rho2 = rs * rs;
+                    }
+                    const float tmin = (dist - q3) * (1.0f - 0x1p-20f) - slack;
+                    const float tmax = dist * (1.0f + 0x1p-20f) + slack;
+                    L.fr.disc[n_cand + below_l] = make_float4(X, Y, rho2, tmin);
+                    L.fr.far_ref[n_cand + below_l] = make_float2(tmax, __uint_as_float((node << 2) | sl));
+                }
+                n_next += (uint32_t)__popcll(mi);
+                n_cand += (uint32_t)__popcll(ml);
+            }
+            if (n_next > kFront || n_cand > kTileCand) {
+                fb = true;
+                break;
+            }
+            cur ^= 1u;
+            n_front = n_next;
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
 
     HitBuf<K> B;
     while (__ballot(active)) {
@@ -477,7 +625,34 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
                 if (__ballot(nc > (uint32_t)kQueue - 4u)) flush();
             }
         };
-        if constexpr (LANE && K > 8) {
+        // Frustum walk: the tile's candidates against the lane's ray.  The
+        // screen test is the disc above; the depth range must reach below the
+        // prune key and past the last composited key, as in the per-lane
+        // prefilter.  Survivors are queued for the exact test, as in the walks.
+        auto cand_pass = [&]() {
+            uint32_t j = 0;
+            while (j < n_cand) {
+                do {
+                    const float4 dc = L.fr.disc[j];
+                    const float2 fr = L.fr.far_ref[j];
+                    const float du = sxl - dc.x, dv = syl - dc.y;
+                    const bool may = (fmaf(du, du, dv * dv) <= dc.z) & (dc.w <= pr_f) & (fr.x >= lo_f);
+                    // nc < kQueue here: the queue is flushed once a lane fills it
+                    L.cand[nc][lane] = __float_as_uint(fr.y);
+                    nc += may ? 1u : 0u;
+                    ++j;
+                } while (j < n_cand && !__ballot(nc >= (uint32_t)kQueue));
+                if (__ballot(nc >= (uint32_t)kQueue)) flush();
+            }
+        };
+        if constexpr (FRUSTUM) {
+            if (!fb) {
+                cand_pass();
+            } else {
+                lane_walk(SignTag<kMixedSigns>{});
+                redo = overflow;
+            }
+        } else if constexpr (LANE && K > 8) {
             // a large buffer leaves no registers for copies of the walk
             lane_walk(SignTag<kMixedSigns>{});
             redo = overflow;
@@ -684,7 +859,7 @@ __host__ inline uint32_t blocks_for(int tiles_x, int tiles_y, int schedule)
     return (uint32_t)(((s + 7) / 8) * 8 * 64);
 }
 
-template <int K, bool BWD, bool LANE>
+template <int K, bool BWD, int WALK>
 __global__ void __launch_bounds__(64) k_trace(TraceArgs a, int tiles_x, int tiles_y)
 {
     __shared__ WaveLds lds;
@@ -701,7 +876,7 @@ __global__ void __launch_bounds__(64) k_trace(TraceArgs a, int tiles_x, int tile
     const BvhLayout L(a.layout_cap);
     const BvhHeader *hdr = reinterpret_cast<const BvhHeader *>(mem);
     const WideNode *nodes = reinterpret_cast<const WideNode *>(mem + L.wide);
-    trace_tile<K, BWD, LANE>(a, nodes, hdr, tx, ty, lds);
+    trace_tile<K, BWD, WALK>(a, nodes, hdr, tx, ty, lds);
 }
 
 // Persistent batched trace: waves pull tiles from one atomic counter until
@@ -709,7 +884,7 @@ __global__ void __launch_bounds__(64) k_trace(TraceArgs a, int tiles_x, int tile
 // current one, so the atomic's round trip overlaps the tile's first node
 // loads; every claimed tile below the total is traced by the wave that
 // claimed it, and a wave exits at its first claim at or past the total.
-template <int K, bool LANE>
+template <int K, int WALK>
 __global__ void __launch_bounds__(64)
 k_trace_batched(const splat_batch_job *__restrict__ jobs, const uint32_t *__restrict__ tile_offsets, int n_jobs,
                 uint32_t total_tiles, float alpha_stop, int mode, double t_max, int tile_w, int tile_h,
@@ -752,7 +927,7 @@ k_trace_batched(const splat_batch_job *__restrict__ jobs, const uint32_t *__rest
         a.tile_w = tile_w;
         a.tile_h = tile_h;
         a.schedule = 0;
-        a.walk = LANE ? SPLAT_WALK_LANE : SPLAT_WALK_PACKET;
+        a.walk = WALK;
         a.order = nullptr;
         a.out = reinterpret_cast<float4 *>(j.out_rgba);
         a.hits = j.out_hits;
@@ -762,7 +937,7 @@ k_trace_batched(const splat_batch_job *__restrict__ jobs, const uint32_t *__rest
         const int64_t t64 = (int64_t)item - (int64_t)tile_offsets[lo];
         const int t = t64 < 0 ? 0x7fffffff : (int)min(t64, (int64_t)0x7fffffff);
         const char *mem = static_cast<const char *>(j.bvh_mem);
-        trace_tile<K, false, LANE>(a, reinterpret_cast<const WideNode *>(mem + L.wide), reinterpret_cast<const BvhHeader *>(mem),
+        trace_tile<K, false, WALK>(a, reinterpret_cast<const WideNode *>(mem + L.wide), reinterpret_cast<const BvhHeader *>(mem),
                              t % tiles_x, t / tiles_x, lds);
         item = ufirst(claim);
     }
@@ -773,16 +948,16 @@ __global__ void k_zero_counter(uint32_t *c)
     if (threadIdx.x == 0) *c = 0u;
 }
 
-template <bool BWD, bool LANE>
+template <bool BWD, int WALK>
 static hipError_t launch_k(const TraceArgs &a, int K, dim3 grid, int tiles_x, int tiles_y, hipStream_t s)
 {
     switch (K) {
-    case 1: hipLaunchKernelGGL((k_trace<1, BWD, LANE>), grid, dim3(64), 0, s, a, tiles_x, tiles_y); break;
-    case 2: hipLaunchKernelGGL((k_trace<2, BWD, LANE>), grid, dim3(64), 0, s, a, tiles_x, tiles_y); break;
-    case 4: hipLaunchKernelGGL((k_trace<4, BWD, LANE>), grid, dim3(64), 0, s, a, tiles_x, tiles_y); break;
-    case 6: hipLaunchKernelGGL((k_trace<6, BWD, LANE>), grid, dim3(64), 0, s, a, tiles_x, tiles_y); break;
-    case 8: hipLaunchKernelGGL((k_trace<8, BWD, LANE>), grid, dim3(64), 0, s, a, tiles_x, tiles_y); break;
-    case 16: hipLaunchKernelGGL((k_trace<16, BWD, LANE>), grid, dim3(64), 0, s, a, tiles_x, tiles_y); break;
+    case 1: hipLaunchKernelGGL((k_trace<1, BWD, WALK>), grid, dim3(64), 0, s, a, tiles_x, tiles_y); break;
+    case 2: hipLaunchKernelGGL((k_trace<2, BWD, WALK>), grid, dim3(64), 0, s, a, tiles_x, tiles_y); break;
+    case 4: hipLaunchKernelGGL((k_trace<4, BWD, WALK>), grid, dim3(64), 0, s, a, tiles_x, tiles_y); break;
+    case 6: hipLaunchKernelGGL((k_trace<6, BWD, WALK>), grid, dim3(64), 0, s, a, tiles_x, tiles_y); break;
+    case 8: hipLaunchKernelGGL((k_trace<8, BWD, WALK>), grid, dim3(64), 0, s, a, tiles_x, tiles_y); break;
+    case 16: hipLaunchKernelGGL((k_trace<16, BWD, WALK>), grid, dim3(64), 0, s, a, tiles_x, tiles_y); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -810,11 +985,14 @@ hipError_t launch_trace(const TraceArgs &args, bool backward, void *ws, hipStrea
     }
     hipError_t e;
     if (a.walk == SPLAT_WALK_PACKET)
-        e = backward ? launch_k<true, false>(a, a.kbuf, grid, tiles_x, tiles_y, s)
-                     : launch_k<false, false>(a, a.kbuf, grid, tiles_x, tiles_y, s);
+        e = backward ? launch_k<true, SPLAT_WALK_PACKET>(a, a.kbuf, grid, tiles_x, tiles_y, s)
+                     : launch_k<false, SPLAT_WALK_PACKET>(a, a.kbuf, grid, tiles_x, tiles_y, s);
+    else if (a.walk == SPLAT_WALK_FRUSTUM)
+        e = backward ? launch_k<true, SPLAT_WALK_FRUSTUM>(a, a.kbuf, grid, tiles_x, tiles_y, s)
+                     : launch_k<false, SPLAT_WALK_FRUSTUM>(a, a.kbuf, grid, tiles_x, tiles_y, s);
     else
-        e = backward ? launch_k<true, true>(a, a.kbuf, grid, tiles_x, tiles_y, s)
-                     : launch_k<false, true>(a, a.kbuf, grid, tiles_x, tiles_y, s);
+        e = backward ? launch_k<true, SPLAT_WALK_LANE>(a, a.kbuf, grid, tiles_x, tiles_y, s)
+                     : launch_k<false, SPLAT_WALK_LANE>(a, a.kbuf, grid, tiles_x, tiles_y, s);
     if (e == hipSuccess && ev_end) e = hipEventRecord(ev_end, s);
     return e;
 }
@@ -826,14 +1004,16 @@ hipError_t launch_trace_batched(const splat_batch_job *jobs, const uint32_t *til
     uint32_t *counter = static_cast<uint32_t *>(ws);
     hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, s, counter);
     const dim3 grid(waves), block(64);
-    const bool lane = o.walk != SPLAT_WALK_PACKET;
 #define SPLAT_BATCHED(KK)                                                                                        \
-    if (lane)                                                                                                    \
-        hipLaunchKernelGGL((k_trace_batched<KK, true>), grid, block, 0, s, jobs, tile_offsets, n_jobs,            \
-                           total_tiles, o.alpha_stop, o.mode, o.t_max, o.tile_w, o.tile_h, counter);              \
+    if (o.walk == SPLAT_WALK_PACKET)                                                                             \
+        hipLaunchKernelGGL((k_trace_batched<KK, SPLAT_WALK_PACKET>), grid, block, 0, s, jobs, tile_offsets,      \
+                           n_jobs, total_tiles, o.alpha_stop, o.mode, o.t_max, o.tile_w, o.tile_h, counter);      \
+    else if (o.walk == SPLAT_WALK_FRUSTUM)                                                                       \
+        hipLaunchKernelGGL((k_trace_batched<KK, SPLAT_WALK_FRUSTUM>), grid, block, 0, s, jobs, tile_offsets,     \
+                           n_jobs, total_tiles, o.alpha_stop, o.mode, o.t_max, o.tile_w, o.tile_h, counter);      \
     else                                                                                                         \
-        hipLaunchKernelGGL((k_trace_batched<KK, false>), grid, block, 0, s, jobs, tile_offsets, n_jobs,           \
-                           total_tiles, o.alpha_stop, o.mode, o.t_max, o.tile_w, o.tile_h, counter);
+        hipLaunchKernelGGL((k_trace_batched<KK, SPLAT_WALK_LANE>), grid, block, 0, s, jobs, tile_offsets,        \
+                           n_jobs, total_tiles, o.alpha_stop, o.mode, o.t_max, o.tile_w, o.tile_h, counter);
     switch (o.kbuf) {
     case 1: SPLAT_BATCHED(1) break;
     case 2: SPLAT_BATCHED(2) break;

@@ -107,7 +107,7 @@ def test_trace_option_validation():
     for kw, code in [({"kbuf": 3}, _lib.SPLAT_EUNSUPPORTED), ({"tile_w": 8, "tile_h": 4}, _lib.SPLAT_EUNSUPPORTED),
                      ({"mode": 5}, _lib.SPLAT_EUNSUPPORTED), ({"alpha_stop": math.nan}, _lib.SPLAT_EINVAL),
                      ({"t_max": 0.0}, _lib.SPLAT_EINVAL), ({"schedule": 3}, _lib.SPLAT_EUNSUPPORTED),
-                     ({"walk": 2}, _lib.SPLAT_EUNSUPPORTED), ({"schedule": 2}, _lib.SPLAT_ENOSPC)]:
+                     ({"walk": 3}, _lib.SPLAT_EUNSUPPORTED), ({"schedule": 2}, _lib.SPLAT_ENOSPC)]:
         o = _lib.splat_trace_opts()
         o.alpha_stop, o.t_max = 0.99, math.inf
         for k, v in kw.items():

@@ -71,7 +71,7 @@ def test_backward_with_restarts(sp):
     ref = oracle.grad_table(oracle.sphere_table(cr, col), cam, g, alpha_stop=0.99, mode=1)
     sph = sp.spheres_from_tensors(up(cr), up(col))
     bvh = sp.build_bvh(sph)
-    for k, walk in ((1, 0), (2, 1), (6, 0), (16, 1)):
+    for k, walk in ((1, 0), (2, 1), (6, 0), (16, 1), (4, 2), (16, 2)):
         opts = sp.TraceOptions(mode=1, kbuf=k, walk=walk)
         out, hits = sp.trace(bvh, sph, cam, opts)
         assert int(hits.max()) > 8  # several passes at k = 1 and 2

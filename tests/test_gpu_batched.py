@@ -51,7 +51,7 @@ def assert_same(a, b):
 
 
 @pytest.mark.parametrize("kbuf,tile,waves,walk", [(6, (8, 8), 0, 0), (8, (8, 8), 0, 1), (4, (16, 4), 97, 0),
-                                                  (1, (32, 2), 3, 1)])
+                                                  (1, (32, 2), 3, 1), (6, (8, 8), 0, 2), (2, (16, 4), 97, 2)])
 def test_batched_equals_sequential(sp, small_batch, kbuf, tile, waves, walk):
     r = make_renderer(sp, small_batch, half=True, opts=sp.TraceOptions(kbuf=kbuf, tile=tile, walk=walk), waves=waves)
     assert r.n_jobs >= 7

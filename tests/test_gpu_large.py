@@ -43,7 +43,7 @@ def test_large_unprojection(sp, large):
     assert np.array_equal(s.rgba[:n].cpu().numpy().view(np.uint16), col.view(np.uint16))
 
 
-@pytest.mark.parametrize("frame,walk", [(0, 0), (14, 0), (29, 0), (0, 1)])
+@pytest.mark.parametrize("frame,walk", [(0, 0), (14, 0), (29, 0), (0, 1), (0, 2), (29, 2)])
 def test_large_orbit_sampled(sp, large, frame, walk):
     rgba, depth, src, cr, col, _ = large
     dst = synth.rotated_camera(src, 15.0 + frame, 0.0)

@@ -199,7 +199,7 @@ def test_refit_matches_full_build(sp):
 
 # ---------------------------------------------------------------- trace
 
-@pytest.mark.parametrize("walk", [0, 1])
+@pytest.mark.parametrize("walk", [0, 1, 2])
 @pytest.mark.parametrize("seed", [0, 1, 2])
 @pytest.mark.parametrize("mode,stop", [(0, 0.99), (0, NEVER), (0, 0.0), (1, 0.99), (1, NEVER)])
 def test_trace_random_scenes(sp, seed, mode, stop, walk):
@@ -214,7 +214,7 @@ def test_trace_random_scenes(sp, seed, mode, stop, walk):
     assert st["hits_checked"] > (100 if stop == 0.0 else 200)
 
 
-@pytest.mark.parametrize("walk", [0, 1])
+@pytest.mark.parametrize("walk", [0, 1, 2])
 @pytest.mark.parametrize("half", [False, True])
 def test_trace_adversarial_scene(sp, half, walk):
     cr, col = synth.adversarial_spheres(5)
@@ -242,10 +242,11 @@ def test_every_direction_sign_pattern(sp, yaw):
     assert abs(abs(f[2]) - 1.0) < 1e-12
     print(f"sign patterns yaw={yaw}", flush=True)
     out = {}
-    for walk in (0, 1):
+    for walk in (0, 1, 2):
         out[walk] = gpu_trace(sp, cr, col, cam, walk=walk)[:2]
-    assert np.array_equal(out[0][0].view(np.uint32), out[1][0].view(np.uint32))
-    assert np.array_equal(out[0][1], out[1][1])
+    for walk in (1, 2):
+        assert np.array_equal(out[0][0].view(np.uint32), out[walk][0].view(np.uint32)), walk
+        assert np.array_equal(out[0][1], out[walk][1]), walk
     st = compare(out[0][0], out[0][1], oracle.render(cr, col, cam))
     assert_parity(st, exempt_frac=None, context=f"sign patterns yaw={yaw}")
     assert st["hits_checked"] > 3000
@@ -268,13 +269,14 @@ def test_column_along_the_view_ray(sp, stop):
     col = np.concatenate([rng.uniform(0, 1, (n, 3)), np.full((n, 1), 0.05)], axis=1).astype(np.float32)
     orc = oracle.render(cr, col, cam, alpha_stop=stop)
     out = {}
-    for walk in (0, 1):
+    for walk in (0, 1, 2):
         print(f"column stop={stop} walk={walk}", flush=True)
         g, h, _, _ = gpu_trace(sp, cr, col, cam, alpha_stop=stop, walk=walk)
         assert_parity(compare(g, h, orc), exempt_frac=None, context=f"column walk={walk}")
         out[walk] = (g, h)
     assert int(out[0][1].max()) > (1000 if stop == NEVER else 50)
-    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+    for walk in (1, 2):
+        assert np.array_equal(out[0][0], out[walk][0]) and np.array_equal(out[0][1], out[walk][1]), walk
 
 
 def test_heaviest_first_order_matches_other_schedules(sp):
@@ -287,7 +289,7 @@ def test_heaviest_first_order_matches_other_schedules(sp):
     sph = sp.spheres_from_tensors(up(cr), up(col))
     bvh = sp.build_bvh(sph)
     ref = None
-    for walk in (0, 1):
+    for walk in (0, 1, 2):
         for sched in (2, 0, 1):
             img, hits = sp.trace(bvh, sph, cam, sp.TraceOptions(schedule=sched, walk=walk))
             if ref is None:
@@ -313,7 +315,7 @@ def test_result_independent_of_kbuf_and_tile(sp):
         ref = None
         for k in (1, 2, 4, 6, 8, 16):
             for tile in ((8, 8), (16, 4), (32, 2)):
-                for walk in (0, 1):
+                for walk in (0, 1, 2):
                     for sched in (0, 1, 2):
                         o = sp.TraceOptions(alpha_stop=stop, kbuf=k, tile=tile, walk=walk, schedule=sched)
                         img, hits = sp.trace(bvh, sph, cam, o)
@@ -335,7 +337,8 @@ def test_tiny_config_full_frame(sp):
     assert st["hits_checked"] > 100
 
 
-@pytest.mark.parametrize("scale,walk", [(0.5, 0), (1.0, 0), (2.0, 0), (1.0, 1), (2.0, 1)])
+@pytest.mark.parametrize("scale,walk", [(0.5, 0), (1.0, 0), (2.0, 0), (1.0, 1), (2.0, 1), (0.5, 2), (1.0, 2),
+                                        (2.0, 2)])
 def test_client_frame_sampled(sp, scale, walk):
     """1024^2 source -> 1920x1080 after 10 deg yaw + 3 deg pitch, half colours, full-size launch
     with the default schedule; the oracle checks one random pixel in every 8x8 tile (32,400) and
