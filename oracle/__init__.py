@@ -10,7 +10,9 @@ over pixels), brute force: every ray against every sphere, hits sorted by
 
 * ``unproject``  Sec. 4.1, Eq. 1 (p = o + d t_i), footprint radius, compaction
 * ``render``     Sec. 4.1 / Fig. 2: spheres traced from a new camera,
-                 composited front to back with an alpha stop
+                 composited front to back with an alpha stop; or spheroids
+                 (samples smeared along their source ray, Sec. 7)
+* ``unproject_spheroids``  those spheroids from a depth interval (Sec. 7)
 * ``grad``       analytic gradient of a per-pixel loss through ``render``
 * ``half_bits``  double -> binary16 with round-to-nearest-even
 * ``raymarch``   the server stage before the path (Sec. 4.1): volume ray
@@ -99,7 +101,12 @@ def _load():
                                      ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                      ctypes.c_double, ctypes.c_double, _P, ctypes.c_int64, _P]
         lib.orc_unproject_policy.argtypes = [ctypes.POINTER(_Cam), _P, _P, _P, ctypes.c_int32, ctypes.c_double,
-                                             ctypes.c_double, ctypes.c_double, _P, _P, _P, _P]
+                                             ctypes.c_double, ctypes.c_double, _P, _P, _P, _P, _P]
+        lib.orc_spheroid_test.argtypes = [_P, _P, _P, ctypes.c_double, _P, ctypes.c_double, ctypes.c_double, _P]
+        lib.orc_spheroid_test.restype = ctypes.c_int
+        lib.orc_render_axis.argtypes = [_P, _P, ctypes.c_int64, ctypes.POINTER(_Cam), ctypes.c_double,
+                                        ctypes.c_double, ctypes.c_int, _P, ctypes.c_int64, _P, _P, _P, _P, _P, _P]
+        lib.orc_render_axis.restype = ctypes.c_int
         lib.orc_unproject_policy.restype = ctypes.c_int64
         lib.orc_raymarch.restype = ctypes.c_int
         lib.orc_encode_position.argtypes = [_P, ctypes.c_double, _P, ctypes.c_double, ctypes.c_double]
@@ -149,7 +156,7 @@ def unproject(cam, rgba: np.ndarray, depth: np.ndarray, radius_scale: float, hal
     return cr[:n].copy(), col[:n].copy(), idx[:n].copy()
 
 
-RADIUS_FOOTPRINT, RADIUS_OPACITY, RADIUS_INTERVAL = 0, 1, 2
+RADIUS_FOOTPRINT, RADIUS_OPACITY, RADIUS_INTERVAL, RADIUS_SPHEROID = 0, 1, 2, 3
 
 
 def unproject_policy(cam, rgba: np.ndarray, depth: np.ndarray, mode: int, radius_scale: float = 1.0,
@@ -171,12 +178,37 @@ def unproject_policy(cam, rgba: np.ndarray, depth: np.ndarray, mode: int, radius
     idx = np.zeros(cap, dtype=np.uint32)
     c = _cam(cam)
     # the floor and kappa are float parameters of the GPU call: use their float values
+    assert mode != RADIUS_SPHEROID, "unproject_spheroids returns the axes too"
     n = _load().orc_unproject_policy(ctypes.byref(c), rgba.ctypes.data, depth.ctypes.data, _ptr(itv), int(mode),
                                      float(np.float32(radius_scale)), float(np.float32(opacity_floor)),
                                      float(np.float32(interval_scale)), cr.ctypes.data, _ptr(col32), _ptr(col16),
-                                     idx.ctypes.data)
+                                     idx.ctypes.data, None)
     col = col16.view(np.float16) if half else col32
     return cr[:n].copy(), col[:n].copy(), idx[:n].copy()
+
+
+def unproject_spheroids(cam, rgba: np.ndarray, depth: np.ndarray, interval: np.ndarray, radius_scale: float = 1.0,
+                        interval_scale: float = 1.0, half: bool = True):
+    """Samples smeared along their source ray over the depth interval (Sec. 7): prolate spheroids centred at the
+    interval's midpoint, radius s fp(t_c) across the ray, half-length max(r, kappa half-interval) along it.
+    Returns (centre_radius float32 [N][4], colour [N][4], src_index uint32 [N], axis float32 [N][4] = (u, h))."""
+    H, W = int(cam.height), int(cam.width)
+    rgba = np.ascontiguousarray(rgba, dtype=np.float32).reshape(H, W, 4)
+    depth = np.ascontiguousarray(depth, dtype=np.float32).reshape(H, W)
+    itv = np.ascontiguousarray(interval, dtype=np.float32).reshape(H, W, 2)
+    cap = H * W
+    cr = np.zeros((cap, 4), dtype=np.float32)
+    col32 = None if half else np.zeros((cap, 4), dtype=np.float32)
+    col16 = np.zeros((cap, 4), dtype=np.uint16) if half else None
+    idx = np.zeros(cap, dtype=np.uint32)
+    ax = np.zeros((cap, 4), dtype=np.float32)
+    c = _cam(cam)
+    n = _load().orc_unproject_policy(ctypes.byref(c), rgba.ctypes.data, depth.ctypes.data, itv.ctypes.data,
+                                     RADIUS_SPHEROID, float(np.float32(radius_scale)), 1.0,
+                                     float(np.float32(interval_scale)), cr.ctypes.data, _ptr(col32), _ptr(col16),
+                                     idx.ctypes.data, ax.ctypes.data)
+    col = col16.view(np.float16) if half else col32
+    return cr[:n].copy(), col[:n].copy(), idx[:n].copy(), ax[:n].copy()
 
 
 def sphere_table(centre_radius: np.ndarray, colour: np.ndarray) -> np.ndarray:
@@ -187,9 +219,12 @@ def sphere_table(centre_radius: np.ndarray, colour: np.ndarray) -> np.ndarray:
 
 
 def render_table(table: np.ndarray, cam, alpha_stop: float = 0.99, t_max: float = np.inf,
-                 mode: int = MODE_CONSTANT, pixels=None):
-    """Brute-force render from an [N][8] float64 sphere table (cx cy cz r kr kg kb a)."""
+                 mode: int = MODE_CONSTANT, pixels=None, axis=None):
+    """Brute-force render from an [N][8] float64 sphere table (cx cy cz r kr kg kb a); with `axis` ([N][4] u, h)
+    the samples are prolate spheroids (constant alpha only)."""
     table = np.ascontiguousarray(table, dtype=np.float64).reshape(-1, 8)
+    ax = None if axis is None else np.ascontiguousarray(np.asarray(axis).reshape(-1, 4).astype(np.float64))
+    assert ax is None or ax.shape[0] == table.shape[0]
     if pixels is None:
         pix = None
         npix = int(cam.width) * int(cam.height)
@@ -203,18 +238,25 @@ def render_table(table: np.ndarray, cam, alpha_stop: float = 0.99, t_max: float 
     flags = np.zeros(npix, dtype=np.int32)
     sig = np.zeros(npix, dtype=np.uint64)
     c = _cam(cam)
-    rc = _load().orc_render(table.ctypes.data, table.shape[0], ctypes.byref(c), float(alpha_stop), float(t_max),
-                            int(mode), _ptr(pix), npix, out.ctypes.data, n.ctypes.data, flags.ctypes.data,
-                            alt.ctypes.data, nalt.ctypes.data, sig.ctypes.data)
+    if ax is None:
+        rc = _load().orc_render(table.ctypes.data, table.shape[0], ctypes.byref(c), float(alpha_stop), float(t_max),
+                                int(mode), _ptr(pix), npix, out.ctypes.data, n.ctypes.data, flags.ctypes.data,
+                                alt.ctypes.data, nalt.ctypes.data, sig.ctypes.data)
+    else:
+        rc = _load().orc_render_axis(table.ctypes.data, ax.ctypes.data, table.shape[0], ctypes.byref(c),
+                                     float(alpha_stop), float(t_max), int(mode), _ptr(pix), npix, out.ctypes.data,
+                                     n.ctypes.data, flags.ctypes.data, alt.ctypes.data, nalt.ctypes.data,
+                                     sig.ctypes.data)
     if rc != 0:
         raise RuntimeError(f"orc_render failed ({rc})")
     return {"rgba": out, "n": n, "flags": flags, "alt_rgba": alt, "alt_n": nalt, "sig": sig}
 
 
 def render(centre_radius, colour, cam, alpha_stop: float = 0.99, t_max: float = np.inf,
-           mode: int = MODE_CONSTANT, pixels=None):
-    """Brute-force FP64 render of stored spheres (float32 centre/radius, float16/32 colour)."""
-    return render_table(sphere_table(centre_radius, colour), cam, alpha_stop, t_max, mode, pixels)
+           mode: int = MODE_CONSTANT, pixels=None, axis=None):
+    """Brute-force FP64 render of stored spheres (float32 centre/radius, float16/32 colour), or of spheroids
+    with the stored axes (float32 [N][4]: unit axis, half-length along it)."""
+    return render_table(sphere_table(centre_radius, colour), cam, alpha_stop, t_max, mode, pixels, axis)
 
 
 def grad_table(table: np.ndarray, cam, grad_rgba: np.ndarray, alpha_stop: float = 0.99,
@@ -241,6 +283,15 @@ def sphere_test(o, d, c, r: float, t_max: float = np.inf):
     hit = _load().orc_sphere_test(o.ctypes.data, d.ctypes.data, c.ctypes.data, float(r), float(t_max),
                                   out.ctypes.data)
     return bool(hit), out[0], out[1], out[2], out[3:6].copy(), out[6]
+
+
+def spheroid_test(o, d, c, r: float, u, h: float, t_max: float = np.inf):
+    """One ray against one prolate spheroid: (hit, t0, disc, t_mid, qq)."""
+    a = [np.ascontiguousarray(v, dtype=np.float64) for v in (o, d, c, u)]
+    out = np.zeros(4, dtype=np.float64)
+    hit = _load().orc_spheroid_test(a[0].ctypes.data, a[1].ctypes.data, a[2].ctypes.data, float(r), a[3].ctypes.data,
+                                    float(h), float(t_max), out.ctypes.data)
+    return bool(hit), out[0], out[1], out[2], out[3]
 
 
 def pixels_near(cam, centre, radius: float) -> np.ndarray:

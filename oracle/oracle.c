@@ -21,6 +21,10 @@
  *   orc_grad        gradient of a per-pixel loss through orc_render.
  *   orc_pixels_near lists the pixels whose ray passes near a point.
  *   orc_sphere_test one ray against one sphere (exposed for closed-form pins).
+ *   orc_spheroid_test  one ray against a prolate spheroid: a sample smeared
+ *                   along its source ray over its depth interval (Sec. 7).
+ *   orc_render_axis orc_render over spheroids (an axis and half-length per
+ *                   sample); orc_render is its sphere case.
  *   orc_half_bits   double -> IEEE binary16, round to nearest even.
  *   orc_raymarch    the server stage before the path (Sec. 4.1): a volume
  *                   ray marcher writing colour and a representative depth;
@@ -143,12 +147,17 @@ int64_t orc_unproject(const orc_camera *cam, const float *rgba, const float *dep
  *     marcher) replaces the single depth: the centre sits at its midpoint
  *     t_c = (t_lo + t_hi) / 2 on the ray and r = max(s fp(t_c),
  *     kappa (t_hi - t_lo) / 2), so the sphere covers the interval.  A pixel
- *     holds a sample iff the depth rule holds and 0 < t_lo <= t_hi, both finite.
+ *     holds a sample iff the depth rule holds and 0 < t_lo <= t_hi, both finite;
+ *   - mode 3, spheroid: the interval's sample smeared along the ray instead of
+ *     grown in every direction: centre at t_c on the ray, r = s fp(t_c) across
+ *     the ray, half-length h = max(r, kappa (t_hi - t_lo) / 2) along it, axis
+ *     u = the unit source ray d; axis[4n..4n+3] = (u, h), each rounded once to
+ *     float.  The validity rule is mode 2's.
  * Colour, alpha, order and compaction are those of orc_unproject.
  */
 int64_t orc_unproject_policy(const orc_camera *cam, const float *rgba, const float *depth, const float *interval,
                              int32_t mode, double radius_scale, double a_floor, double kappa, float *centre_radius,
-                             float *col_f32, uint16_t *col_f16, uint32_t *src_index)
+                             float *col_f32, uint16_t *col_f16, uint32_t *src_index, float *axis)
 {
     const int64_t W = cam->width, H = cam->height;
     int64_t n = 0;
@@ -159,7 +168,7 @@ int64_t orc_unproject_policy(const orc_camera *cam, const float *rgba, const flo
             const double A = rgba[4 * i + 3];
             if (!(isfinite(t) && t > 0.0 && A > 0.0)) continue;
             double half_len = 0.0;
-            if (mode == 2) {
+            if (mode == 2 || mode == 3) {
                 const double lo = interval[2 * i], hi = interval[2 * i + 1];
                 if (!(isfinite(lo) && isfinite(hi) && lo > 0.0 && hi >= lo)) continue;
                 t = 0.5 * (lo + hi);
@@ -173,6 +182,11 @@ int64_t orc_unproject_policy(const orc_camera *cam, const float *rgba, const flo
             if (mode == 1) r = r * sqrt(A > a_floor ? A : a_floor);
             if (mode == 2 && kappa * half_len > r) r = kappa * half_len;
             centre_radius[4 * n + 3] = (float)r;
+            if (mode == 3) {
+                const double h = kappa * half_len > r ? kappa * half_len : r;
+                for (int k = 0; k < 3; ++k) axis[4 * n + k] = (float)d[k];
+                axis[4 * n + 3] = (float)h;
+            }
             double col[4];
             for (int k = 0; k < 3; ++k) {
                 double kc = (double)rgba[4 * i + k] / A;
@@ -299,16 +313,68 @@ int orc_sphere_test(const double o[3], const double d[3], const double c[3], dou
     return disc >= 0.0 && t0 > 0.0 && t0 < t_max;
 }
 
-static void orc_collect(const double *sph, int64_t nsph, const double o[3], const double d[3], double t_max,
-                        orc_ray_hits *rh)
+/*
+ * Ray against a prolate spheroid (Sec. 7 suggests smearing a sample whose
+ * depth is uncertain over an interval along its ray; this is that shape):
+ * centre c, axis u, half-length h along u and radius r across it, the points
+ * x with |x - c|^2 / r^2 + ((x - c).u)^2 (1/h^2 - 1/r^2) <= 1.  The linear
+ * map S y = y / r + (y.u)(1/h - 1/r) u takes it to the unit ball, and the ray
+ * o + t d (d unit) to t D - L with D = S d, L = S (c - o).  The robust form of
+ * the sphere test then applies in those coordinates: t_m = L.D / D.D,
+ * v = L - t_m D, qq = v.v, disc = 1 - qq, t0 = t_m - sqrt(disc / D.D).
+ * out[0] = t0, out[1] = disc, out[2] = t_m, out[3] = qq.
+ * Returns 1 iff disc >= 0 and 0 < t0 < t_max.  With h = r this is the sphere.
+ */
+int orc_spheroid_test(const double o[3], const double d[3], const double c[3], double r, const double u[3], double h,
+                      double t_max, double out[4])
+{
+    const double oc[3] = {c[0] - o[0], c[1] - o[1], c[2] - o[2]};
+    const double w = 1.0 / h - 1.0 / r;
+    const double du = d[0] * u[0] + d[1] * u[1] + d[2] * u[2];
+    const double ou = oc[0] * u[0] + oc[1] * u[1] + oc[2] * u[2];
+    double D[3], L[3];
+    for (int k = 0; k < 3; ++k) {
+        D[k] = d[k] / r + du * w * u[k];
+        L[k] = oc[k] / r + ou * w * u[k];
+    }
+    const double DD = D[0] * D[0] + D[1] * D[1] + D[2] * D[2];
+    const double tm = (L[0] * D[0] + L[1] * D[1] + L[2] * D[2]) / DD;
+    const double v[3] = {L[0] - tm * D[0], L[1] - tm * D[1], L[2] - tm * D[2]};
+    const double qq = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+    const double disc = 1.0 - qq;
+    const double t0 = disc >= 0.0 ? tm - sqrt(disc / DD) : NAN;
+    out[0] = t0;
+    out[1] = disc;
+    out[2] = tm;
+    out[3] = qq;
+    return disc >= 0.0 && t0 > 0.0 && t0 < t_max;
+}
+
+/* Every sample against the ray: spheres (ax NULL), or spheroids with
+ * ax[4 j..4 j + 3] = (u, h) of sample j. */
+static void orc_collect(const double *sph, const double *ax, int64_t nsph, const double o[3], const double d[3],
+                        double t_max, orc_ray_hits *rh)
 {
     rh->nhits = 0;
     rh->ngraze = 0;
     for (int64_t j = 0; j < nsph; ++j) {
         double res[7];
         double r = SPH(j, 3);
-        int hit = orc_sphere_test(o, d, &SPH(j, 0), r, t_max, res);
-        if (fabs(res[2]) <= 1e-6 * r * r) {
+        int hit;
+        if (ax) {
+            /* disc is relative to the unit ball here: the same 1e-6 band */
+            double e[4];
+            hit = orc_spheroid_test(o, d, &SPH(j, 0), r, &ax[4 * j], ax[4 * j + 3], t_max, e);
+            res[0] = e[0];
+            res[1] = e[3];
+            res[2] = e[1] * r * r;
+            res[3] = res[4] = res[5] = 0.0;
+            res[6] = e[2];
+            r = ax[4 * j + 3] > r ? ax[4 * j + 3] : r;  /* the extent along the ray, for the grazing range */
+        } else {
+            hit = orc_sphere_test(o, d, &SPH(j, 0), r, t_max, res);
+        }
+        if (fabs(res[2]) <= 1e-6 * SPH(j, 3) * SPH(j, 3)) {
             if (rh->ngraze == rh->cap_graze && orc_rh_grow_graze(rh)) return;
             rh->graze_t[rh->ngraze] = res[6];
             rh->graze_r[rh->ngraze] = r;
@@ -385,11 +451,12 @@ static int orc_composite(const double *sph, const orc_hit *hits_in, int64_t nh, 
  * out_sig (nullable) receives a hash of the ordered composited sphere ids.
  * Returns 0, 1 on bad arguments, 2 when out of memory.
  */
-int orc_render(const double *sph, int64_t nsph, const orc_camera *cam, double alpha_stop, double t_max, int mode,
-               const int64_t *pix, int64_t npix, double *out_rgba, int32_t *out_n, int32_t *flags,
-               double *alt_rgba, int32_t *alt_n, uint64_t *out_sig)
+int orc_render_axis(const double *sph, const double *ax, int64_t nsph, const orc_camera *cam, double alpha_stop,
+                    double t_max, int mode, const int64_t *pix, int64_t npix, double *out_rgba, int32_t *out_n,
+                    int32_t *flags, double *alt_rgba, int32_t *alt_n, uint64_t *out_sig)
 {
     if (!sph && nsph > 0) return 1;
+    if (ax && mode != 0) return 1; /* spheroids: constant alpha only */
     if (!cam || !out_rgba || !out_n || !flags || !alt_rgba || !alt_n) return 1;
     const int64_t W = cam->width;
     if (!pix) npix = (int64_t)cam->width * cam->height;
@@ -406,7 +473,7 @@ int orc_render(const double *sph, int64_t nsph, const orc_camera *cam, double al
             int64_t id = pix ? pix[p] : p;
             double d[3];
             orc_ray(cam, id % W, id / W, d);
-            orc_collect(sph, nsph, cam->eye, d, t_max, &rh);
+            orc_collect(sph, ax, nsph, cam->eye, d, t_max, &rh);
             if (rh.oom) continue;
             double rgba[4], t_last;
             int64_t n;
@@ -453,6 +520,15 @@ int orc_render(const double *sph, int64_t nsph, const orc_camera *cam, double al
     return err;
 }
 
+/* orc_render_axis over spheres. */
+int orc_render(const double *sph, int64_t nsph, const orc_camera *cam, double alpha_stop, double t_max, int mode,
+               const int64_t *pix, int64_t npix, double *out_rgba, int32_t *out_n, int32_t *flags,
+               double *alt_rgba, int32_t *alt_n, uint64_t *out_sig)
+{
+    return orc_render_axis(sph, NULL, nsph, cam, alpha_stop, t_max, mode, pix, npix, out_rgba, out_n, flags,
+                           alt_rgba, alt_n, out_sig);
+}
+
 /*
  * Gradient of L = sum_p sum_ch g[p][ch] * I[p][ch] (a linearised loss: pass
  * g = dL/dI of the real loss) with respect to every sphere parameter.
@@ -491,7 +567,7 @@ int orc_grad(const double *sph, int64_t nsph, const orc_camera *cam, double alph
             const double *g = grad_rgba + 4 * p;
             double d[3];
             orc_ray(cam, p % W, p / W, d);
-            orc_collect(sph, nsph, cam->eye, d, t_max, &rh);
+            orc_collect(sph, NULL, nsph, cam->eye, d, t_max, &rh);
             if (rh.oom) continue;
             double rgba[4], t_last;
             int64_t n;

@@ -13,6 +13,7 @@ import test_oracle_codec_pins as K
 import test_oracle_grad_pins as G
 import test_oracle_march_pins as M
 import test_oracle_policy_pins as R
+import test_oracle_spheroid_pins as S
 import test_oracle_pins as P
 
 SRC = open(os.path.join(os.path.dirname(oracle.__file__), "oracle.c")).read()
@@ -81,6 +82,19 @@ MUTANTS = [
     ("accumulate no upper clamp", "if (q > (double)(grid - 1)) q = (double)(grid - 1);", ""),
     ("accumulate keeps one frame too long", "if ((int32_t)hist_age[i] + 1 > max_age) continue;",
      "if ((int32_t)hist_age[i] > max_age) continue;"),
+    ("spheroid direction scaled by h across", "D[k] = d[k] / r + du * w * u[k];", "D[k] = d[k] / h + du * w * u[k];"),
+    ("spheroid axis term reversed", "const double w = 1.0 / h - 1.0 / r;", "const double w = 1.0 / r - 1.0 / h;"),
+    ("spheroid exit instead of entry", "const double t0 = disc >= 0.0 ? tm - sqrt(disc / DD) : NAN;",
+     "const double t0 = disc >= 0.0 ? tm + sqrt(disc / DD) : NAN;"),
+    ("spheroid chord not scaled by D.D", "const double t0 = disc >= 0.0 ? tm - sqrt(disc / DD) : NAN;",
+     "const double t0 = disc >= 0.0 ? tm - sqrt(disc) : NAN;"),
+    ("spheroid half-length ignores kappa", "const double h = kappa * half_len > r ? kappa * half_len : r;",
+     "const double h = half_len > r ? half_len : r;"),
+    ("spheroid half-length may fall below r", "const double h = kappa * half_len > r ? kappa * half_len : r;",
+     "const double h = kappa * half_len;"),
+    ("spheroid axis along the view, not the pixel ray", "for (int k = 0; k < 3; ++k) axis[4 * n + k] = (float)d[k];",
+     "for (int k = 0; k < 3; ++k) axis[4 * n + k] = (float)(-cam->forward[k]);"),
+    ("spheroid grazing band unscaled", "res[2] = e[1] * r * r;", "res[2] = e[1];"),
 ]
 
 # pins run against each mutant (parametrised pins with their cases)
@@ -120,6 +134,16 @@ PINS = [
                                                                   (0.0, 1.0), (-1.0, 1.0), (np.nan, 1.0)]],
     R.test_interval_centre_on_the_pixel_ray,
     R.test_footprint_policy_is_the_plain_unprojection_and_full_opacity_too,
+    lambda: [S.test_spheroid_closed_form(*c) for c in [((0, 0, 5), (0, 0, 1), 3.0, 1.0),
+                                                         ((0, 0, 5), (1, 0, 0), 4.5, 1.0),
+                                                         ((2, 0, 5), (1, 0, 0), 5.0, 0.0)]],
+    S.test_spheroid_misses_and_eye_inside,
+    S.test_equal_half_length_is_the_sphere,
+    S.test_spheroid_matches_quadratic_roots,
+    S.test_unproject_spheroids_on_the_axis_hand_computed,
+    S.test_unproject_spheroids_lie_along_the_pixel_rays,
+    S.test_view_along_the_source_ray_meets_the_tip,
+    S.test_spheroid_tangent_pixel_is_flagged_grazing,
     T.test_hand_placed_cells,
     T.test_age_limits,
     lambda: [T.test_random_cells_by_construction(sd) for sd in (0, 1, 2)],
