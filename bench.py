@@ -32,7 +32,7 @@ def parse():
     p.add_argument("--scale", type=float, default=1.0)
     p.add_argument("--kbuf", type=int, default=6)
     p.add_argument("--tile", type=str, default="8x8")
-    p.add_argument("--walk", type=int, default=0, help="0 per-lane BVH walk, 1 packet walk")
+    p.add_argument("--walk", type=int, default=2, help="0 per-lane BVH walk, 1 packet walk, 2 frustum walk")
     p.add_argument("--schedule", type=int, default=2, help="tile order: 0 super-tiles per XCD, 1 bands, 2 heaviest first")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--no-bwd", action="store_true", help="skip the fwd+bwd measurement")
@@ -67,7 +67,7 @@ def profile_record(name: str, args, sources=TRACE_SOURCES, key="trace_source_sha
     """key = value lines of a committed profile summary, or None when the file is missing, the kernel
     sources differ from the ones profiled or the launch configuration is not the profiled one."""
     path = os.path.join(ROOT, "profiles", name)
-    if not os.path.exists(path) or (args.kbuf, args.tile, args.scale, args.walk, args.schedule) != (6, "8x8", 1.0, 0, 2):
+    if not os.path.exists(path) or (args.kbuf, args.tile, args.scale, args.walk, args.schedule) != (6, "8x8", 1.0, 2, 2):
         return None
     rec = {}
     for line in open(path):
@@ -245,7 +245,7 @@ def main():
                                f"source ({n} spheres, radius scale {args.scale}) -> {dst.width}x{dst.height} target, "
                                f"yaw {work.yaw} pitch {work.pitch}",
                    "rays": P, "spheres": n, "kbuf": args.kbuf, "tile": args.tile,
-                   "walk": "per-lane" if args.walk == 0 else "packet",
+                   "walk": ["per-lane", "packet", "frustum"][args.walk],
                    "schedule": ["xcd super-tiles", "xcd bands", "heaviest first"][args.schedule], "alpha_stop": 0.99},
         "stages_ms": {"unproject": round(float(np.median(stage[:, 0])), 4),
                       "build": round(float(np.median(stage[:, 1])), 4),
@@ -259,7 +259,7 @@ def main():
         "mean_hits_per_ray": round(float(hit_stats.mean()), 3),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": measured_traffic(args, wl),
-                     "kernel": f"k_trace<{args.kbuf}, false, {'true' if args.walk == 0 else 'false'}>",
+                     "kernel": f"k_trace<{args.kbuf}, false, {args.walk}>",
                      "algorithmic_bytes": tb, "avg_launch_ms": round(trace_ms, 4),
                      "l2_hit_rate": l2_hit_rate(args, wl),
                      "note": "avg_launch_ms is the trace kernel alone, between events the library records around "

@@ -118,12 +118,13 @@ typedef struct splat_bvh {
  *               tiles, whose waves all fit on the GPU at once, run as 0);
  *               the result does not depend on it.  The batched launch
  *               ignores it (it has its own work queue)
- *   walk        SPLAT_WALK_LANE (each ray on its own path; default),
+ *   walk        SPLAT_WALK_LANE (each ray on its own path; the zero value),
  *               SPLAT_WALK_PACKET (a wavefront's rays as one packet) or
  *               SPLAT_WALK_FRUSTUM (the tile's candidates gathered once
  *               through its frustum, then screened per ray; a tile with more
  *               than 256 candidates, or a level of more than 128 nodes, takes
- *               the per-lane walk); the result does not depend on it
+ *               the per-lane walk; the fastest on the client and large
+ *               frames); the result does not depend on it
  *   event_begin, event_end
  *               hipEvent_t or NULL: recorded on the stream immediately
  *               before and after the trace kernel itself (after the tile

@@ -110,16 +110,24 @@ struct FrustumLds {
 };
 
 // LDS of one wave: the leaf candidates awaiting the exact test (a column per
-// lane) and the traversal stacks.  The per-lane stacks are only used by a
-// frustum-walk tile that fell back to the per-lane walk, when its candidate
-// lists are no longer needed, so the two share memory.
+// lane) and the traversal stacks; with the frustum walk also its lists.  The
+// per-lane stacks are only used by a frustum-walk tile that fell back to the
+// per-lane walk, when its lists are no longer needed, so the two share
+// memory.  The other walks do without the lists (their waves fit more per CU).
+template <bool FR>
 struct WaveLds {
-    uint32_t cand[kQueue][kWave];          // (wide node index << 2) | slot
+    uint32_t cand[kQueue][kWave];            // (wide node index << 2) | slot
+    uint32_t lstack[kLaneStack][kWave];      // per-lane walk: a stack per lane
+    uint32_t stack[kStack];                  // packet walk: one stack per wave
+};
+template <>
+struct WaveLds<true> {
+    uint32_t cand[kQueue][kWave];
     union {
-        uint32_t lstack[kLaneStack][kWave];  // per-lane walk: a stack per lane
-        FrustumLds fr;                       // frustum walk
+        uint32_t lstack[kLaneStack][kWave];
+        FrustumLds fr;
     };
-    uint32_t stack[kStack];                // packet walk: one stack per wave
+    uint32_t stack[kStack];
 };
 
 // A lane's hits of one pass, sorted by key, in registers (every index is a
@@ -136,7 +144,7 @@ struct HitBuf {
 
 template <int K, bool BWD, int WALK>
 __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ nodes, const BvhHeader *__restrict__ hdr,
-                           int tile_x, int tile_y, WaveLds &L)
+                           int tile_x, int tile_y, WaveLds<WALK == SPLAT_WALK_FRUSTUM> &L)
 {
     // the frustum walk falls back to the per-lane walk for a tile whose
     // candidate lists overflow
@@ -377,17 +385,34 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
         // prune key.  Afterwards the prune key moves down to the hit at which
         // the alpha stop is already certain (the same float steps as the
         // compositing below).
+        // The slots of kFlushGroup queue entries are loaded together before
+        // any of them is tested, so a flush waits for memory once per group
+        // (entries past a lane's queue read slot 0 of node 0, never used).
+        // The frustum walk tests one entry at a time: its kernel keeps fewer
+        // registers that way, and more of its waves fit a SIMD.
+        constexpr int kFlushGroup = FRUSTUM ? 1 : 4;
         auto flush = [&]() {
             bool changed = false;
-            for (uint32_t j = 0; j < (uint32_t)kQueue; ++j) {
-                if (!__ballot(j < nc)) break;
-                if (j >= nc) continue;
-                const uint32_t e = L.cand[j][lane];
-                const float *s = nodes[e >> 2].f + 6 * (e & 3u);
-                const float2 s01 = *reinterpret_cast<const float2 *>(s);
-                const float2 s23 = *reinterpret_cast<const float2 *>(s + 2);
-                const float ca = s[4];
-                const uint32_t id = __float_as_uint(nodes[e >> 2].f[24 + (e & 3u)]) & ~kLeafBit;
+            for (uint32_t j0 = 0; j0 < (uint32_t)kQueue; j0 += kFlushGroup) {
+              if (!__ballot(j0 < nc)) break;
+              float2 p01[kFlushGroup], p23[kFlushGroup];
+              float pa[kFlushGroup];
+              uint32_t pid[kFlushGroup];
+#pragma unroll
+              for (int u = 0; u < kFlushGroup; ++u) {
+                  const uint32_t e = j0 + u < nc ? L.cand[j0 + u][lane] : 0u;
+                  const float *s = nodes[e >> 2].f + 6 * (e & 3u);
+                  p01[u] = *reinterpret_cast<const float2 *>(s);
+                  p23[u] = *reinterpret_cast<const float2 *>(s + 2);
+                  pa[u] = s[4];
+                  pid[u] = __float_as_uint(nodes[e >> 2].f[24 + (e & 3u)]) & ~kLeafBit;
+              }
+#pragma unroll
+              for (int u = 0; u < kFlushGroup; ++u) {
+                if (j0 + u >= nc) continue;
+                const float2 s01 = p01[u], s23 = p23[u];
+                const float ca = pa[u];
+                const uint32_t id = pid[u];
                 if (id >= n_spheres) continue;
                 const double oc0 = (double)s01.x - eye.o[0], oc1 = (double)s01.y - eye.o[1],
                              oc2 = (double)s23.x - eye.o[2];
@@ -439,6 +464,7 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
                     pr_id = B.id[K - 1];
                     pr_f = (float)(pr_t * (1.0 + 0x1p-20));
                 }
+              }
             }
             nc = 0;
             if (changed) {
@@ -629,25 +655,34 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
         // screen test is the disc above; the depth range must reach below the
         // prune key and past the last composited key, as in the per-lane
         // prefilter.  Survivors are queued for the exact test, as in the walks.
-        auto cand_pass = [&]() {
-            uint32_t j = 0;
-            while (j < n_cand) {
-                do {
-                    const float4 dc = L.fr.disc[j];
-                    const float2 fr = L.fr.far_ref[j];
-                    const float du = sxl - dc.x, dv = syl - dc.y;
-                    const bool may = (fmaf(du, du, dv * dv) <= dc.z) & (dc.w <= pr_f) & (fr.x >= lo_f);
-                    // nc < kQueue here: the queue is flushed once a lane fills it
-                    L.cand[nc][lane] = __float_as_uint(fr.y);
+        // kCandGroup candidates per round, their records read together.
+        constexpr int kCandGroup = 2;
+        auto cand_pass = [&](auto &F) {
+            for (uint32_t j = 0; j < n_cand; j += kCandGroup) {
+                float4 dc[kCandGroup];
+                float2 fr[kCandGroup];
+#pragma unroll
+                for (int u = 0; u < kCandGroup; ++u) {
+                    const uint32_t i = min(j + (uint32_t)u, n_cand - 1u);
+                    dc[u] = F.disc[i];
+                    fr[u] = F.far_ref[i];
+                }
+#pragma unroll
+                for (int u = 0; u < kCandGroup; ++u) {
+                    const float du = sxl - dc[u].x, dv = syl - dc[u].y;
+                    const bool may = (j + u < n_cand) & (fmaf(du, du, dv * dv) <= dc[u].z) & (dc[u].w <= pr_f) &
+                                     (fr[u].x >= lo_f);
+                    // nc <= kQueue - kCandGroup at the start of a round: the
+                    // queue is flushed once a lane could overflow it
+                    L.cand[nc][lane] = __float_as_uint(fr[u].y);
                     nc += may ? 1u : 0u;
-                    ++j;
-                } while (j < n_cand && !__ballot(nc >= (uint32_t)kQueue));
-                if (__ballot(nc >= (uint32_t)kQueue)) flush();
+                }
+                if (__ballot(nc > (uint32_t)(kQueue - kCandGroup))) flush();
             }
         };
         if constexpr (FRUSTUM) {
             if (!fb) {
-                cand_pass();
+                cand_pass(L.fr);
             } else {
                 lane_walk(SignTag<kMixedSigns>{});
                 redo = overflow;
@@ -862,7 +897,7 @@ __host__ inline uint32_t blocks_for(int tiles_x, int tiles_y, int schedule)
 template <int K, bool BWD, int WALK>
 __global__ void __launch_bounds__(64) k_trace(TraceArgs a, int tiles_x, int tiles_y)
 {
-    __shared__ WaveLds lds;
+    __shared__ WaveLds<WALK == SPLAT_WALK_FRUSTUM> lds;
     int tx, ty;
     if (a.order) {
         if (blockIdx.x >= (uint32_t)(tiles_x * tiles_y)) return;
@@ -890,7 +925,7 @@ k_trace_batched(const splat_batch_job *__restrict__ jobs, const uint32_t *__rest
                 uint32_t total_tiles, float alpha_stop, int mode, double t_max, int tile_w, int tile_h,
                 uint32_t *__restrict__ counter)
 {
-    __shared__ WaveLds lds;
+    __shared__ WaveLds<WALK == SPLAT_WALK_FRUSTUM> lds;
     uint32_t claim = 0;
     if (threadIdx.x == 0) claim = atomicAdd(counter, 1u);
     uint32_t item = ufirst(claim);

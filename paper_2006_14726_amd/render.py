@@ -307,7 +307,7 @@ class TraceOptions:
     kbuf: int = 6
     tile: tuple = field(default=(8, 8))
     schedule: int = 2  # 0 super-tiles per XCD, 1 bands, 2 heaviest tiles first
-    walk: int = 0  # SPLAT_WALK_LANE (0) or SPLAT_WALK_PACKET (1)
+    walk: int = 2  # SPLAT_WALK_LANE (0), SPLAT_WALK_PACKET (1) or SPLAT_WALK_FRUSTUM (2)
     # raw hipEvent_t handles (torch.cuda.Event.cuda_event, after a first record) recorded around the trace
     # kernel alone; (0, 0) for none
     events: tuple = field(default=(0, 0))

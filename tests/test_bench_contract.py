@@ -28,8 +28,8 @@ def test_trace_bytes_counts_spheres_nodes_and_pixels():
 
 
 def test_profile_figures_only_for_the_profiled_configuration():
-    base = dict(kbuf=6, tile="8x8", scale=1.0, walk=0, schedule=2)
-    for change in ({"kbuf": 8}, {"tile": "16x4"}, {"scale": 2.0}, {"walk": 1}, {"schedule": 0}):
+    base = dict(kbuf=6, tile="8x8", scale=1.0, walk=2, schedule=2)
+    for change in ({"kbuf": 8}, {"tile": "16x4"}, {"scale": 2.0}, {"walk": 0}, {"schedule": 0}):
         a = argparse.Namespace(**dict(base, **change))
         assert bench.measured_traffic(a) is None
         assert bench.valu_issue(a, 0.3) is None
