@@ -190,6 +190,10 @@ struct BuildLayout {
 constexpr int kOrderBuckets = 64;
 constexpr int kOrderMinTiles = 8192;  // fewer tiles: the order is skipped (schedule 0)
 
+// With the frustum walk, the heaviest tiles of the order are traced as four
+// quadrant items each: the first order_split(tiles) tiles, at most 1024.
+__host__ __device__ inline uint32_t order_split(uint32_t tiles) { return tiles / 64 < 1024 ? tiles / 64 : 1024; }
+
 struct TileOrderLayout {
     size_t counts, bucket, order, hist, total;
     __host__ __device__ explicit TileOrderLayout(uint32_t tiles)
@@ -198,7 +202,7 @@ struct TileOrderLayout {
         counts = 0;
         bucket = align256(counts + t * 4);
         order = align256(bucket + t * 4);
-        hist = align256(order + t * 4);
+        hist = align256(order + (t + 3 * (size_t)order_split(tiles)) * 4);  // the items
         total = align256(hist + 2 * kOrderBuckets * 4);  // histogram, then cursors
     }
 };

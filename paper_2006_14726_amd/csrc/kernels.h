@@ -20,7 +20,8 @@ struct TraceArgs {
     int32_t tile_w, tile_h;
     int32_t schedule;           // tile -> XCD assignment (0 super-tiles, 1 bands)
     int32_t walk;               // SPLAT_WALK_LANE or SPLAT_WALK_PACKET
-    const uint32_t *order;      // schedule 2: tile of each block, heaviest first (else NULL)
+    const uint32_t *order;      // schedule 2: item of each block, heaviest first (else NULL): tile << 3 | part
+    uint32_t order_items;       // schedule 2: items of the order
     float4 *out;                // forward output
     uint32_t *hits;             // nullable
     // backward only
@@ -54,9 +55,10 @@ hipError_t launch_build(const splat_spheres &sph, const splat_bvh &bvh, bool ref
 hipError_t launch_trace(const TraceArgs &a, bool backward, void *ws, hipStream_t s, hipEvent_t ev_begin,
                         hipEvent_t ev_end);
 
-// Schedule 2: computes the heaviest-first tile order into the workspace.
+// Schedule 2: computes the heaviest-first order of trace items into the
+// workspace (the heaviest tiles as four quadrant items each).
 hipError_t launch_tile_order(const TraceArgs &a, int tiles_x, int tiles_y, void *ws, hipStream_t s,
-                             const uint32_t **order_out);
+                             const uint32_t **order_out, uint32_t *items_out);
 
 hipError_t launch_trace_batched(const splat_batch_job *jobs, const uint32_t *tile_offsets, int32_t n_jobs,
                                 uint32_t total_tiles, const splat_trace_opts &o, int32_t waves, void *ws,

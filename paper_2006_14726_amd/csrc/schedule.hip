@@ -17,7 +17,8 @@
 //   keys     one thread per tile, 16 x 16 tiles per block through LDS:
 //            neighbourhood maximum (separable) -> log bucket (bucket 0 =
 //            heaviest) and the bucket histogram
-//   scatter  one thread per tile: its slot in the order, buckets ascending
+//   scatter  one thread per tile: its slot in the order, buckets ascending;
+//            the heaviest tiles as four quadrant items each
 #include "common.h"
 #include "kernels.h"
 
@@ -119,11 +120,13 @@ k_tile_keys(const uint32_t *__restrict__ counts, int tiles_x, int tiles_y, uint3
 }
 
 // Every block scans the bucket histogram itself (64 entries, one wave);
-// slots are reserved per block and bucket with one atomic on the bucket's
-// cursor, then handed out within the block.  The order inside a bucket is
-// arbitrary.
+// positions are reserved per block and bucket with one atomic on the
+// bucket's cursor, then handed out within the block.  The order inside a
+// bucket is arbitrary.  A tile at position p < split becomes the four items
+// 4p .. 4p + 3 (tile << 3 | quadrant); a later one the item p + 3 split
+// (tile << 3 | 4, the whole tile).
 __global__ void __launch_bounds__(kOrderBlock)
-k_tile_scatter(const uint32_t *__restrict__ bucket, uint32_t tiles, uint32_t *__restrict__ hist,
+k_tile_scatter(const uint32_t *__restrict__ bucket, uint32_t tiles, uint32_t split, uint32_t *__restrict__ hist,
                uint32_t *__restrict__ order)
 {
     static_assert(kOrderBuckets == kWave, "one bucket per lane");
@@ -150,11 +153,18 @@ k_tile_scatter(const uint32_t *__restrict__ bucket, uint32_t tiles, uint32_t *__
     if (threadIdx.x < (unsigned)kOrderBuckets && cnt[threadIdx.x])
         base[threadIdx.x] = start[threadIdx.x] + atomicAdd(&cursor[threadIdx.x], cnt[threadIdx.x]);
     __syncthreads();
-    if (t < tiles) order[base[b] + rank] = t;
+    if (t < tiles) {
+        const uint32_t pos = base[b] + rank;
+        if (pos < split) {
+            for (uint32_t q = 0; q < 4; ++q) order[4 * pos + q] = (t << 3) | q;
+        } else {
+            order[pos + 3 * split] = (t << 3) | 4u;
+        }
+    }
 }
 
 hipError_t launch_tile_order(const TraceArgs &a, int tiles_x, int tiles_y, void *ws, hipStream_t s,
-                             const uint32_t **order_out)
+                             const uint32_t **order_out, uint32_t *items_out)
 {
     const uint32_t tiles = (uint32_t)tiles_x * (uint32_t)tiles_y;
     const TileOrderLayout W(tiles);
@@ -176,8 +186,12 @@ hipError_t launch_tile_order(const TraceArgs &a, int tiles_x, int tiles_y, void 
                        a.tile_w, a.tile_h, tiles_x, tiles_y, counts);
     const dim3 key_grid((tiles_x + kKeyTile - 1) / kKeyTile, (tiles_y + kKeyTile - 1) / kKeyTile);
     hipLaunchKernelGGL(k_tile_keys, key_grid, dim3(kOrderBlock), 0, s, counts, tiles_x, tiles_y, bucket, hist);
-    hipLaunchKernelGGL(k_tile_scatter, dim3(tile_blocks), dim3(kOrderBlock), 0, s, bucket, tiles, hist, order);
+    // quadrant items pay off only with the frustum walk, whose costly tiles
+    // are the ones whose frustum meets a long stretch of the sphere sheet
+    const uint32_t split = a.walk == SPLAT_WALK_FRUSTUM ? order_split(tiles) : 0u;
+    hipLaunchKernelGGL(k_tile_scatter, dim3(tile_blocks), dim3(kOrderBlock), 0, s, bucket, tiles, split, hist, order);
     *order_out = order;
+    *items_out = tiles + 3 * split;
     return hipGetLastError();
 }
 

@@ -142,18 +142,28 @@ struct HitBuf {
 
 // ---------------------------------------------------------------- one tile
 
+// Region of a tile, in pixel columns [x0, x1) and rows [y0, y1) of the
+// tile: the lanes outside it take no part.  The heaviest-first order gives
+// the heaviest tiles to four waves, one per quadrant, so that they run side
+// by side instead of on one wave at the end of the launch.
+struct TileRegion {
+    int x0, x1, y0, y1;
+};
+
+// Traces the pixels of one region of a tile; the frustum walk falls back to
+// the per-lane walk for a region whose candidate lists overflow.
 template <int K, bool BWD, int WALK>
 __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ nodes, const BvhHeader *__restrict__ hdr,
-                           int tile_x, int tile_y, WaveLds<WALK == SPLAT_WALK_FRUSTUM> &L)
+                           int tile_x, int tile_y, WaveLds<WALK == SPLAT_WALK_FRUSTUM> &L, TileRegion rg)
 {
-    // the frustum walk falls back to the per-lane walk for a tile whose
-    // candidate lists overflow
     constexpr bool FRUSTUM = WALK == SPLAT_WALK_FRUSTUM;
     constexpr bool LANE = WALK == SPLAT_WALK_LANE || FRUSTUM;
     const int lane = threadIdx.x & (kWave - 1);
-    const int px = tile_x * a.tile_w + (lane % a.tile_w);
-    const int py = tile_y * a.tile_h + (lane / a.tile_w);
-    const bool inside = px >= 0 && py >= 0 && px < a.cam.w && py < a.cam.h;
+    const int lx = lane % a.tile_w, ly = lane / a.tile_w;
+    const int px = tile_x * a.tile_w + lx;
+    const int py = tile_y * a.tile_h + ly;
+    const bool inside = px >= 0 && py >= 0 && px < a.cam.w && py < a.cam.h && lx >= rg.x0 && lx < rg.x1 &&
+                        ly >= rg.y0 && ly < rg.y1;
     // the header count is clamped to the allocation, so even a BVH that was
     // never built cannot send the walk outside it
     const uint32_t n_spheres = min(ufirst(hdr->n), a.bvh_capacity);
@@ -256,7 +266,9 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
             sxl = (float)(((2.0 * cx + 1.0) / (double)a.cam.w - 1.0) * a.cam.tan_half * aspect);
             syl = (float)((1.0 - (2.0 * cy + 1.0) / (double)a.cam.h) * a.cam.tan_half);
         }
-        const int corner[4] = {0, a.tile_w - 1, kWave - 1, kWave - a.tile_w};  // clockwise on the screen
+        const int tw = a.tile_w;  // the region's corner lanes, clockwise on the screen
+        const int corner[4] = {rg.y0 * tw + rg.x0, rg.y0 * tw + rg.x1 - 1, (rg.y1 - 1) * tw + rg.x1 - 1,
+                               (rg.y1 - 1) * tw + rg.x0};
         double cd[4][3];
 #pragma unroll
         for (int c = 0; c < 4; ++c)
@@ -899,11 +911,22 @@ __global__ void __launch_bounds__(64) k_trace(TraceArgs a, int tiles_x, int tile
 {
     __shared__ WaveLds<WALK == SPLAT_WALK_FRUSTUM> lds;
     int tx, ty;
+    TileRegion rg = {0, a.tile_w, 0, a.tile_h};
     if (a.order) {
-        if (blockIdx.x >= (uint32_t)(tiles_x * tiles_y)) return;
-        const uint32_t t = a.order[blockIdx.x];
+        // an item of the heaviest-first order: tile << 3 | part, part 4 the
+        // whole tile, 0..3 one of its quadrants
+        if (blockIdx.x >= a.order_items) return;
+        const uint32_t item = a.order[blockIdx.x], t = item >> 3, part = item & 7u;
+        if (t >= (uint32_t)(tiles_x * tiles_y)) return;
         tx = (int)(t % (uint32_t)tiles_x);
         ty = (int)(t / (uint32_t)tiles_x);
+        if (part < 4u) {
+            const int nx = a.tile_w >= 2 ? 2 : 1, ny = a.tile_h >= 2 ? 2 : 1;
+            const int rx = (int)(part & 1u) % nx, ry = (int)(part >> 1) % ny;
+            // a one-row or one-column tile has two parts; the others are empty
+            if ((int)(part & 1u) >= nx || (int)(part >> 1) >= ny) return;
+            rg = {rx * a.tile_w / nx, (rx + 1) * a.tile_w / nx, ry * a.tile_h / ny, (ry + 1) * a.tile_h / ny};
+        }
     } else if (!tile_of_block(blockIdx.x, tiles_x, tiles_y, a.schedule, tx, ty)) {
         return;
     }
@@ -911,7 +934,7 @@ __global__ void __launch_bounds__(64) k_trace(TraceArgs a, int tiles_x, int tile
     const BvhLayout L(a.layout_cap);
     const BvhHeader *hdr = reinterpret_cast<const BvhHeader *>(mem);
     const WideNode *nodes = reinterpret_cast<const WideNode *>(mem + L.wide);
-    trace_tile<K, BWD, WALK>(a, nodes, hdr, tx, ty, lds);
+    trace_tile<K, BWD, WALK>(a, nodes, hdr, tx, ty, lds, rg);
 }
 
 // Persistent batched trace: waves pull tiles from one atomic counter until
@@ -964,6 +987,7 @@ k_trace_batched(const splat_batch_job *__restrict__ jobs, const uint32_t *__rest
         a.schedule = 0;
         a.walk = WALK;
         a.order = nullptr;
+        a.order_items = 0;
         a.out = reinterpret_cast<float4 *>(j.out_rgba);
         a.hits = j.out_hits;
         a.grad = nullptr;
@@ -972,8 +996,9 @@ k_trace_batched(const splat_batch_job *__restrict__ jobs, const uint32_t *__rest
         const int64_t t64 = (int64_t)item - (int64_t)tile_offsets[lo];
         const int t = t64 < 0 ? 0x7fffffff : (int)min(t64, (int64_t)0x7fffffff);
         const char *mem = static_cast<const char *>(j.bvh_mem);
+        const TileRegion whole = {0, tile_w, 0, tile_h};
         trace_tile<K, false, WALK>(a, reinterpret_cast<const WideNode *>(mem + L.wide), reinterpret_cast<const BvhHeader *>(mem),
-                             t % tiles_x, t / tiles_x, lds);
+                             t % tiles_x, t / tiles_x, lds, whole);
         item = ufirst(claim);
     }
 }
@@ -1005,14 +1030,15 @@ hipError_t launch_trace(const TraceArgs &args, bool backward, void *ws, hipStrea
     const int tiles_x = (a.cam.w + a.tile_w - 1) / a.tile_w;
     const int tiles_y = (a.cam.h + a.tile_h - 1) / a.tile_h;
     a.order = nullptr;
+    a.order_items = 0;
     // with few tiles every wave is resident from the start and the order
     // cannot pay for its kernels: schedule 0 then
     if (a.schedule == 2 && tiles_x * tiles_y <= kOrderMinTiles) a.schedule = 0;
     if (a.schedule == 2) {
-        const hipError_t e = launch_tile_order(a, tiles_x, tiles_y, ws, s, &a.order);
+        const hipError_t e = launch_tile_order(a, tiles_x, tiles_y, ws, s, &a.order, &a.order_items);
         if (e != hipSuccess) return e;
     }
-    const dim3 grid(a.order ? (uint32_t)(tiles_x * tiles_y) : blocks_for(tiles_x, tiles_y, a.schedule));
+    const dim3 grid(a.order ? a.order_items : blocks_for(tiles_x, tiles_y, a.schedule));
     // optional events bracketing the trace kernel alone (not the tile ordering)
     if (ev_begin) {
         const hipError_t e = hipEventRecord(ev_begin, s);
