@@ -540,7 +540,10 @@ def radius_policies(sp, torch, synth, dev, src, dst, opts, reps):
     for name, mode, kw in (("footprint", sp.SPLAT_RADIUS_FOOTPRINT, {}),
                            ("opacity", sp.SPLAT_RADIUS_OPACITY, {"opacity_floor": 0.05}),
                            ("interval", sp.SPLAT_RADIUS_INTERVAL, {"interval_scale": 0.1}),
-                           ("interval_wide", sp.SPLAT_RADIUS_INTERVAL, {"interval_scale": 0.25})):
+                           ("interval_wide", sp.SPLAT_RADIUS_INTERVAL, {"interval_scale": 0.25}),
+                           ("spheroid", sp.SPLAT_RADIUS_SPHEROID, {"interval_scale": 0.1}),
+                           ("spheroid_wide", sp.SPLAT_RADIUS_SPHEROID, {"interval_scale": 0.25}),
+                           ("spheroid_full", sp.SPLAT_RADIUS_SPHEROID, {"interval_scale": 1.0})):
         sph = sp.unproject_policy(src, rgba, depth, mode, interval=itv, **kw)
         bvh = sp.build_bvh(sph)
         img, hits = sp.trace(bvh, sph, dst, opts)
@@ -558,11 +561,17 @@ def radius_policies(sp, torch, synth, dev, src, dst, opts, reps):
         if base is None:
             base = img.clone()
         r = sph.centre_radius[:sph.n(), 3]
-        out[name] = {"params": kw, "spheres": sph.n(), "median_radius": round(float(r.median()), 6),
+        extra = {}
+        if sph.axis is not None:
+            extra["median_half_length"] = round(float(sph.axis[:sph.n(), 3].median()), 6)
+        out[name] = {"params": kw, "spheres": sph.n(), "median_radius": round(float(r.median()), 6), **extra,
                      "mean_hits": round(float(hits.float().mean()), 3),
                      "stages_ms": {k: round(float(v), 4) for k, v in zip(("unproject", "build", "trace"), med)},
                      "trace_ms_kbuf16": round(t16, 4),
                      "image_mean_abs_change": round(float((img - base).abs().mean()), 6)}
+    foot = out["footprint"]["stages_ms"]["trace"]
+    for name in out:
+        out[name]["trace_over_footprint"] = round(out[name]["stages_ms"]["trace"] / foot, 3)
     return out
 
 

@@ -79,6 +79,14 @@ typedef struct splat_camera {
  *   rgba_dtype     SPLAT_F16 or SPLAT_F32
  *   src_index      device uint32[capacity]: source pixel of each sphere (may be NULL)
  *   count          device uint32 scalar: N
+ *   axis           device float4[capacity] or NULL.  With it the samples are
+ *                  prolate spheroids smeared along their source ray (Sec. 7):
+ *                  axis (ux, uy, uz) and half-length h >= r along it, radius r
+ *                  across it, i.e. the points x with
+ *                  |x - c|^2 / r^2 + ((x - c).u)^2 (1/h^2 - 1/r^2) <= 1
+ *                  (u as stored, scaled to unit length in double).  Spheroid sets are traced
+ *                  with constant alpha only; the backward, the sample codec,
+ *                  the accumulation and the batched trace take sphere sets.
  * Sphere ids are slot indices; they break ties between equal hit distances.
  */
 typedef struct splat_spheres {
@@ -89,6 +97,7 @@ typedef struct splat_spheres {
     uint32_t *src_index;
     uint32_t *count;
     uint32_t capacity;
+    float *axis;
 } splat_spheres;
 
 /*
@@ -323,11 +332,18 @@ int splat_unproject(const splat_camera *src, const float *rgba_premul, const flo
  *                           the centre at t_c = (t_lo + t_hi) / 2 on the ray,
  *                           r = max(radius_scale fp(t_c), interval_scale (t_hi - t_lo) / 2);
  *                           a pixel then also needs 0 < t_lo <= t_hi, both finite
+ *   SPLAT_RADIUS_SPHEROID   the same pixels and centres as the interval policy,
+ *                           smeared along the ray instead of grown in every
+ *                           direction: r = radius_scale fp(t_c) across the ray,
+ *                           axis u = the unit pixel ray d and half-length
+ *                           h = max(r, interval_scale (t_hi - t_lo) / 2) along it,
+ *                           written to out->axis (required) as (u, h)
  * All in double, each output rounded once to float.
  */
 #define SPLAT_RADIUS_FOOTPRINT 0
 #define SPLAT_RADIUS_OPACITY 1
 #define SPLAT_RADIUS_INTERVAL 2
+#define SPLAT_RADIUS_SPHEROID 3
 
 typedef struct splat_radius_policy {
     int32_t mode;           /* SPLAT_RADIUS_* */
@@ -429,7 +445,7 @@ int splat_trace_batched(const splat_batch_job *jobs, const uint32_t *tile_offset
 /* Thread-local text for the last non-zero status. */
 const char *splat_last_error(void);
 
-/* ABI version (major * 100 + minor). */
+/* ABI version (major * 100 + minor): 106 added splat_spheres.axis. */
 int splat_version(void);
 
 #ifdef __cplusplus

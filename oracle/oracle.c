@@ -317,7 +317,9 @@ int orc_sphere_test(const double o[3], const double d[3], const double c[3], dou
  * Ray against a prolate spheroid (Sec. 7 suggests smearing a sample whose
  * depth is uncertain over an interval along its ray; this is that shape):
  * centre c, axis u, half-length h along u and radius r across it, the points
- * x with |x - c|^2 / r^2 + ((x - c).u)^2 (1/h^2 - 1/r^2) <= 1.  The linear
+ * x with |x - c|^2 / r^2 + ((x - c).u)^2 (1/h^2 - 1/r^2) <= 1, u the given
+ * axis scaled to unit length in double (a stored float axis is off unit length
+ * by rounding, and the shape must stay a spheroid for any r / h).  The linear
  * map S y = y / r + (y.u)(1/h - 1/r) u takes it to the unit ball, and the ray
  * o + t d (d unit) to t D - L with D = S d, L = S (c - o).  The robust form of
  * the sphere test then applies in those coordinates: t_m = L.D / D.D,
@@ -325,11 +327,13 @@ int orc_sphere_test(const double o[3], const double d[3], const double c[3], dou
  * out[0] = t0, out[1] = disc, out[2] = t_m, out[3] = qq.
  * Returns 1 iff disc >= 0 and 0 < t0 < t_max.  With h = r this is the sphere.
  */
-int orc_spheroid_test(const double o[3], const double d[3], const double c[3], double r, const double u[3], double h,
-                      double t_max, double out[4])
+int orc_spheroid_test(const double o[3], const double d[3], const double c[3], double r, const double u_in[3],
+                      double h, double t_max, double out[4])
 {
     const double oc[3] = {c[0] - o[0], c[1] - o[1], c[2] - o[2]};
     const double w = 1.0 / h - 1.0 / r;
+    const double ul = sqrt(u_in[0] * u_in[0] + u_in[1] * u_in[1] + u_in[2] * u_in[2]);
+    const double u[3] = {u_in[0] / ul, u_in[1] / ul, u_in[2] / ul};
     const double du = d[0] * u[0] + d[1] * u[1] + d[2] * u[2];
     const double ou = oc[0] * u[0] + oc[1] * u[1] + oc[2] * u[2];
     double D[3], L[3];

@@ -11,7 +11,7 @@ SPLAT_OK, SPLAT_EINVAL, SPLAT_ENOSPC, SPLAT_ENODEV, SPLAT_EHIP, SPLAT_EUNSUPPORT
 SPLAT_F32, SPLAT_F16 = 0, 1
 SPLAT_ALPHA_CONSTANT, SPLAT_ALPHA_SOFT = 0, 1
 SPLAT_WALK_LANE, SPLAT_WALK_PACKET = 0, 1
-SPLAT_RADIUS_FOOTPRINT, SPLAT_RADIUS_OPACITY, SPLAT_RADIUS_INTERVAL = 0, 1, 2
+SPLAT_RADIUS_FOOTPRINT, SPLAT_RADIUS_OPACITY, SPLAT_RADIUS_INTERVAL, SPLAT_RADIUS_SPHEROID = 0, 1, 2, 3
 SPLAT_OP_UNPROJECT, SPLAT_OP_BUILD, SPLAT_OP_TRACE, SPLAT_OP_BACKWARD, SPLAT_OP_BATCHED, SPLAT_OP_ACCUMULATE = range(6)
 
 # every symbol include/splat.h declares
@@ -31,7 +31,7 @@ class splat_camera(ctypes.Structure):
 
 class splat_spheres(ctypes.Structure):
     _fields_ = [("centre_radius", _P), ("rgba", _P), ("rgba_dtype", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("src_index", _P), ("count", _P), ("capacity", ctypes.c_uint32)]
+                ("src_index", _P), ("count", _P), ("capacity", ctypes.c_uint32), ("axis", _P)]
 
 
 class splat_bvh(ctypes.Structure):

@@ -118,7 +118,7 @@ int hip_status(hipError_t e, const char *what)
 
 extern "C" {
 
-int splat_version(void) { return 105; }
+int splat_version(void) { return 106; }
 
 const char *splat_last_error(void) { return g_err; }
 
@@ -199,6 +199,7 @@ int splat_encode_samples(const splat_spheres *sph, const splat_codec *codec, uin
 {
     int rc;
     if ((rc = check_spheres(sph, true))) return rc;
+    if (sph->axis) return fail(SPLAT_EUNSUPPORTED, "the sample codec takes sphere sets (no axis)");
     if ((rc = check_codec(codec))) return rc;
     if (!out_pos || !out_rgba) return fail(SPLAT_EINVAL, "out_pos/out_rgba is NULL");
     if ((rc = check_device())) return rc;
@@ -212,6 +213,7 @@ int splat_decode_samples(const uint64_t *pos, const uint32_t *rgba, const uint32
     int rc;
     if (!pos || !rgba || !count) return fail(SPLAT_EINVAL, "pos/rgba/count is NULL");
     if ((rc = check_spheres(out, true))) return rc;
+    if (out->axis) return fail(SPLAT_EUNSUPPORTED, "the sample codec takes sphere sets (no axis)");
     if ((rc = check_codec(codec))) return rc;
     if ((rc = check_device())) return rc;
     return hip_status(launch_decode(pos, rgba, count, *codec, *out, static_cast<hipStream_t>(stream)),
@@ -246,6 +248,8 @@ int splat_accumulate(const splat_spheres *frame, const splat_spheres *history, c
             return fail(SPLAT_EINVAL, "history and frame colour dtypes differ");
     }
     if (out->rgba_dtype != frame->rgba_dtype) return fail(SPLAT_EINVAL, "out and frame colour dtypes differ");
+    if (frame->axis || out->axis || (history && history->axis))
+        return fail(SPLAT_EUNSUPPORTED, "the accumulation takes sphere sets (no axis)");
     if (!out_age) return fail(SPLAT_EINVAL, "out_age is NULL");
     if (out->src_index && (!frame->src_index || (history && !history->src_index)))
         return fail(SPLAT_EINVAL, "out->src_index needs src_index on the frame and the history");
@@ -292,14 +296,16 @@ int splat_unproject_policy(const splat_camera *src, const float *rgba_premul, co
     if ((rc = check_spheres(out, true))) return rc;
     if (!policy) return fail(SPLAT_EINVAL, "radius policy is NULL");
     if (policy->mode != SPLAT_RADIUS_FOOTPRINT && policy->mode != SPLAT_RADIUS_OPACITY &&
-        policy->mode != SPLAT_RADIUS_INTERVAL)
+        policy->mode != SPLAT_RADIUS_INTERVAL && policy->mode != SPLAT_RADIUS_SPHEROID)
         return fail(SPLAT_EUNSUPPORTED, "unknown radius policy %d", policy->mode);
+    if (policy->mode == SPLAT_RADIUS_SPHEROID && !out->axis)
+        return fail(SPLAT_EINVAL, "the spheroid policy needs out->axis");
     if (!std::isfinite(policy->radius_scale) || policy->radius_scale < 0)
         return fail(SPLAT_EINVAL, "radius_scale must be >= 0");
     if (policy->mode == SPLAT_RADIUS_OPACITY && !(policy->opacity_floor > 0 && policy->opacity_floor <= 1))
         return fail(SPLAT_EINVAL, "opacity_floor must be in (0, 1]");
-    if (policy->mode == SPLAT_RADIUS_INTERVAL) {
-        if (!interval) return fail(SPLAT_EINVAL, "the interval policy needs the depth interval");
+    if (policy->mode == SPLAT_RADIUS_INTERVAL || policy->mode == SPLAT_RADIUS_SPHEROID) {
+        if (!interval) return fail(SPLAT_EINVAL, "the interval policies need the depth interval");
         if (!std::isfinite(policy->interval_scale) || policy->interval_scale < 0)
             return fail(SPLAT_EINVAL, "interval_scale must be >= 0");
     }
@@ -347,11 +353,14 @@ static int trace_common(const splat_bvh *bvh, const splat_spheres *sph, const sp
     if ((rc = check_camera(cam, "target"))) return rc;
     splat_trace_opts o;
     if ((rc = resolve_opts(opts, &o))) return rc;
+    if (sph->axis && o.mode != SPLAT_ALPHA_CONSTANT)
+        return fail(SPLAT_EUNSUPPORTED, "spheroid sets are traced with constant alpha only");
     std::memset(&a, 0, sizeof a);
     a.bvh_mem = bvh->mem;
     a.bvh_capacity = bvh->capacity < sph->capacity ? bvh->capacity : sph->capacity;
     a.layout_cap = bvh->capacity;
     a.centre_radius = reinterpret_cast<const float4 *>(sph->centre_radius);
+    a.axis = reinterpret_cast<const float4 *>(sph->axis);
     a.rgba = sph->rgba;
     a.half = sph->rgba_dtype == SPLAT_F16;
     a.cam = make_cam(*cam);
@@ -451,6 +460,7 @@ int splat_trace_backward(const splat_bvh *bvh, const splat_spheres *sph, const s
     if ((rc = trace_common(bvh, sph, cam, opts, a))) return rc;
     if (!out_rgba || !grad_rgba) return fail(SPLAT_EINVAL, "out_rgba/grad_rgba is NULL");
     if ((rc = check_trace_ws(a, ws, ws_bytes))) return rc;
+    if (sph->axis) return fail(SPLAT_EUNSUPPORTED, "the backward takes sphere sets (no axis)");
     if (!grads || !grads->d_rgb || !grads->d_alpha) return fail(SPLAT_EINVAL, "grads d_rgb/d_alpha is NULL");
     if (a.mode == SPLAT_ALPHA_SOFT && (!grads->d_radius || !grads->d_centre))
         return fail(SPLAT_EINVAL, "soft mode needs d_radius and d_centre");

@@ -397,19 +397,42 @@ __global__ void __launch_bounds__(256) k_zero_flags(uint32_t *__restrict__ flags
     if (i < (n > 1 ? n - 1 : 1)) flags[i] = 0u;
 }
 
-// Box of a child slot: the stored box of an internal child, or the sphere's
-// box c +- r rounded outward to float for a leaf child.
-__device__ inline void slot_box(const Node &nd, int side, float lo[3], float hi[3])
+// Box of a sample, rounded outward to float: c +- r for a sphere; for a
+// spheroid (axis set: unit axis u, half-length h along it, r across) its
+// exact extent along each coordinate axis, sqrt(r^2 + (h^2 - r^2) u_k^2), in
+// double, then rounded outward by one more float step.
+__device__ inline void leaf_box(float cx, float cy, float cz, float r, float h, const float4 *__restrict__ axis,
+                                uint32_t id, float lo[3], float hi[3])
+{
+    const float c[3] = {cx, cy, cz};
+    if (!axis) {
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = nextafterf(c[k] - r, -INFINITY);
+            hi[k] = nextafterf(c[k] + r, INFINITY);
+        }
+        return;
+    }
+    const float4 u = axis[id];
+    const double ul = sqrt((double)u.x * u.x + (double)u.y * u.y + (double)u.z * u.z);
+    const double un[3] = {u.x / ul, u.y / ul, u.z / ul};
+    const double rr = (double)r * r, hh = (double)h * h;
+    for (int k = 0; k < 3; ++k) {
+        const double e = sqrt(rr + (hh - rr) * un[k] * un[k]);
+        lo[k] = nextafterf((float)((double)c[k] - e), -INFINITY);
+        hi[k] = nextafterf((float)((double)c[k] + e), INFINITY);
+    }
+}
+
+// Box of a child slot: the stored box of an internal child, or the sample's
+// box (leaf_box) for a leaf child.
+__device__ inline void slot_box(const Node &nd, int side, const float4 *__restrict__ axis, float lo[3], float hi[3])
 {
     const uint32_t ref = __float_as_uint(nd.f[12 + side]);
     const float *s = nd.f + 6 * side;
     if (ref == kEmpty) {
         for (int a = 0; a < 3; ++a) { lo[a] = INFINITY; hi[a] = -INFINITY; }
     } else if (ref & kLeafBit) {
-        for (int a = 0; a < 3; ++a) {
-            lo[a] = nextafterf(s[a] - s[3], -INFINITY);
-            hi[a] = nextafterf(s[a] + s[3], INFINITY);
-        }
+        leaf_box(s[0], s[1], s[2], s[3], s[5], axis, ref & ~kLeafBit, lo, hi);
     } else {
         for (int a = 0; a < 3; ++a) { lo[a] = s[a]; hi[a] = s[3 + a]; }
     }
@@ -424,12 +447,12 @@ __device__ inline float sphere_alpha_a(const void *rgba, int half, uint32_t id)
 // Box of node p from its two slots, written into its parent's slot (or the
 // header for the root).  Returns the parent reference (kEmpty at the root).
 __device__ inline uint32_t lift_box(Node *nodes, uint32_t p, const uint32_t *__restrict__ node_parent,
-                                    BvhHeader *__restrict__ hdr)
+                                    const float4 *__restrict__ axis, BvhHeader *__restrict__ hdr)
 {
     const Node nd = nodes[p];
     float lo0[3], hi0[3], lo1[3], hi1[3];
-    slot_box(nd, 0, lo0, hi0);
-    slot_box(nd, 1, lo1, hi1);
+    slot_box(nd, 0, axis, lo0, hi0);
+    slot_box(nd, 1, axis, lo1, hi1);
     float lo[3], hi[3];
     for (int k = 0; k < 3; ++k) { lo[k] = fminf(lo0[k], lo1[k]); hi[k] = fmaxf(hi0[k], hi1[k]); }
     const uint32_t pp = node_parent[p];
@@ -453,7 +476,7 @@ __device__ inline uint32_t lift_box(Node *nodes, uint32_t p, const uint32_t *__r
 constexpr int kRefitThreads = 1024;
 
 __global__ void __launch_bounds__(kRefitThreads)
-k_refit_local(const float4 *__restrict__ cr, const void *__restrict__ rgba, int half,
+k_refit_local(const float4 *__restrict__ cr, const float4 *__restrict__ axis, const void *__restrict__ rgba, int half,
               const uint32_t *__restrict__ count, uint32_t cap, Node *nodes, const uint32_t *__restrict__ leaf_parent,
               const uint32_t *__restrict__ node_parent, const uint32_t *__restrict__ leaf_ids,
               const uint2 *__restrict__ ranges, const uint32_t *__restrict__ entries, BvhHeader *hdr)
@@ -482,25 +505,23 @@ k_refit_local(const float4 *__restrict__ cr, const void *__restrict__ rgba, int 
             if (id >= n) continue;  // only after a refit of a hierarchy that was never built
             const float4 c = cr[id];
             const float a = sphere_alpha_a(rgba, half, id);
+            // slot word 5: the spheroid's half-length along its axis (0 for a sphere)
+            const float h = axis ? axis[id].w : 0.0f;
             uint32_t pp = leaf_parent[j];
             uint32_t p = pp >> 1;
             if (p >= n_nodes) continue;
             {
                 float *sl = nodes[p].f + 6 * (pp & 1u);
-                sl[0] = c.x; sl[1] = c.y; sl[2] = c.z; sl[3] = c.w; sl[4] = a; sl[5] = 0.0f;
+                sl[0] = c.x; sl[1] = c.y; sl[2] = c.z; sl[3] = c.w; sl[4] = a; sl[5] = h;
             }
             if (n == 1) {
                 float *sl = nodes[0].f + 6;
                 for (int k = 0; k < 3; ++k) { sl[k] = INFINITY; sl[3 + k] = -INFINITY; }
-                lift_box(nodes, 0, node_parent, hdr);
+                lift_box(nodes, 0, node_parent, axis, hdr);
                 continue;
             }
-            const float ctr[3] = {c.x, c.y, c.z};
             float bl[3], bh[3];
-            for (int k = 0; k < 3; ++k) {
-                bl[k] = nextafterf(ctr[k] - c.w, -INFINITY);
-                bh[k] = nextafterf(ctr[k] + c.w, INFINITY);
-            }
+            leaf_box(c.x, c.y, c.z, c.w, h, axis, id, bl, bh);
             // (bl, bh) is the box of the child in slot (pp & 1) of node p
             for (;;) {
                 if (p < lo || p > hi) break;  // only a corrupt hierarchy leaves the treelet
@@ -542,7 +563,7 @@ k_refit_local(const float4 *__restrict__ cr, const void *__restrict__ rgba, int 
 constexpr int kTopThreads = 1024;
 
 __global__ void __launch_bounds__(kTopThreads)
-k_refit_top(const float4 *__restrict__ cr, const void *__restrict__ rgba, int half,
+k_refit_top(const float4 *__restrict__ cr, const float4 *__restrict__ axis, const void *__restrict__ rgba, int half,
             const uint32_t *__restrict__ count, uint32_t cap, Node *nodes, const uint32_t *__restrict__ leaf_parent,
             const uint32_t *__restrict__ node_parent, const uint32_t *__restrict__ leaf_ids, uint32_t *flags,
             const uint32_t *__restrict__ entries, BvhHeader *hdr)
@@ -562,7 +583,8 @@ k_refit_top(const float4 *__restrict__ cr, const void *__restrict__ rgba, int ha
             pp = leaf_parent[j];
             if ((pp >> 1) >= n_nodes) continue;
             float *sl = nodes[pp >> 1].f + 6 * (pp & 1u);
-            sl[0] = c.x; sl[1] = c.y; sl[2] = c.z; sl[3] = c.w; sl[4] = sphere_alpha_a(rgba, half, id); sl[5] = 0.0f;
+            sl[0] = c.x; sl[1] = c.y; sl[2] = c.z; sl[3] = c.w; sl[4] = sphere_alpha_a(rgba, half, id);
+            sl[5] = axis ? axis[id].w : 0.0f;
         } else {
             if (e >= n_nodes) continue;
             pp = node_parent[e];
@@ -572,7 +594,7 @@ k_refit_top(const float4 *__restrict__ cr, const void *__restrict__ rgba, int ha
         while (p < n_nodes) {
             const uint32_t old = __hip_atomic_fetch_add(&flags[p], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
             if (old != 1u) break;
-            const uint32_t up = lift_box(nodes, p, node_parent, hdr);
+            const uint32_t up = lift_box(nodes, p, node_parent, axis, hdr);
             if (up == kEmpty) break;
             p = up >> 1;
         }
@@ -674,9 +696,10 @@ hipError_t launch_build(const splat_spheres &sph, const splat_bvh &bvh, bool ref
         hipLaunchKernelGGL(k_header_count, dim3(1), dim3(64), 0, s, sph.count, cap, hdr);
         hipLaunchKernelGGL(k_zero_flags, dim3(blocks), dim3(256), 0, s, flags, sph.count, cap);
     }
-    hipLaunchKernelGGL(k_refit_local, dim3(refit_blocks), dim3(kRefitThreads), 0, s, cr, sph.rgba, half, sph.count,
-                       cap, nodes, leaf_parent, node_parent, leaf_ids, ranges, entries, hdr);
-    hipLaunchKernelGGL(k_refit_top, dim3(1), dim3(kTopThreads), 0, s, cr, sph.rgba, half, sph.count, cap, nodes,
+    const float4 *axis = reinterpret_cast<const float4 *>(sph.axis);
+    hipLaunchKernelGGL(k_refit_local, dim3(refit_blocks), dim3(kRefitThreads), 0, s, cr, axis, sph.rgba, half,
+                       sph.count, cap, nodes, leaf_parent, node_parent, leaf_ids, ranges, entries, hdr);
+    hipLaunchKernelGGL(k_refit_top, dim3(1), dim3(kTopThreads), 0, s, cr, axis, sph.rgba, half, sph.count, cap, nodes,
                        leaf_parent, node_parent, leaf_ids, flags, entries, hdr);
     hipLaunchKernelGGL(k_gather_wide, dim3(blocks), dim3(256), 0, s, sph.count, cap, nodes,
                        reinterpret_cast<WideNode *>(mem + L.wide));

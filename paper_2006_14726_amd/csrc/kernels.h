@@ -19,7 +19,7 @@ struct TraceArgs {
     int32_t kbuf;
     int32_t tile_w, tile_h;
     int32_t schedule;           // tile -> XCD assignment (0 super-tiles, 1 bands)
-    int32_t walk;               // SPLAT_WALK_LANE or SPLAT_WALK_PACKET
+    int32_t walk;               // SPLAT_WALK_LANE, SPLAT_WALK_PACKET or SPLAT_WALK_FRUSTUM
     const uint32_t *order;      // schedule 2: item of each block, heaviest first (else NULL): tile << 3 | part
     uint32_t order_items;       // schedule 2: items of the order
     float4 *out;                // forward output
@@ -27,6 +27,7 @@ struct TraceArgs {
     // backward only
     const float4 *grad;         // dL/d out
     float *d_rgb, *d_alpha, *d_radius, *d_centre;
+    const float4 *axis;         // spheroid sets: (u, h) per sample; NULL for spheres
 };
 
 hipError_t launch_raymarch(const float *vol, int32_t n, double lo, double size, const Cam &cam,

@@ -152,7 +152,9 @@ struct TileRegion {
 
 // Traces the pixels of one region of a tile; the frustum walk falls back to
 // the per-lane walk for a region whose candidate lists overflow.
-template <int K, bool BWD, int WALK>
+// SPH: the set is a spheroid set (an axis per sample); its kernels are
+// compiled apart, so that the sphere kernels carry none of its code.
+template <int K, bool BWD, int WALK, bool SPH = false>
 __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ nodes, const BvhHeader *__restrict__ hdr,
                            int tile_x, int tile_y, WaveLds<WALK == SPLAT_WALK_FRUSTUM> &L, TileRegion rg)
 {
@@ -214,7 +216,7 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
     // test; a 1/d beyond 2^40 could overflow the slab products, so such a
     // wave keeps the general test
     uint32_t sign_pattern = kMixedSigns;
-    if (WALK == SPLAT_WALK_LANE && K <= 8) {
+    if (WALK == SPLAT_WALK_LANE && K <= 8 && !SPH) {
         const bool part = inside && n_spheres > 0;
         uint32_t neg = 0, pos = 0;
         bool tame = true;
@@ -328,7 +330,7 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
                     const float bx = fmaf(pp[pl][0], q3, fmaf(pn[pl][0], q0, pc[pl]));
                     const float vb = fmaf(pp[pl][2], q5, fmaf(pn[pl][2], q2, fmaf(pp[pl][1], q4, fmaf(pn[pl][1], q1, bx))));
                     const float vs = fmaf(pp[pl][0] + pn[pl][0], q0, fmaf(pp[pl][1] + pn[pl][1], q1,
-                                     fmaf(pp[pl][2] + pn[pl][2], q2, pc[pl]))) + q3;
+                                     fmaf(pp[pl][2] + pn[pl][2], q2, pc[pl]))) + (SPH ? fmaxf(q3, q5) : q3);
                     pass = pass && (is_leaf ? vs : vb) >= -slack;
                 }
                 const uint64_t mi = __ballot(pass && is_int), ml = __ballot(pass && is_leaf);
@@ -344,17 +346,19 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
                     const float y = ox * bU[0] + oy * bU[1] + oz * bU[2];
                     const float z = ox * bF[0] + oy * bF[1] + oz * bF[2];
                     const float dist = sqrtf(ox * ox + oy * oy + oz * oz);
-                    const float zr = z - q3;
+                    // a spheroid by its bounding ball: radius h (word 5), entry up to dist + h
+                    const float rb = SPH ? fmaxf(q3, q5) : q3;
+                    const float zr = z - rb;
                     float X = 0.0f, Y = 0.0f, rho2 = INFINITY;
                     if (zr > 0x1p-10f * dist) {
                         X = x / z;
                         Y = y / z;
-                        const float rho = q3 * sqrtf(1.0f + X * X + Y * Y) / zr;
+                        const float rho = rb * sqrtf(1.0f + X * X + Y * Y) / zr;
                         const float rs = rho * (1.0f + 0x1p-12f) + 0x1p-18f * (1.0f + fabsf(X) + fabsf(Y));
                         rho2 = rs * rs;
                     }
-                    const float tmin = (dist - q3) * (1.0f - 0x1p-20f) - slack;
-                    const float tmax = dist * (1.0f + 0x1p-20f) + slack;
+                    const float tmin = (dist - rb) * (1.0f - 0x1p-20f) - slack;
+                    const float tmax = (SPH ? dist + q5 : dist) * (1.0f + 0x1p-20f) + slack;
                     L.fr.disc[n_cand + below_l] = make_float4(X, Y, rho2, tmin);
                     L.fr.far_ref[n_cand + below_l] = make_float2(tmax, __uint_as_float((node << 2) | sl));
                 }
@@ -408,7 +412,7 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
             for (uint32_t j0 = 0; j0 < (uint32_t)kQueue; j0 += kFlushGroup) {
               if (!__ballot(j0 < nc)) break;
               float2 p01[kFlushGroup], p23[kFlushGroup];
-              float pa[kFlushGroup];
+              float pa[kFlushGroup], ph[kFlushGroup];
               uint32_t pid[kFlushGroup];
 #pragma unroll
               for (int u = 0; u < kFlushGroup; ++u) {
@@ -417,6 +421,7 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
                   p01[u] = *reinterpret_cast<const float2 *>(s);
                   p23[u] = *reinterpret_cast<const float2 *>(s + 2);
                   pa[u] = s[4];
+                  if constexpr (SPH) ph[u] = s[5];
                   pid[u] = __float_as_uint(nodes[e >> 2].f[24 + (e & 3u)]) & ~kLeafBit;
               }
 #pragma unroll
@@ -428,13 +433,38 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
                 if (id >= n_spheres) continue;
                 const double oc0 = (double)s01.x - eye.o[0], oc1 = (double)s01.y - eye.o[1],
                              oc2 = (double)s23.x - eye.o[2];
+                const double r = (double)s23.y;
                 const double b = oc0 * ray.d[0] + oc1 * ray.d[1] + oc2 * ray.d[2];
                 const double v0 = oc0 - b * ray.d[0], v1 = oc1 - b * ray.d[1], v2 = oc2 - b * ray.d[2];
                 const double q = v0 * v0 + v1 * v1 + v2 * v2;
-                const double r = (double)s23.y;
-                const double disc = r * r - q;
+                double disc = r * r - q, tc = b;
+                if constexpr (SPH) {
+                    if (ph[u] > 0.0f) {
+                        // spheroid (axis u scaled to unit length, half-length h
+                        // along it, r across): S y = y / r + (y.u)(1/h - 1/r) u maps
+                        // it to the unit ball and the ray to t D - L, D = S d,
+                        // L = S (c - o); then the robust sphere form: t_m = L.D / D.D,
+                        // w = L - t_m D, t0 = t_m - sqrt((1 - w.w) / D.D)
+                        const float4 ua = a.axis[id];
+                        const double ul = sqrt((double)ua.x * ua.x + (double)ua.y * ua.y + (double)ua.z * ua.z);
+                        const double u0 = ua.x / ul, u1 = ua.y / ul, u2 = ua.z / ul;
+                        const double w = 1.0 / (double)ph[u] - 1.0 / r;
+                        const double du = ray.d[0] * u0 + ray.d[1] * u1 + ray.d[2] * u2;
+                        const double ou = oc0 * u0 + oc1 * u1 + oc2 * u2;
+                        const double D0 = ray.d[0] / r + du * w * u0, D1 = ray.d[1] / r + du * w * u1,
+                                     D2 = ray.d[2] / r + du * w * u2;
+                        const double L0 = oc0 / r + ou * w * u0, L1 = oc1 / r + ou * w * u1,
+                                     L2 = oc2 / r + ou * w * u2;
+                        const double DD = D0 * D0 + D1 * D1 + D2 * D2;
+                        const double tm = (L0 * D0 + L1 * D1 + L2 * D2) / DD;
+                        const double w0 = L0 - tm * D0, w1 = L1 - tm * D1, w2 = L2 - tm * D2;
+                        const double ds = 1.0 - (w0 * w0 + w1 * w1 + w2 * w2);
+                        disc = ds < 0.0 ? ds : ds / DD;
+                        tc = tm;
+                    }
+                }
                 if (disc < 0.0) continue;
-                const double t0 = b - sqrt(disc);
+                const double t0 = tc - sqrt(disc);
                 if (!(t0 > 0.0)) continue;
                 if (!key_less(lo_t, lo_id, t0, id)) continue;
                 if (!key_less(t0, id, pr_t, pr_id)) continue;
@@ -496,7 +526,6 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
                 }
             }
         };
-
         // Leaf slots of a node: float prefilter, certain misses only (the ray
         // passes farther than r + E from the centre, or the sphere lies wholly
         // beyond the prune key or before the last composited key: t0 lies in
@@ -512,8 +541,11 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
                 const float bf = ox * ray.df[0] + oy * ray.df[1] + oz * ray.df[2];
                 const float vx = ox - bf * ray.df[0], vy = oy - bf * ray.df[1], vz = oz - bf * ray.df[2];
                 const float qf = vx * vx + vy * vy + vz * vz;
-                const float rE = s[3] + eye.E;
-                const bool may = (qf <= rE * rE) & (bf - rE <= pf) & (bf + eye.E >= lo_f);
+                // a spheroid (word 5: its half-length h, which is at least r) lies
+                // in the ball of radius h around its centre, and its entry in
+                // [b - h, b + h]; a sphere's (word 5: 0) in [b - r, b]
+                const float rE = (SPH ? fmaxf(s[3], s[5]) : s[3]) + eye.E;
+                const bool may = (qf <= rE * rE) & (bf - rE <= pf) & ((SPH ? bf + s[5] : bf) + eye.E >= lo_f);
                 // nc < kQueue here: the queue is flushed once a lane could overflow
                 L.cand[nc][lane] = (node << 2) | (uint32_t)side;
                 nc += may ? 1u : 0u;
@@ -699,8 +731,9 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
                 lane_walk(SignTag<kMixedSigns>{});
                 redo = overflow;
             }
-        } else if constexpr (LANE && K > 8) {
-            // a large buffer leaves no registers for copies of the walk
+        } else if constexpr (LANE && (K > 8 || SPH)) {
+            // a large buffer leaves no registers for copies of the walk (and a
+            // spheroid set keeps to the general one)
             lane_walk(SignTag<kMixedSigns>{});
             redo = overflow;
         } else if (LANE) {
@@ -906,7 +939,7 @@ __host__ inline uint32_t blocks_for(int tiles_x, int tiles_y, int schedule)
     return (uint32_t)(((s + 7) / 8) * 8 * 64);
 }
 
-template <int K, bool BWD, int WALK>
+template <int K, bool BWD, int WALK, bool SPH>
 __global__ void __launch_bounds__(64) k_trace(TraceArgs a, int tiles_x, int tiles_y)
 {
     __shared__ WaveLds<WALK == SPLAT_WALK_FRUSTUM> lds;
@@ -934,7 +967,7 @@ __global__ void __launch_bounds__(64) k_trace(TraceArgs a, int tiles_x, int tile
     const BvhLayout L(a.layout_cap);
     const BvhHeader *hdr = reinterpret_cast<const BvhHeader *>(mem);
     const WideNode *nodes = reinterpret_cast<const WideNode *>(mem + L.wide);
-    trace_tile<K, BWD, WALK>(a, nodes, hdr, tx, ty, lds, rg);
+    trace_tile<K, BWD, WALK, SPH>(a, nodes, hdr, tx, ty, lds, rg);
 }
 
 // Persistent batched trace: waves pull tiles from one atomic counter until
@@ -967,6 +1000,7 @@ k_trace_batched(const splat_batch_job *__restrict__ jobs, const uint32_t *__rest
         a.layout_cap = j.bvh_capacity;
         const BvhLayout L(a.layout_cap);
         a.centre_radius = reinterpret_cast<const float4 *>(j.centre_radius);
+        a.axis = nullptr;
         a.rgba = j.rgba;
         a.half = j.rgba_dtype == SPLAT_F16;
         for (int k = 0; k < 3; ++k) {
@@ -1008,16 +1042,16 @@ __global__ void k_zero_counter(uint32_t *c)
     if (threadIdx.x == 0) *c = 0u;
 }
 
-template <bool BWD, int WALK>
+template <bool BWD, int WALK, bool SPH = false>
 static hipError_t launch_k(const TraceArgs &a, int K, dim3 grid, int tiles_x, int tiles_y, hipStream_t s)
 {
     switch (K) {
-    case 1: hipLaunchKernelGGL((k_trace<1, BWD, WALK>), grid, dim3(64), 0, s, a, tiles_x, tiles_y); break;
-    case 2: hipLaunchKernelGGL((k_trace<2, BWD, WALK>), grid, dim3(64), 0, s, a, tiles_x, tiles_y); break;
-    case 4: hipLaunchKernelGGL((k_trace<4, BWD, WALK>), grid, dim3(64), 0, s, a, tiles_x, tiles_y); break;
-    case 6: hipLaunchKernelGGL((k_trace<6, BWD, WALK>), grid, dim3(64), 0, s, a, tiles_x, tiles_y); break;
-    case 8: hipLaunchKernelGGL((k_trace<8, BWD, WALK>), grid, dim3(64), 0, s, a, tiles_x, tiles_y); break;
-    case 16: hipLaunchKernelGGL((k_trace<16, BWD, WALK>), grid, dim3(64), 0, s, a, tiles_x, tiles_y); break;
+    case 1: hipLaunchKernelGGL((k_trace<1, BWD, WALK, SPH>), grid, dim3(64), 0, s, a, tiles_x, tiles_y); break;
+    case 2: hipLaunchKernelGGL((k_trace<2, BWD, WALK, SPH>), grid, dim3(64), 0, s, a, tiles_x, tiles_y); break;
+    case 4: hipLaunchKernelGGL((k_trace<4, BWD, WALK, SPH>), grid, dim3(64), 0, s, a, tiles_x, tiles_y); break;
+    case 6: hipLaunchKernelGGL((k_trace<6, BWD, WALK, SPH>), grid, dim3(64), 0, s, a, tiles_x, tiles_y); break;
+    case 8: hipLaunchKernelGGL((k_trace<8, BWD, WALK, SPH>), grid, dim3(64), 0, s, a, tiles_x, tiles_y); break;
+    case 16: hipLaunchKernelGGL((k_trace<16, BWD, WALK, SPH>), grid, dim3(64), 0, s, a, tiles_x, tiles_y); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1045,7 +1079,16 @@ hipError_t launch_trace(const TraceArgs &args, bool backward, void *ws, hipStrea
         if (e != hipSuccess) return e;
     }
     hipError_t e;
-    if (a.walk == SPLAT_WALK_PACKET)
+    if (a.axis) {
+        // spheroid sets: forward only (the API refuses their backward)
+        if (backward) return hipErrorInvalidValue;
+        if (a.walk == SPLAT_WALK_PACKET)
+            e = launch_k<false, SPLAT_WALK_PACKET, true>(a, a.kbuf, grid, tiles_x, tiles_y, s);
+        else if (a.walk == SPLAT_WALK_FRUSTUM)
+            e = launch_k<false, SPLAT_WALK_FRUSTUM, true>(a, a.kbuf, grid, tiles_x, tiles_y, s);
+        else
+            e = launch_k<false, SPLAT_WALK_LANE, true>(a, a.kbuf, grid, tiles_x, tiles_y, s);
+    } else if (a.walk == SPLAT_WALK_PACKET)
         e = backward ? launch_k<true, SPLAT_WALK_PACKET>(a, a.kbuf, grid, tiles_x, tiles_y, s)
                      : launch_k<false, SPLAT_WALK_PACKET>(a, a.kbuf, grid, tiles_x, tiles_y, s);
     else if (a.walk == SPLAT_WALK_FRUSTUM)

@@ -73,14 +73,17 @@ __global__ void __launch_bounds__(1024) k_unproject_scan(uint32_t *__restrict__ 
     if (threadIdx.x == 1023) *count = part[1023];
 }
 
-// MODE: SPLAT_RADIUS_FOOTPRINT, SPLAT_RADIUS_OPACITY or SPLAT_RADIUS_INTERVAL
+// MODE: SPLAT_RADIUS_FOOTPRINT, SPLAT_RADIUS_OPACITY, SPLAT_RADIUS_INTERVAL or
+// SPLAT_RADIUS_SPHEROID (the interval's sample smeared along its ray: axis the
+// unit pixel ray, half-length max(r, kappa half-interval), r the footprint)
 template <bool HALF, int MODE>
 __global__ void __launch_bounds__(kUnprojBlock)
 k_unproject_write(Cam cam, const float *__restrict__ rgba, const float *__restrict__ depth,
                   const float *__restrict__ interval, int64_t pixels, double radius_scale, double a_floor,
                   double kappa, const uint32_t *__restrict__ tile_offsets, float4 *__restrict__ centre_radius,
-                  void *__restrict__ colour, uint32_t *__restrict__ src_index)
+                  void *__restrict__ colour, uint32_t *__restrict__ src_index, float4 *__restrict__ axis)
 {
+    constexpr bool ITV = MODE == SPLAT_RADIUS_INTERVAL || MODE == SPLAT_RADIUS_SPHEROID;
     __shared__ uint32_t wcount[kUnprojItems][kUnprojBlock / kWave];
     const int64_t base = (int64_t)blockIdx.x * kUnprojTile;
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
@@ -89,7 +92,7 @@ k_unproject_write(Cam cam, const float *__restrict__ rgba, const float *__restri
 #pragma unroll
     for (int i = 0; i < kUnprojItems; ++i) {
         const int64_t p = base + i * kUnprojBlock + threadIdx.x;
-        valid[i] = p < pixels && pixel_valid(rgba, depth, MODE == SPLAT_RADIUS_INTERVAL ? interval : nullptr, p);
+        valid[i] = p < pixels && pixel_valid(rgba, depth, ITV ? interval : nullptr, p);
         const uint64_t m = __ballot(valid[i]);
         rank_in_wave[i] = (uint32_t)__popcll(m & ((1ull << lane) - 1));
         if (lane == 0) wcount[i][wave] = (uint32_t)__popcll(m);
@@ -109,8 +112,8 @@ k_unproject_write(Cam cam, const float *__restrict__ rgba, const float *__restri
         double d[3];
         pixel_ray(cam, x, y, d);
         double t = (double)depth[p], half_len = 0.0;
-        if (MODE == SPLAT_RADIUS_INTERVAL) {
-            // the interval's midpoint replaces the depth; the sphere covers kappa times its half length
+        if (ITV) {
+            // the interval's midpoint replaces the depth; the sample covers kappa times its half length
             const float2 iv = reinterpret_cast<const float2 *>(interval)[p];
             t = 0.5 * ((double)iv.x + (double)iv.y);
             half_len = 0.5 * ((double)iv.y - (double)iv.x);
@@ -129,6 +132,10 @@ k_unproject_write(Cam cam, const float *__restrict__ rgba, const float *__restri
         if (MODE == SPLAT_RADIUS_INTERVAL && kappa * half_len > r) r = kappa * half_len;
         cr.w = (float)r;
         centre_radius[j] = cr;
+        if (MODE == SPLAT_RADIUS_SPHEROID) {
+            const double h = kappa * half_len > r ? kappa * half_len : r;
+            axis[j] = make_float4((float)d[0], (float)d[1], (float)d[2], (float)h);
+        }
         const double A = (double)src.w;
         double k[3] = {(double)src.x / A, (double)src.y / A, (double)src.z / A};
 #pragma unroll
@@ -162,11 +169,11 @@ static void launch_write(const Cam &cam, const float *rgba, const float *depth, 
     if (out.rgba_dtype == SPLAT_F16)
         hipLaunchKernelGGL((k_unproject_write<true, MODE>), dim3(tiles), dim3(kUnprojBlock), 0, s, cam, rgba, depth,
                            interval, pixels, rs, fl, ka, tile_counts, reinterpret_cast<float4 *>(out.centre_radius),
-                           out.rgba, out.src_index);
+                           out.rgba, out.src_index, reinterpret_cast<float4 *>(out.axis));
     else
         hipLaunchKernelGGL((k_unproject_write<false, MODE>), dim3(tiles), dim3(kUnprojBlock), 0, s, cam, rgba, depth,
                            interval, pixels, rs, fl, ka, tile_counts, reinterpret_cast<float4 *>(out.centre_radius),
-                           out.rgba, out.src_index);
+                           out.rgba, out.src_index, reinterpret_cast<float4 *>(out.axis));
 }
 
 hipError_t launch_unproject(const Cam &cam, const float *rgba, const float *depth, const float *interval,
@@ -175,7 +182,8 @@ hipError_t launch_unproject(const Cam &cam, const float *rgba, const float *dept
     const int64_t pixels = (int64_t)cam.w * cam.h;
     const uint32_t tiles = (uint32_t)((pixels + kUnprojTile - 1) / kUnprojTile);
     uint32_t *tile_counts = static_cast<uint32_t *>(ws);
-    const float *itv = policy.mode == SPLAT_RADIUS_INTERVAL ? interval : nullptr;
+    const float *itv =
+        policy.mode == SPLAT_RADIUS_INTERVAL || policy.mode == SPLAT_RADIUS_SPHEROID ? interval : nullptr;
     hipLaunchKernelGGL(k_unproject_count, dim3(tiles), dim3(kUnprojBlock), 0, s, rgba, depth, itv, pixels,
                        tile_counts);
     hipLaunchKernelGGL(k_unproject_scan, dim3(1), dim3(1024), 0, s, tile_counts, tiles, out.count);
@@ -185,6 +193,9 @@ hipError_t launch_unproject(const Cam &cam, const float *rgba, const float *dept
         break;
     case SPLAT_RADIUS_INTERVAL:
         launch_write<SPLAT_RADIUS_INTERVAL>(cam, rgba, depth, itv, pixels, tiles, policy, tile_counts, out, s);
+        break;
+    case SPLAT_RADIUS_SPHEROID:
+        launch_write<SPLAT_RADIUS_SPHEROID>(cam, rgba, depth, itv, pixels, tiles, policy, tile_counts, out, s);
         break;
     default:
         launch_write<SPLAT_RADIUS_FOOTPRINT>(cam, rgba, depth, itv, pixels, tiles, policy, tile_counts, out, s);

@@ -70,6 +70,7 @@ class Spheres:
     rgba: torch.Tensor                     # float16 or float32 [cap, 4], straight colour + alpha
     count: torch.Tensor                    # int32 [1] on the device
     src_index: torch.Tensor | None = None  # int32 [cap]
+    axis: torch.Tensor | None = None       # float32 [cap, 4]: spheroids' unit axis and half-length (None: spheres)
 
     @property
     def capacity(self) -> int:
@@ -87,6 +88,7 @@ class Spheres:
         s.src_index = None if self.src_index is None else self.src_index.data_ptr()
         s.count = self.count.data_ptr()
         s.capacity = self.capacity
+        s.axis = None if self.axis is None else self.axis.data_ptr()
         return s
 
     def n(self) -> int:
@@ -94,8 +96,8 @@ class Spheres:
         return int(self.count.item())
 
 
-def spheres_from_tensors(centre_radius: torch.Tensor, rgba: torch.Tensor) -> Spheres:
-    """Wrap existing [N, 4] tensors as a sphere set of N spheres."""
+def spheres_from_tensors(centre_radius: torch.Tensor, rgba: torch.Tensor, axis: torch.Tensor | None = None) -> Spheres:
+    """Wrap existing [N, 4] tensors as a sphere set of N spheres (or of N spheroids with `axis` [N, 4])."""
     _require_cuda(centre_radius, "centre_radius", torch.float32)
     _require_cuda(rgba, "rgba")
     if rgba.dtype not in (torch.float16, torch.float32):
@@ -103,15 +105,20 @@ def spheres_from_tensors(centre_radius: torch.Tensor, rgba: torch.Tensor) -> Sph
     n = centre_radius.shape[0]
     if centre_radius.shape != (n, 4) or rgba.shape != (n, 4) or n == 0:
         raise ValueError("centre_radius and rgba must both be [N, 4] with N >= 1")
+    if axis is not None:
+        _require_cuda(axis, "axis", torch.float32)
+        if axis.shape != (n, 4):
+            raise ValueError("axis must be [N, 4]")
     count = torch.full((1,), n, dtype=torch.int32, device=centre_radius.device)
-    return Spheres(centre_radius, rgba, count)
+    return Spheres(centre_radius, rgba, count, axis=axis)
 
 
-def alloc_spheres(capacity: int, device, half: bool = True) -> Spheres:
+def alloc_spheres(capacity: int, device, half: bool = True, spheroids: bool = False) -> Spheres:
     return Spheres(torch.empty((capacity, 4), dtype=torch.float32, device=device),
                    torch.empty((capacity, 4), dtype=torch.float16 if half else torch.float32, device=device),
                    torch.zeros((1,), dtype=torch.int32, device=device),
-                   torch.empty((capacity,), dtype=torch.int32, device=device))
+                   torch.empty((capacity,), dtype=torch.int32, device=device),
+                   torch.empty((capacity, 4), dtype=torch.float32, device=device) if spheroids else None)
 
 
 def raymarch(volume: torch.Tensor, box_lo: float, box_size: float, cam, step: float = 0.5,
@@ -244,8 +251,10 @@ def unproject_policy(src_cam, rgba: torch.Tensor, depth: torch.Tensor, mode: int
                      opacity_floor: float = 0.05, interval_scale: float = 1.0, interval: torch.Tensor | None = None,
                      half: bool = True, out: Spheres | None = None, ws: torch.Tensor | None = None) -> Spheres:
     """Unprojection with a radius policy (splat_unproject_policy): SPLAT_RADIUS_FOOTPRINT, _OPACITY
-    (r = s fp sqrt(max(A, floor))) or _INTERVAL (centre at the depth interval's midpoint,
-    r = max(s fp, interval_scale half-length); needs `interval` [H, W, 2] from `raymarch`)."""
+    (r = s fp sqrt(max(A, floor))), _INTERVAL (centre at the depth interval's midpoint,
+    r = max(s fp, interval_scale half-length)) or _SPHEROID (the same centre, smeared along the ray:
+    r = s fp, axis the pixel ray, half-length max(r, interval_scale half-length)); the last two need
+    `interval` [H, W, 2] from `raymarch`, and _SPHEROID an output set with axes."""
     H, W = int(src_cam.height), int(src_cam.width)
     _require_cuda(rgba, "rgba", torch.float32)
     _require_cuda(depth, "depth", torch.float32)
@@ -256,7 +265,7 @@ def unproject_policy(src_cam, rgba: torch.Tensor, depth: torch.Tensor, mode: int
         if tuple(interval.shape) != (H, W, 2):
             raise ValueError(f"interval must be [{H}, {W}, 2]")
     if out is None:
-        out = alloc_spheres(H * W, rgba.device, half)
+        out = alloc_spheres(H * W, rgba.device, half, spheroids=int(mode) == _lib.SPLAT_RADIUS_SPHEROID)
     lib = _lib.load()
     ws = _own_ws(ws, lib.splat_workspace_bytes(_lib.SPLAT_OP_UNPROJECT, 0, W, H), rgba.device, "unproject")
     pol = _lib.splat_radius_policy()

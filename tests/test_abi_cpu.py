@@ -27,7 +27,7 @@ def test_library_exports_every_declared_symbol():
     lib = _lib.load()
     for name in declared_functions():
         assert hasattr(lib, name), name
-    assert lib.splat_version() == 105
+    assert lib.splat_version() == 106
 
 
 def test_sizes_are_pure_host_functions():
@@ -47,7 +47,7 @@ def test_sizes_are_pure_host_functions():
 
 def test_struct_layouts_match_the_header():
     assert ctypes.sizeof(_lib.splat_camera) == 13 * 8 + 2 * 4
-    assert ctypes.sizeof(_lib.splat_spheres) == 8 + 8 + 4 + 4 + 8 + 8 + 8
+    assert ctypes.sizeof(_lib.splat_spheres) == 8 + 8 + 4 + 4 + 8 + 8 + 8 + 8  # capacity padded, then axis
     assert ctypes.sizeof(_lib.splat_trace_opts) == 56
     assert ctypes.sizeof(_lib.splat_volume) == 32
     assert ctypes.sizeof(_lib.splat_march_opts) == 48
@@ -267,7 +267,15 @@ def test_unproject_policy_validation():
                                                ctypes.byref(p) if pol else None, ctypes.byref(sph), fake, need, None))
 
     assert call(pol=False)[0] == _lib.SPLAT_EINVAL
-    assert call(mode=3)[0] == _lib.SPLAT_EUNSUPPORTED
+    assert call(mode=4)[0] == _lib.SPLAT_EUNSUPPORTED
+    # the spheroid policy needs an output set with axes, and the interval
+    code, msg = call(mode=_lib.SPLAT_RADIUS_SPHEROID)
+    assert code == _lib.SPLAT_EINVAL and "axis" in msg
+    sph.axis = 4096
+    assert call(mode=_lib.SPLAT_RADIUS_SPHEROID, interval=None)[0] == _lib.SPLAT_EINVAL
+    if not torch.cuda.is_available():
+        assert call(mode=_lib.SPLAT_RADIUS_SPHEROID)[0] == _lib.SPLAT_ENODEV
+    sph.axis = None
     assert call(scale=-1.0)[0] == _lib.SPLAT_EINVAL
     assert call(mode=_lib.SPLAT_RADIUS_OPACITY, floor=0.0)[0] == _lib.SPLAT_EINVAL
     assert call(mode=_lib.SPLAT_RADIUS_OPACITY, floor=1.5)[0] == _lib.SPLAT_EINVAL
@@ -278,6 +286,35 @@ def test_unproject_policy_validation():
             assert call(mode=mode)[0] == _lib.SPLAT_ENODEV
         # the footprint and opacity policies do not need the interval
         assert call(mode=_lib.SPLAT_RADIUS_OPACITY, interval=None)[0] == _lib.SPLAT_ENODEV
+
+
+def test_spheroid_sets_are_refused_where_unsupported():
+    """Spheroid sets (axis set) trace with constant alpha only; the backward, the codec and the accumulation take
+    sphere sets.  All refused on the host."""
+    lib = _lib.load()
+    cam = _lib.camera_struct(_Cam())
+    sph = _fake_set(1 << 30, cap=64)
+    sph.axis = 4096
+    bvh = _lib.splat_bvh()
+    bvh.mem, bvh.capacity = 256 * 64, 64
+    fake = ctypes.c_void_p(4096)
+    o = _lib.splat_trace_opts()
+    o.alpha_stop, o.t_max, o.mode = 0.99, math.inf, _lib.SPLAT_ALPHA_SOFT
+    code, msg = _err(lib.splat_trace(ctypes.byref(bvh), ctypes.byref(sph), ctypes.byref(cam), ctypes.byref(o), fake,
+                                     None, None, 0, None))
+    assert code == _lib.SPLAT_EUNSUPPORTED and "constant alpha" in msg
+    o.mode = _lib.SPLAT_ALPHA_CONSTANT
+    g = _lib.splat_grads()
+    g.d_rgb = g.d_alpha = g.d_radius = g.d_centre = 4096
+    code, msg = _err(lib.splat_trace_backward(ctypes.byref(bvh), ctypes.byref(sph), ctypes.byref(cam), ctypes.byref(o),
+                                              fake, fake, ctypes.byref(g), None, 0, None))
+    assert code == _lib.SPLAT_EUNSUPPORTED and "sphere sets" in msg
+    c = _lib.splat_codec()
+    c.box_size, c.r_unit = 1.0, 1e-3
+    assert _err(lib.splat_encode_samples(ctypes.byref(sph), ctypes.byref(c), fake, fake, None))[0] == \
+        _lib.SPLAT_EUNSUPPORTED
+    assert _err(lib.splat_decode_samples(fake, fake, fake, ctypes.byref(c), ctypes.byref(sph), None))[0] == \
+        _lib.SPLAT_EUNSUPPORTED
 
 
 def test_gradient_buffers_clear_in_one_fill():
