@@ -98,15 +98,29 @@ constexpr uint32_t kLaneStack = 16;  // per-lane walk: stack entries per lane (a
 
 constexpr uint32_t kFront = 128;  // frustum walk: nodes of one level of the breadth-first walk
 constexpr uint32_t kTileCand = 256;  // frustum walk: candidate spheres of one tile
+// spheroid sets: their long boxes overlap more, so their lists are longer
+constexpr uint32_t kFrontS = 384;
+constexpr uint32_t kTileCandS = 384;
 
 // Frustum walk: the two levels of the breadth-first walk, and per candidate
 // sphere of the tile its screen disc (centre X, Y and squared radius in the
 // tangent units of the pixel grid), its depth range [tmin, tmax] along any
 // ray of the tile, and its slot, (wide node index << 2) | slot.
+// A spheroid set stores per candidate the screen capsule instead: the disc's
+// centre is one end of the capsule's screen segment, and seg holds the
+// segment (dX, dY) to the other end.
+template <bool SPH>
 struct FrustumLds {
     uint32_t front[2][kFront];
     float4 disc[kTileCand];   // X, Y, rho^2, tmin
     float2 far_ref[kTileCand];  // tmax, slot (bits)
+};
+template <>
+struct FrustumLds<true> {
+    uint32_t front[2][kFrontS];
+    float4 disc[kTileCandS];
+    float2 far_ref[kTileCandS];
+    float2 seg[kTileCandS];   // dX, dY
 };
 
 // LDS of one wave: the leaf candidates awaiting the exact test (a column per
@@ -114,18 +128,18 @@ struct FrustumLds {
 // per-lane stacks are only used by a frustum-walk tile that fell back to the
 // per-lane walk, when its lists are no longer needed, so the two share
 // memory.  The other walks do without the lists (their waves fit more per CU).
-template <bool FR>
+template <bool FR, bool SPH = false>
 struct WaveLds {
     uint32_t cand[kQueue][kWave];            // (wide node index << 2) | slot
     uint32_t lstack[kLaneStack][kWave];      // per-lane walk: a stack per lane
     uint32_t stack[kStack];                  // packet walk: one stack per wave
 };
-template <>
-struct WaveLds<true> {
+template <bool SPH>
+struct WaveLds<true, SPH> {
     uint32_t cand[kQueue][kWave];
     union {
         uint32_t lstack[kLaneStack][kWave];
-        FrustumLds fr;
+        FrustumLds<SPH> fr;
     };
     uint32_t stack[kStack];
 };
@@ -156,7 +170,7 @@ struct TileRegion {
 // compiled apart, so that the sphere kernels carry none of its code.
 template <int K, bool BWD, int WALK, bool SPH = false>
 __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ nodes, const BvhHeader *__restrict__ hdr,
-                           int tile_x, int tile_y, WaveLds<WALK == SPLAT_WALK_FRUSTUM> &L, TileRegion rg)
+                           int tile_x, int tile_y, WaveLds<WALK == SPLAT_WALK_FRUSTUM, SPH> &L, TileRegion rg)
 {
     constexpr bool FRUSTUM = WALK == SPLAT_WALK_FRUSTUM;
     constexpr bool LANE = WALK == SPLAT_WALK_LANE || FRUSTUM;
@@ -301,6 +315,7 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
         const float bU[3] = {(float)a.cam.up[0], (float)a.cam.up[1], (float)a.cam.up[2]};
         const float bF[3] = {(float)a.cam.fwd[0], (float)a.cam.fwd[1], (float)a.cam.fwd[2]};
         const bool any = __ballot(active) != 0;
+        constexpr uint32_t kFr = SPH ? kFrontS : kFront, kTc = SPH ? kTileCandS : kTileCand;
         uint32_t cur = 0, n_front = any ? 1u : 0u;
         if (lane == 0) L.fr.front[0][0] = 0u;  // the root
         fb = false;
@@ -333,11 +348,40 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
                                      fmaf(pp[pl][2] + pn[pl][2], q2, pc[pl]))) + (SPH ? fmaxf(q3, q5) : q3);
                     pass = pass && (is_leaf ? vs : vb) >= -slack;
                 }
+                // a spheroid with h > r lies in the capsule of radius r around
+                // the segment c +- (h - r) u (at a distance x from c along u
+                // its half-width r sqrt(1 - x^2 / h^2) stays within the
+                // capsule's); the capsule meets the half-space of a plane with
+                // unit normal n when n.c + (h - r)|n.u| + r does, with margins
+                // for the float axis and end points
+                float u0 = 0.0f, u1 = 0.0f, u2 = 0.0f, ha = 0.0f;
+                if constexpr (SPH) {
+                    const uint32_t id = ref & ~kLeafBit;
+                    // an id beyond the set is never tested (the exact test skips it)
+                    if (pass && is_leaf && id >= n_spheres) pass = false;
+                    if (pass && is_leaf && q5 > q3) {
+                        const float4 ua = a.axis[id];
+                        const float il = rsqrtf(fmaf(ua.x, ua.x, fmaf(ua.y, ua.y, ua.z * ua.z)));
+                        u0 = ua.x * il;
+                        u1 = ua.y * il;
+                        u2 = ua.z * il;
+                        ha = q5 - q3;
+                        const float rr = q3 + eye.E + ha * 0x1p-20f;
+#pragma unroll
+                        for (int pl = 0; pl < 4; ++pl) {
+                            const float n0 = pp[pl][0] + pn[pl][0], n1 = pp[pl][1] + pn[pl][1],
+                                        n2 = pp[pl][2] + pn[pl][2];
+                            const float sc = fmaf(n0, q0, fmaf(n1, q1, fmaf(n2, q2, pc[pl])));
+                            const float nu = fabsf(fmaf(n0, u0, fmaf(n1, u1, n2 * u2)));
+                            pass = pass && fmaf(ha, nu, sc + rr) >= -slack;
+                        }
+                    }
+                }
                 const uint64_t mi = __ballot(pass && is_int), ml = __ballot(pass && is_leaf);
                 const uint32_t below_i = (uint32_t)__popcll(mi & ((1ull << lane) - 1ull));
                 const uint32_t below_l = (uint32_t)__popcll(ml & ((1ull << lane) - 1ull));
-                if (pass && is_int && n_next + below_i < kFront) L.fr.front[cur ^ 1u][n_next + below_i] = ref;
-                if (pass && is_leaf && n_cand + below_l < kTileCand) {
+                if (pass && is_int && n_next + below_i < kFr) L.fr.front[cur ^ 1u][n_next + below_i] = ref;
+                if (pass && is_leaf && n_cand + below_l < kTc) {
                     // the candidate's screen disc and depth range, in float with
                     // outward slack (relative 2^-12 on rho, 2^-18 absolute in tangent
                     // units, 2^-20 relative on depths plus the margin)
@@ -346,26 +390,66 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
                     const float y = ox * bU[0] + oy * bU[1] + oz * bU[2];
                     const float z = ox * bF[0] + oy * bF[1] + oz * bF[2];
                     const float dist = sqrtf(ox * ox + oy * oy + oz * oz);
-                    // a spheroid by its bounding ball: radius h (word 5), entry up to dist + h
-                    const float rb = SPH ? fmaxf(q3, q5) : q3;
-                    const float zr = z - rb;
-                    float X = 0.0f, Y = 0.0f, rho2 = INFINITY;
-                    if (zr > 0x1p-10f * dist) {
-                        X = x / z;
-                        Y = y / z;
-                        const float rho = rb * sqrtf(1.0f + X * X + Y * Y) / zr;
-                        const float rs = rho * (1.0f + 0x1p-12f) + 0x1p-18f * (1.0f + fabsf(X) + fabsf(Y));
-                        rho2 = rs * rs;
+                    if constexpr (!SPH) {
+                        const float zr = z - q3;
+                        float X = 0.0f, Y = 0.0f, rho2 = INFINITY;
+                        if (zr > 0x1p-10f * dist) {
+                            X = x / z;
+                            Y = y / z;
+                            const float rho = q3 * sqrtf(1.0f + X * X + Y * Y) / zr;
+                            const float rs = rho * (1.0f + 0x1p-12f) + 0x1p-18f * (1.0f + fabsf(X) + fabsf(Y));
+                            rho2 = rs * rs;
+                        }
+                        const float tmin = (dist - q3) * (1.0f - 0x1p-20f) - slack;
+                        const float tmax = dist * (1.0f + 0x1p-20f) + slack;
+                        L.fr.disc[n_cand + below_l] = make_float4(X, Y, rho2, tmin);
+                        L.fr.far_ref[n_cand + below_l] = make_float2(tmax, __uint_as_float((node << 2) | sl));
+                    } else {
+                        // the screen capsule: the balls of radius rr centred on the
+                        // segment project into discs whose centres run along the
+                        // screen segment between the projected end points A, B and
+                        // whose radii rr sqrt(1 + X^2 + Y^2) / (z - rr) are convex
+                        // along it (z is affine in the segment's parameter, 1 / z
+                        // affine along the screen segment), so at most the larger
+                        // of the two ends' radii, the smaller z and the larger
+                        // sqrt(1 + X^2 + Y^2) taken together.  Depths: the entry
+                        // lies no nearer than the eye's distance to the segment
+                        // minus rr, and no farther than dist + h.  A sphere of the
+                        // set (h <= r) is the capsule with ha = 0.
+                        const float rr = q3 + eye.E + ha * 0x1p-20f;
+                        const float ux = u0 * bR[0] + u1 * bR[1] + u2 * bR[2];
+                        const float uy = u0 * bU[0] + u1 * bU[1] + u2 * bU[2];
+                        const float uz = u0 * bF[0] + u1 * bF[1] + u2 * bF[2];
+                        const float xa = fmaf(-ha, ux, x), ya = fmaf(-ha, uy, y), za = fmaf(-ha, uz, z);
+                        const float xb = fmaf(ha, ux, x), yb = fmaf(ha, uy, y), zb = fmaf(ha, uz, z);
+                        const float zr = fminf(za, zb) - rr;
+                        float Xa = 0.0f, Ya = 0.0f, rho2 = INFINITY, dX = 0.0f, dY = 0.0f;
+                        if (zr > 0x1p-10f * dist) {
+                            Xa = xa / za;
+                            Ya = ya / za;
+                            const float Xb = xb / zb, Yb = yb / zb;
+                            const float m2 = fmaxf(1.0f + Xa * Xa + Ya * Ya, 1.0f + Xb * Xb + Yb * Yb);
+                            const float rho = rr * sqrtf(m2) / zr;
+                            const float rs = rho * (1.0f + 0x1p-12f) +
+                                             0x1p-18f * (1.0f + fmaxf(fabsf(Xa), fabsf(Xb)) + fmaxf(fabsf(Ya), fabsf(Yb)));
+                            rho2 = rs * rs;
+                            dX = Xb - Xa;
+                            dY = Yb - Ya;
+                        }
+                        const float sd = fminf(fmaxf(-(ox * u0 + oy * u1 + oz * u2), -ha), ha);
+                        const float wx = fmaf(sd, u0, ox), wy = fmaf(sd, u1, oy), wz = fmaf(sd, u2, oz);
+                        const float dmin = sqrtf(wx * wx + wy * wy + wz * wz);
+                        const float tmin = (dmin - rr) * (1.0f - 0x1p-20f) - slack;
+                        const float tmax = (dist + fmaxf(q3, q5) + eye.E) * (1.0f + 0x1p-20f) + slack;
+                        L.fr.disc[n_cand + below_l] = make_float4(Xa, Ya, rho2, tmin);
+                        L.fr.far_ref[n_cand + below_l] = make_float2(tmax, __uint_as_float((node << 2) | sl));
+                        L.fr.seg[n_cand + below_l] = make_float2(dX, dY);
                     }
-                    const float tmin = (dist - rb) * (1.0f - 0x1p-20f) - slack;
-                    const float tmax = (SPH ? dist + q5 : dist) * (1.0f + 0x1p-20f) + slack;
-                    L.fr.disc[n_cand + below_l] = make_float4(X, Y, rho2, tmin);
-                    L.fr.far_ref[n_cand + below_l] = make_float2(tmax, __uint_as_float((node << 2) | sl));
                 }
                 n_next += (uint32_t)__popcll(mi);
                 n_cand += (uint32_t)__popcll(ml);
             }
-            if (n_next > kFront || n_cand > kTileCand) {
+            if (n_next > kFr || n_cand > kTc) {
                 fb = true;
                 break;
             }
@@ -405,14 +489,17 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
         // any of them is tested, so a flush waits for memory once per group
         // (entries past a lane's queue read slot 0 of node 0, never used).
         // The frustum walk tests one entry at a time: its kernel keeps fewer
-        // registers that way, and more of its waves fit a SIMD.
-        constexpr int kFlushGroup = FRUSTUM ? 1 : 4;
+        // registers that way, and more of its waves fit a SIMD.  Spheroid sets
+        // also load each entry's axis, a second dependent load, so they keep
+        // the groups.
+        constexpr int kFlushGroup = (FRUSTUM && !SPH) ? 1 : 4;
         auto flush = [&]() {
             bool changed = false;
             for (uint32_t j0 = 0; j0 < (uint32_t)kQueue; j0 += kFlushGroup) {
               if (!__ballot(j0 < nc)) break;
               float2 p01[kFlushGroup], p23[kFlushGroup];
               float pa[kFlushGroup], ph[kFlushGroup];
+              float4 pax[kFlushGroup];
               uint32_t pid[kFlushGroup];
 #pragma unroll
               for (int u = 0; u < kFlushGroup; ++u) {
@@ -423,6 +510,12 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
                   pa[u] = s[4];
                   if constexpr (SPH) ph[u] = s[5];
                   pid[u] = __float_as_uint(nodes[e >> 2].f[24 + (e & 3u)]) & ~kLeafBit;
+              }
+              if constexpr (SPH) {
+#pragma unroll
+                  for (int u = 0; u < kFlushGroup; ++u)
+                      pax[u] = (j0 + u < nc && ph[u] > 0.0f && pid[u] < n_spheres) ? a.axis[pid[u]]
+                                                                                    : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
               }
 #pragma unroll
               for (int u = 0; u < kFlushGroup; ++u) {
@@ -441,25 +534,24 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
                 if constexpr (SPH) {
                     if (ph[u] > 0.0f) {
                         // spheroid (axis u scaled to unit length, half-length h
-                        // along it, r across): S y = y / r + (y.u)(1/h - 1/r) u maps
-                        // it to the unit ball and the ray to t D - L, D = S d,
-                        // L = S (c - o); then the robust sphere form: t_m = L.D / D.D,
-                        // w = L - t_m D, t0 = t_m - sqrt((1 - w.w) / D.D)
-                        const float4 ua = a.axis[id];
-                        const double ul = sqrt((double)ua.x * ua.x + (double)ua.y * ua.y + (double)ua.z * ua.z);
-                        const double u0 = ua.x / ul, u1 = ua.y / ul, u2 = ua.z / ul;
-                        const double w = 1.0 / (double)ph[u] - 1.0 / r;
-                        const double du = ray.d[0] * u0 + ray.d[1] * u1 + ray.d[2] * u2;
-                        const double ou = oc0 * u0 + oc1 * u1 + oc2 * u2;
-                        const double D0 = ray.d[0] / r + du * w * u0, D1 = ray.d[1] / r + du * w * u1,
-                                     D2 = ray.d[2] / r + du * w * u2;
-                        const double L0 = oc0 / r + ou * w * u0, L1 = oc1 / r + ou * w * u1,
-                                     L2 = oc2 / r + ou * w * u2;
-                        const double DD = D0 * D0 + D1 * D1 + D2 * D2;
-                        const double tm = (L0 * D0 + L1 * D1 + L2 * D2) / DD;
+                        // along it, r across): y -> y + (y.u)(r/h - 1) u maps it to
+                        // the ball of radius r and the ray to t D - L, D the image of
+                        // d and L that of c - o; then the robust sphere form:
+                        // t_m = L.D / D.D, w = L - t_m D, t0 = t_m - sqrt((r^2 - w.w) / D.D)
+                        const float4 ua = pax[u];
+                        const double il = 1.0 / sqrt((double)ua.x * ua.x + (double)ua.y * ua.y + (double)ua.z * ua.z);
+                        const double u0 = ua.x * il, u1 = ua.y * il, u2 = ua.z * il;
+                        const double h = (double)ph[u];
+                        const double k = (r - h) / h;
+                        const double du = (ray.d[0] * u0 + ray.d[1] * u1 + ray.d[2] * u2) * k;
+                        const double ou = (oc0 * u0 + oc1 * u1 + oc2 * u2) * k;
+                        const double D0 = ray.d[0] + du * u0, D1 = ray.d[1] + du * u1, D2 = ray.d[2] + du * u2;
+                        const double L0 = oc0 + ou * u0, L1 = oc1 + ou * u1, L2 = oc2 + ou * u2;
+                        const double iDD = 1.0 / (D0 * D0 + D1 * D1 + D2 * D2);
+                        const double tm = (L0 * D0 + L1 * D1 + L2 * D2) * iDD;
                         const double w0 = L0 - tm * D0, w1 = L1 - tm * D1, w2 = L2 - tm * D2;
-                        const double ds = 1.0 - (w0 * w0 + w1 * w1 + w2 * w2);
-                        disc = ds < 0.0 ? ds : ds / DD;
+                        const double ds = r * r - (w0 * w0 + w1 * w1 + w2 * w2);
+                        disc = ds < 0.0 ? ds : ds * iDD;
                         tc = tm;
                     }
                 }
@@ -545,7 +637,32 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
                 // in the ball of radius h around its centre, and its entry in
                 // [b - h, b + h]; a sphere's (word 5: 0) in [b - r, b]
                 const float rE = (SPH ? fmaxf(s[3], s[5]) : s[3]) + eye.E;
-                const bool may = (qf <= rE * rE) & (bf - rE <= pf) & ((SPH ? bf + s[5] : bf) + eye.E >= lo_f);
+                bool may = (qf <= rE * rE) & (bf - rE <= pf) & ((SPH ? bf + s[5] : bf) + eye.E >= lo_f);
+                if constexpr (SPH) {
+                    // a spheroid with h > r: the ray's distance to the capsule's
+                    // segment c + s u, |s| <= h - r, at s clamped from the
+                    // minimiser over the line (a ray nearly along the axis keeps
+                    // the ball test: there the clamped minimiser's rounding could
+                    // exceed the margins)
+                    const uint32_t id = __float_as_uint(f[24 + side]) & ~kLeafBit;
+                    if (may && s[5] > s[3] && id < n_spheres) {
+                        const float4 ua = a.axis[id];
+                        const float il = rsqrtf(fmaf(ua.x, ua.x, fmaf(ua.y, ua.y, ua.z * ua.z)));
+                        const float u0 = ua.x * il, u1 = ua.y * il, u2 = ua.z * il;
+                        const float ha = s[5] - s[3];
+                        const float du = u0 * ray.df[0] + u1 * ray.df[1] + u2 * ray.df[2];
+                        const float wu = ox * u0 + oy * u1 + oz * u2;
+                        const float den = 1.0f - du * du;
+                        if (den >= 0x1p-6f) {
+                            const float sd = fminf(fmaxf((bf * du - wu) / den, -ha), ha);
+                            const float gx = fmaf(sd, u0, ox), gy = fmaf(sd, u1, oy), gz = fmaf(sd, u2, oz);
+                            const float gb = gx * ray.df[0] + gy * ray.df[1] + gz * ray.df[2];
+                            const float wx = gx - gb * ray.df[0], wy = gy - gb * ray.df[1], wz = gz - gb * ray.df[2];
+                            const float rc = s[3] + 2.0f * eye.E + ha * 0x1p-20f;
+                            may = wx * wx + wy * wy + wz * wz <= rc * rc;
+                        }
+                    }
+                }
                 // nc < kQueue here: the queue is flushed once a lane could overflow
                 L.cand[nc][lane] = (node << 2) | (uint32_t)side;
                 nc += may ? 1u : 0u;
@@ -704,16 +821,29 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
         auto cand_pass = [&](auto &F) {
             for (uint32_t j = 0; j < n_cand; j += kCandGroup) {
                 float4 dc[kCandGroup];
-                float2 fr[kCandGroup];
+                float2 fr[kCandGroup], sg[kCandGroup];
 #pragma unroll
                 for (int u = 0; u < kCandGroup; ++u) {
                     const uint32_t i = min(j + (uint32_t)u, n_cand - 1u);
                     dc[u] = F.disc[i];
                     fr[u] = F.far_ref[i];
+                    if constexpr (SPH) sg[u] = F.seg[i];
                 }
 #pragma unroll
                 for (int u = 0; u < kCandGroup; ++u) {
-                    const float du = sxl - dc[u].x, dv = syl - dc[u].y;
+                    float du = sxl - dc[u].x, dv = syl - dc[u].y;
+                    if constexpr (SPH) {
+                        // the point of the screen segment nearest the pixel, to
+                        // the rounding of its parameter (an error far inside the
+                        // slack); a segment whose squared length underflows gives
+                        // a NaN or infinite parameter, which the clamp turns into
+                        // an end point, and any of its points will do
+                        const float l2 = fmaf(sg[u].x, sg[u].x, sg[u].y * sg[u].y);
+                        const float w = fminf(fmaxf(fmaf(du, sg[u].x, dv * sg[u].y) * __builtin_amdgcn_rcpf(l2), 0.0f),
+                                              1.0f);
+                        du = fmaf(-w, sg[u].x, du);
+                        dv = fmaf(-w, sg[u].y, dv);
+                    }
                     const bool may = (j + u < n_cand) & (fmaf(du, du, dv * dv) <= dc[u].z) & (dc[u].w <= pr_f) &
                                      (fr[u].x >= lo_f);
                     // nc <= kQueue - kCandGroup at the start of a round: the
@@ -942,7 +1072,7 @@ __host__ inline uint32_t blocks_for(int tiles_x, int tiles_y, int schedule)
 template <int K, bool BWD, int WALK, bool SPH>
 __global__ void __launch_bounds__(64) k_trace(TraceArgs a, int tiles_x, int tiles_y)
 {
-    __shared__ WaveLds<WALK == SPLAT_WALK_FRUSTUM> lds;
+    __shared__ WaveLds<WALK == SPLAT_WALK_FRUSTUM, SPH> lds;
     int tx, ty;
     TileRegion rg = {0, a.tile_w, 0, a.tile_h};
     if (a.order) {
