@@ -98,29 +98,34 @@ constexpr uint32_t kLaneStack = 16;  // per-lane walk: stack entries per lane (a
 
 constexpr uint32_t kFront = 128;  // frustum walk: nodes of one level of the breadth-first walk
 constexpr uint32_t kTileCand = 256;  // frustum walk: candidate spheres of one tile
-// spheroid sets: their long boxes overlap more, so their lists are longer
-constexpr uint32_t kFrontS = 384;
-constexpr uint32_t kTileCandS = 384;
+// spheroid sets: the depth-first frustum walk's stack, and its candidates
+// screened and tested a chunk at a time
+constexpr uint32_t kStackS = 512;
+constexpr uint32_t kChunk = 128;
 
 // Frustum walk: the two levels of the breadth-first walk, and per candidate
 // sphere of the tile its screen disc (centre X, Y and squared radius in the
 // tangent units of the pixel grid), its depth range [tmin, tmax] along any
 // ray of the tile, and its slot, (wide node index << 2) | slot.
-// A spheroid set stores per candidate the screen capsule instead: the disc's
-// centre is one end of the capsule's screen segment, and seg holds the
-// segment (dX, dY) to the other end.
 template <bool SPH>
 struct FrustumLds {
     uint32_t front[2][kFront];
     float4 disc[kTileCand];   // X, Y, rho^2, tmin
     float2 far_ref[kTileCand];  // tmax, slot (bits)
 };
+// Spheroid sets walk the tile's frustum depth first, with the stack of
+// nodes still to visit; per candidate of the current chunk the screen
+// capsule (one end of its screen segment with the squared radius and tmin,
+// the segment to the other end with tmax and the id) and what the exact
+// test reads: centre and radius, axis as stored and half-length, opacity.
 template <>
 struct FrustumLds<true> {
-    uint32_t front[2][kFrontS];
-    float4 disc[kTileCandS];
-    float2 far_ref[kTileCandS];
-    float2 seg[kTileCandS];   // dX, dY
+    uint32_t stack[kStackS];
+    float4 scr[kChunk];       // Xa, Ya, rho^2, tmin
+    float4 seg[kChunk];       // dX, dY, tmax, id (bits)
+    float4 geo[kChunk];       // cx, cy, cz, r
+    float4 ax[kChunk];        // axis, h
+    float alpha[kChunk];
 };
 
 // LDS of one wave: the leaf candidates awaiting the exact test (a column per
@@ -275,7 +280,7 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
     uint32_t n_cand = 0;  // wave-uniform
     bool fb = !FRUSTUM;   // wave-uniform: the tile uses the per-lane walk
     float sxl = 0.0f, syl = 0.0f;
-    if constexpr (FRUSTUM) {
+    if constexpr (FRUSTUM && !SPH) {
         {
             const double aspect = (double)a.cam.w / (double)a.cam.h;
             const int cx = max(min(px, a.cam.w - 1), 0), cy = max(min(py, a.cam.h - 1), 0);
@@ -315,7 +320,6 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
         const float bU[3] = {(float)a.cam.up[0], (float)a.cam.up[1], (float)a.cam.up[2]};
         const float bF[3] = {(float)a.cam.fwd[0], (float)a.cam.fwd[1], (float)a.cam.fwd[2]};
         const bool any = __ballot(active) != 0;
-        constexpr uint32_t kFr = SPH ? kFrontS : kFront, kTc = SPH ? kTileCandS : kTileCand;
         uint32_t cur = 0, n_front = any ? 1u : 0u;
         if (lane == 0) L.fr.front[0][0] = 0u;  // the root
         fb = false;
@@ -345,43 +349,14 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
                     const float bx = fmaf(pp[pl][0], q3, fmaf(pn[pl][0], q0, pc[pl]));
                     const float vb = fmaf(pp[pl][2], q5, fmaf(pn[pl][2], q2, fmaf(pp[pl][1], q4, fmaf(pn[pl][1], q1, bx))));
                     const float vs = fmaf(pp[pl][0] + pn[pl][0], q0, fmaf(pp[pl][1] + pn[pl][1], q1,
-                                     fmaf(pp[pl][2] + pn[pl][2], q2, pc[pl]))) + (SPH ? fmaxf(q3, q5) : q3);
+                                     fmaf(pp[pl][2] + pn[pl][2], q2, pc[pl]))) + q3;
                     pass = pass && (is_leaf ? vs : vb) >= -slack;
-                }
-                // a spheroid with h > r lies in the capsule of radius r around
-                // the segment c +- (h - r) u (at a distance x from c along u
-                // its half-width r sqrt(1 - x^2 / h^2) stays within the
-                // capsule's); the capsule meets the half-space of a plane with
-                // unit normal n when n.c + (h - r)|n.u| + r does, with margins
-                // for the float axis and end points
-                float u0 = 0.0f, u1 = 0.0f, u2 = 0.0f, ha = 0.0f;
-                if constexpr (SPH) {
-                    const uint32_t id = ref & ~kLeafBit;
-                    // an id beyond the set is never tested (the exact test skips it)
-                    if (pass && is_leaf && id >= n_spheres) pass = false;
-                    if (pass && is_leaf && q5 > q3) {
-                        const float4 ua = a.axis[id];
-                        const float il = rsqrtf(fmaf(ua.x, ua.x, fmaf(ua.y, ua.y, ua.z * ua.z)));
-                        u0 = ua.x * il;
-                        u1 = ua.y * il;
-                        u2 = ua.z * il;
-                        ha = q5 - q3;
-                        const float rr = q3 + eye.E + ha * 0x1p-20f;
-#pragma unroll
-                        for (int pl = 0; pl < 4; ++pl) {
-                            const float n0 = pp[pl][0] + pn[pl][0], n1 = pp[pl][1] + pn[pl][1],
-                                        n2 = pp[pl][2] + pn[pl][2];
-                            const float sc = fmaf(n0, q0, fmaf(n1, q1, fmaf(n2, q2, pc[pl])));
-                            const float nu = fabsf(fmaf(n0, u0, fmaf(n1, u1, n2 * u2)));
-                            pass = pass && fmaf(ha, nu, sc + rr) >= -slack;
-                        }
-                    }
                 }
                 const uint64_t mi = __ballot(pass && is_int), ml = __ballot(pass && is_leaf);
                 const uint32_t below_i = (uint32_t)__popcll(mi & ((1ull << lane) - 1ull));
                 const uint32_t below_l = (uint32_t)__popcll(ml & ((1ull << lane) - 1ull));
-                if (pass && is_int && n_next + below_i < kFr) L.fr.front[cur ^ 1u][n_next + below_i] = ref;
-                if (pass && is_leaf && n_cand + below_l < kTc) {
+                if (pass && is_int && n_next + below_i < kFront) L.fr.front[cur ^ 1u][n_next + below_i] = ref;
+                if (pass && is_leaf && n_cand + below_l < kTileCand) {
                     // the candidate's screen disc and depth range, in float with
                     // outward slack (relative 2^-12 on rho, 2^-18 absolute in tangent
                     // units, 2^-20 relative on depths plus the margin)
@@ -390,66 +365,24 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
                     const float y = ox * bU[0] + oy * bU[1] + oz * bU[2];
                     const float z = ox * bF[0] + oy * bF[1] + oz * bF[2];
                     const float dist = sqrtf(ox * ox + oy * oy + oz * oz);
-                    if constexpr (!SPH) {
-                        const float zr = z - q3;
-                        float X = 0.0f, Y = 0.0f, rho2 = INFINITY;
-                        if (zr > 0x1p-10f * dist) {
-                            X = x / z;
-                            Y = y / z;
-                            const float rho = q3 * sqrtf(1.0f + X * X + Y * Y) / zr;
-                            const float rs = rho * (1.0f + 0x1p-12f) + 0x1p-18f * (1.0f + fabsf(X) + fabsf(Y));
-                            rho2 = rs * rs;
-                        }
-                        const float tmin = (dist - q3) * (1.0f - 0x1p-20f) - slack;
-                        const float tmax = dist * (1.0f + 0x1p-20f) + slack;
-                        L.fr.disc[n_cand + below_l] = make_float4(X, Y, rho2, tmin);
-                        L.fr.far_ref[n_cand + below_l] = make_float2(tmax, __uint_as_float((node << 2) | sl));
-                    } else {
-                        // the screen capsule: the balls of radius rr centred on the
-                        // segment project into discs whose centres run along the
-                        // screen segment between the projected end points A, B and
-                        // whose radii rr sqrt(1 + X^2 + Y^2) / (z - rr) are convex
-                        // along it (z is affine in the segment's parameter, 1 / z
-                        // affine along the screen segment), so at most the larger
-                        // of the two ends' radii, the smaller z and the larger
-                        // sqrt(1 + X^2 + Y^2) taken together.  Depths: the entry
-                        // lies no nearer than the eye's distance to the segment
-                        // minus rr, and no farther than dist + h.  A sphere of the
-                        // set (h <= r) is the capsule with ha = 0.
-                        const float rr = q3 + eye.E + ha * 0x1p-20f;
-                        const float ux = u0 * bR[0] + u1 * bR[1] + u2 * bR[2];
-                        const float uy = u0 * bU[0] + u1 * bU[1] + u2 * bU[2];
-                        const float uz = u0 * bF[0] + u1 * bF[1] + u2 * bF[2];
-                        const float xa = fmaf(-ha, ux, x), ya = fmaf(-ha, uy, y), za = fmaf(-ha, uz, z);
-                        const float xb = fmaf(ha, ux, x), yb = fmaf(ha, uy, y), zb = fmaf(ha, uz, z);
-                        const float zr = fminf(za, zb) - rr;
-                        float Xa = 0.0f, Ya = 0.0f, rho2 = INFINITY, dX = 0.0f, dY = 0.0f;
-                        if (zr > 0x1p-10f * dist) {
-                            Xa = xa / za;
-                            Ya = ya / za;
-                            const float Xb = xb / zb, Yb = yb / zb;
-                            const float m2 = fmaxf(1.0f + Xa * Xa + Ya * Ya, 1.0f + Xb * Xb + Yb * Yb);
-                            const float rho = rr * sqrtf(m2) / zr;
-                            const float rs = rho * (1.0f + 0x1p-12f) +
-                                             0x1p-18f * (1.0f + fmaxf(fabsf(Xa), fabsf(Xb)) + fmaxf(fabsf(Ya), fabsf(Yb)));
-                            rho2 = rs * rs;
-                            dX = Xb - Xa;
-                            dY = Yb - Ya;
-                        }
-                        const float sd = fminf(fmaxf(-(ox * u0 + oy * u1 + oz * u2), -ha), ha);
-                        const float wx = fmaf(sd, u0, ox), wy = fmaf(sd, u1, oy), wz = fmaf(sd, u2, oz);
-                        const float dmin = sqrtf(wx * wx + wy * wy + wz * wz);
-                        const float tmin = (dmin - rr) * (1.0f - 0x1p-20f) - slack;
-                        const float tmax = (dist + fmaxf(q3, q5) + eye.E) * (1.0f + 0x1p-20f) + slack;
-                        L.fr.disc[n_cand + below_l] = make_float4(Xa, Ya, rho2, tmin);
-                        L.fr.far_ref[n_cand + below_l] = make_float2(tmax, __uint_as_float((node << 2) | sl));
-                        L.fr.seg[n_cand + below_l] = make_float2(dX, dY);
+                    const float zr = z - q3;
+                    float X = 0.0f, Y = 0.0f, rho2 = INFINITY;
+                    if (zr > 0x1p-10f * dist) {
+                        X = x / z;
+                        Y = y / z;
+                        const float rho = q3 * sqrtf(1.0f + X * X + Y * Y) / zr;
+                        const float rs = rho * (1.0f + 0x1p-12f) + 0x1p-18f * (1.0f + fabsf(X) + fabsf(Y));
+                        rho2 = rs * rs;
                     }
+                    const float tmin = (dist - q3) * (1.0f - 0x1p-20f) - slack;
+                    const float tmax = dist * (1.0f + 0x1p-20f) + slack;
+                    L.fr.disc[n_cand + below_l] = make_float4(X, Y, rho2, tmin);
+                    L.fr.far_ref[n_cand + below_l] = make_float2(tmax, __uint_as_float((node << 2) | sl));
                 }
                 n_next += (uint32_t)__popcll(mi);
                 n_cand += (uint32_t)__popcll(ml);
             }
-            if (n_next > kFr || n_cand > kTc) {
+            if (n_next > kFront || n_cand > kTileCand) {
                 fb = true;
                 break;
             }
@@ -476,6 +409,7 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
         const float lo_f = (float)(lo_t * (1.0 - 0x1p-20));
         uint32_t nc = 0;                         // queued leaf candidates
         bool redo = false;                       // spheres may be tested a second time
+        bool from_chunk = false;                 // spheroid frustum walk: the queue holds chunk indices
 
         // The exact test of the queued candidates.  A leaf slot holds the
         // sphere's centre, radius and opacity as stored by the last build or
@@ -501,6 +435,25 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
               float pa[kFlushGroup], ph[kFlushGroup];
               float4 pax[kFlushGroup];
               uint32_t pid[kFlushGroup];
+              bool loaded = false;
+              if constexpr (SPH && FRUSTUM) {
+                  if (from_chunk) {
+                      // everything from the chunk in LDS
+#pragma unroll
+                      for (int u = 0; u < kFlushGroup; ++u) {
+                          const uint32_t e = j0 + u < nc ? L.cand[j0 + u][lane] : 0u;
+                          const float4 gc = L.fr.geo[e];
+                          pax[u] = L.fr.ax[e];
+                          p01[u] = make_float2(gc.x, gc.y);
+                          p23[u] = make_float2(gc.z, gc.w);
+                          pa[u] = L.fr.alpha[e];
+                          ph[u] = pax[u].w;
+                          pid[u] = __float_as_uint(L.fr.seg[e].w);
+                      }
+                      loaded = true;
+                  }
+              }
+              if (!loaded) {
 #pragma unroll
               for (int u = 0; u < kFlushGroup; ++u) {
                   const uint32_t e = j0 + u < nc ? L.cand[j0 + u][lane] : 0u;
@@ -516,6 +469,7 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
                   for (int u = 0; u < kFlushGroup; ++u)
                       pax[u] = (j0 + u < nc && ph[u] > 0.0f && pid[u] < n_spheres) ? a.axis[pid[u]]
                                                                                     : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+              }
               }
 #pragma unroll
               for (int u = 0; u < kFlushGroup; ++u) {
@@ -821,29 +775,16 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
         auto cand_pass = [&](auto &F) {
             for (uint32_t j = 0; j < n_cand; j += kCandGroup) {
                 float4 dc[kCandGroup];
-                float2 fr[kCandGroup], sg[kCandGroup];
+                float2 fr[kCandGroup];
 #pragma unroll
                 for (int u = 0; u < kCandGroup; ++u) {
                     const uint32_t i = min(j + (uint32_t)u, n_cand - 1u);
                     dc[u] = F.disc[i];
                     fr[u] = F.far_ref[i];
-                    if constexpr (SPH) sg[u] = F.seg[i];
                 }
 #pragma unroll
                 for (int u = 0; u < kCandGroup; ++u) {
-                    float du = sxl - dc[u].x, dv = syl - dc[u].y;
-                    if constexpr (SPH) {
-                        // the point of the screen segment nearest the pixel, to
-                        // the rounding of its parameter (an error far inside the
-                        // slack); a segment whose squared length underflows gives
-                        // a NaN or infinite parameter, which the clamp turns into
-                        // an end point, and any of its points will do
-                        const float l2 = fmaf(sg[u].x, sg[u].x, sg[u].y * sg[u].y);
-                        const float w = fminf(fmaxf(fmaf(du, sg[u].x, dv * sg[u].y) * __builtin_amdgcn_rcpf(l2), 0.0f),
-                                              1.0f);
-                        du = fmaf(-w, sg[u].x, du);
-                        dv = fmaf(-w, sg[u].y, dv);
-                    }
+                    const float du = sxl - dc[u].x, dv = syl - dc[u].y;
                     const bool may = (j + u < n_cand) & (fmaf(du, du, dv * dv) <= dc[u].z) & (dc[u].w <= pr_f) &
                                      (fr[u].x >= lo_f);
                     // nc <= kQueue - kCandGroup at the start of a round: the
@@ -854,7 +795,243 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
                 if (__ballot(nc > (uint32_t)(kQueue - kCandGroup))) flush();
             }
         };
-        if constexpr (FRUSTUM) {
+        // Spheroid sets: the tile's frustum walked depth first, sixteen nodes a
+        // step (one slot per lane) from a stack in LDS.  A box that lies wholly
+        // beyond every lane's prune key is dropped, which the stop at the alpha
+        // threshold makes common behind an opaque layer.  Each spheroid the
+        // frustum meets goes into the current chunk with its screen capsule and
+        // what the exact test reads; a chunk is screened per lane and tested
+        // when it fills, so no list bounds the walk.  A stack overflow or a
+        // corrupt hierarchy sets fb: the tile then takes the per-lane walk.
+        auto frustum_dfs = [&]() {
+          if constexpr (FRUSTUM && SPH) {
+            {
+                const double aspect = (double)a.cam.w / (double)a.cam.h;
+                const int cx = max(min(px, a.cam.w - 1), 0), cy = max(min(py, a.cam.h - 1), 0);
+                sxl = (float)(((2.0 * cx + 1.0) / (double)a.cam.w - 1.0) * a.cam.tan_half * aspect);
+                syl = (float)((1.0 - (2.0 * cy + 1.0) / (double)a.cam.h) * a.cam.tan_half);
+            }
+            // the tile's four side planes, as for the breadth-first walk
+            const int tw = a.tile_w;
+            const int corner[4] = {rg.y0 * tw + rg.x0, rg.y0 * tw + rg.x1 - 1, (rg.y1 - 1) * tw + rg.x1 - 1,
+                                   (rg.y1 - 1) * tw + rg.x0};
+            double cd[4][3];
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+#pragma unroll
+                for (int k = 0; k < 3; ++k) cd[c][k] = __shfl(ray.d[k], corner[c], kWave);
+            const double cen[3] = {cd[0][0] + cd[1][0] + cd[2][0] + cd[3][0], cd[0][1] + cd[1][1] + cd[2][1] + cd[3][1],
+                                   cd[0][2] + cd[1][2] + cd[2][2] + cd[3][2]};
+            float pp[4][3], pn[4][3], pc[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const double *u = cd[i], *v = cd[(i + 1) & 3];
+                double n0 = u[1] * v[2] - u[2] * v[1], n1 = u[2] * v[0] - u[0] * v[2], n2 = u[0] * v[1] - u[1] * v[0];
+                const double len = sqrt(n0 * n0 + n1 * n1 + n2 * n2);
+                const double sg = (n0 * cen[0] + n1 * cen[1] + n2 * cen[2]) < 0.0 ? -1.0 : 1.0;
+                const double inv = len > 1e-300 ? sg / len : 0.0;
+                const float f0 = (float)(n0 * inv), f1 = (float)(n1 * inv), f2 = (float)(n2 * inv);
+                pp[i][0] = fmaxf(f0, 0.0f); pp[i][1] = fmaxf(f1, 0.0f); pp[i][2] = fmaxf(f2, 0.0f);
+                pn[i][0] = fminf(f0, 0.0f); pn[i][1] = fminf(f1, 0.0f); pn[i][2] = fminf(f2, 0.0f);
+                pc[i] = (float)(-((double)f0 * eye.o[0] + (double)f1 * eye.o[1] + (double)f2 * eye.o[2]));
+            }
+            const float slack = 4.0f * eye.E;
+            const float bR[3] = {(float)a.cam.right[0], (float)a.cam.right[1], (float)a.cam.right[2]};
+            const float bU[3] = {(float)a.cam.up[0], (float)a.cam.up[1], (float)a.cam.up[2]};
+            const float bF[3] = {(float)a.cam.fwd[0], (float)a.cam.fwd[1], (float)a.cam.fwd[2]};
+            auto wave_max = [](float v) {
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, kWave));
+                return v;
+            };
+            float wmax = wave_max(pr_f);  // lanes taking no part hold -inf
+            // The chunk's screening: the point of the capsule's screen segment
+            // nearest the pixel, to the rounding of its parameter (an error far
+            // inside the slack); a segment whose squared length underflows gives
+            // a NaN or infinite parameter, which the clamp turns into an end
+            // point, and any of its points will do.  Then the chunk is tested
+            // before it is overwritten.
+            auto chunk_pass = [&](uint32_t n) {
+                from_chunk = true;
+                for (uint32_t j = 0; j < n; j += kCandGroup) {
+                    float4 dc[kCandGroup], sg[kCandGroup];
+#pragma unroll
+                    for (int u = 0; u < kCandGroup; ++u) {
+                        const uint32_t i = min(j + (uint32_t)u, n - 1u);
+                        dc[u] = L.fr.scr[i];
+                        sg[u] = L.fr.seg[i];
+                    }
+#pragma unroll
+                    for (int u = 0; u < kCandGroup; ++u) {
+                        float du = sxl - dc[u].x, dv = syl - dc[u].y;
+                        const float l2 = fmaf(sg[u].x, sg[u].x, sg[u].y * sg[u].y);
+                        const float w = fminf(fmaxf(fmaf(du, sg[u].x, dv * sg[u].y) * __builtin_amdgcn_rcpf(l2), 0.0f),
+                                              1.0f);
+                        du = fmaf(-w, sg[u].x, du);
+                        dv = fmaf(-w, sg[u].y, dv);
+                        const bool may = (j + u < n) & (fmaf(du, du, dv * dv) <= dc[u].z) & (dc[u].w <= pr_f) &
+                                         (sg[u].z >= lo_f);
+                        L.cand[nc][lane] = j + (uint32_t)u;
+                        nc += may ? 1u : 0u;
+                    }
+                    if (__ballot(nc > (uint32_t)(kQueue - kCandGroup))) flush();
+                }
+                if (__ballot(nc > 0u)) flush();
+                from_chunk = false;
+                wmax = wave_max(pr_f);
+            };
+            uint32_t top = __ballot(active) ? 1u : 0u;  // wave-uniform
+            if (lane == 0) L.fr.stack[0] = 0u;          // the root
+            uint32_t n_chunk = 0, visits = 0;
+            while (top > 0u) {
+                __builtin_amdgcn_wave_barrier();
+                const uint32_t take = min(top, (uint32_t)kWave / 4u);
+                // a pass visits every node at most once; more visits only
+                // occur in a corrupt hierarchy
+                visits += take;
+                if (visits > n_nodes + (uint32_t)kWave) {
+                    fb = true;
+                    break;
+                }
+                const uint32_t base = top - take;
+                const uint32_t i = (uint32_t)lane / 4u, sl = (uint32_t)lane & 3u;
+                const bool valid = i < take;
+                const uint32_t node = valid ? min(L.fr.stack[base + i], n_nodes - 1) : 0u;
+                top = base;
+                const float *f = nodes[node].f;
+                const uint32_t kinds = valid ? __float_as_uint(f[31]) : 0u;
+                const bool is_leaf = (kinds >> sl) & 1u, is_int = (kinds >> (4u + sl)) & 1u;
+                const float *q = f + 6 * sl;
+                const float q0 = q[0], q1 = q[1], q2 = q[2], q3 = q[3], q4 = q[4], q5 = q[5];
+                const uint32_t ref = __float_as_uint(f[24 + sl]);
+                const uint32_t id = ref & ~kLeafBit;
+                // an id beyond the set is never tested (the exact test skips it)
+                bool pass = is_int || (is_leaf && id < n_spheres);
+#pragma unroll
+                for (int pl = 0; pl < 4; ++pl) {
+                    // box: its corner farthest along the normal; spheroid: the
+                    // ball of radius max(r, h) around its centre
+                    const float bx = fmaf(pp[pl][0], q3, fmaf(pn[pl][0], q0, pc[pl]));
+                    const float vb = fmaf(pp[pl][2], q5, fmaf(pn[pl][2], q2, fmaf(pp[pl][1], q4, fmaf(pn[pl][1], q1, bx))));
+                    const float vs = fmaf(pp[pl][0] + pn[pl][0], q0, fmaf(pp[pl][1] + pn[pl][1], q1,
+                                     fmaf(pp[pl][2] + pn[pl][2], q2, pc[pl]))) + fmaxf(q3, q5);
+                    pass = pass && (is_leaf ? vs : vb) >= -slack;
+                }
+                if (pass && is_int) {
+                    // the eye's distance to the box bounds every entry in it
+                    const float ex = fmaxf(fmaxf(q0 - eye.of[0], eye.of[0] - q3), 0.0f);
+                    const float ey = fmaxf(fmaxf(q1 - eye.of[1], eye.of[1] - q4), 0.0f);
+                    const float ez = fmaxf(fmaxf(q2 - eye.of[2], eye.of[2] - q5), 0.0f);
+                    pass = sqrtf(ex * ex + ey * ey + ez * ez) * (1.0f - 0x1p-20f) - slack <= wmax;
+                }
+                // a spheroid with h > r lies in the capsule of radius r around
+                // the segment c +- (h - r) u (at a distance x from c along u its
+                // half-width r sqrt(1 - x^2 / h^2) stays within the capsule's);
+                // the capsule meets the half-space of a plane with unit normal n
+                // when n.c + (h - r)|n.u| + r does, with margins for the float
+                // axis and end points.  A sample with 0 < h <= r lies in its ball.
+                float4 ua = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                float u0 = 0.0f, u1 = 0.0f, u2 = 0.0f, ha = 0.0f;
+                if (pass && is_leaf && q5 > 0.0f) {
+                    ua = a.axis[id];
+                    if (q5 > q3) {
+                        const float il = rsqrtf(fmaf(ua.x, ua.x, fmaf(ua.y, ua.y, ua.z * ua.z)));
+                        u0 = ua.x * il;
+                        u1 = ua.y * il;
+                        u2 = ua.z * il;
+                        ha = q5 - q3;
+                        const float rr = q3 + eye.E + ha * 0x1p-20f;
+#pragma unroll
+                        for (int pl = 0; pl < 4; ++pl) {
+                            const float n0 = pp[pl][0] + pn[pl][0], n1 = pp[pl][1] + pn[pl][1],
+                                        n2 = pp[pl][2] + pn[pl][2];
+                            const float sc = fmaf(n0, q0, fmaf(n1, q1, fmaf(n2, q2, pc[pl])));
+                            const float nu = fabsf(fmaf(n0, u0, fmaf(n1, u1, n2 * u2)));
+                            pass = pass && fmaf(ha, nu, sc + rr) >= -slack;
+                        }
+                    }
+                }
+                const uint64_t mi = __ballot(pass && is_int), ml = __ballot(pass && is_leaf);
+                const uint32_t below_i = (uint32_t)__popcll(mi & ((1ull << lane) - 1ull));
+                const uint32_t below_l = (uint32_t)__popcll(ml & ((1ull << lane) - 1ull));
+                if (pass && is_int && top + below_i < kStackS) L.fr.stack[top + below_i] = ref;
+                if (pass && is_leaf) {
+                    // n_chunk <= kChunk - 64 here: a fuller chunk is tested first.
+                    // The screen capsule: the balls of radius rr centred on the
+                    // segment project into discs whose centres run along the
+                    // screen segment between the projected end points A, B and
+                    // whose radii rr sqrt(1 + X^2 + Y^2) / (z - rr) are convex
+                    // along it (z is affine in the segment's parameter, 1 / z
+                    // affine along the screen segment), so at most the larger of
+                    // the two ends' radii, the smaller z and the larger
+                    // sqrt(1 + X^2 + Y^2) taken together.  Depths: the entry lies
+                    // no nearer than the eye's distance to the segment minus rr,
+                    // and no farther than dist + max(r, h).  A sample with h <= r
+                    // is the capsule with ha = 0.
+                    const uint32_t slot = n_chunk + below_l;
+                    const float ox = q0 - eye.of[0], oy = q1 - eye.of[1], oz = q2 - eye.of[2];
+                    const float x = ox * bR[0] + oy * bR[1] + oz * bR[2];
+                    const float y = ox * bU[0] + oy * bU[1] + oz * bU[2];
+                    const float z = ox * bF[0] + oy * bF[1] + oz * bF[2];
+                    const float dist = sqrtf(ox * ox + oy * oy + oz * oz);
+                    const float rr = q3 + eye.E + ha * 0x1p-20f;
+                    const float ux = u0 * bR[0] + u1 * bR[1] + u2 * bR[2];
+                    const float uy = u0 * bU[0] + u1 * bU[1] + u2 * bU[2];
+                    const float uz = u0 * bF[0] + u1 * bF[1] + u2 * bF[2];
+                    const float xa = fmaf(-ha, ux, x), ya = fmaf(-ha, uy, y), za = fmaf(-ha, uz, z);
+                    const float xb = fmaf(ha, ux, x), yb = fmaf(ha, uy, y), zb = fmaf(ha, uz, z);
+                    const float zr = fminf(za, zb) - rr;
+                    float Xa = 0.0f, Ya = 0.0f, rho2 = INFINITY, dX = 0.0f, dY = 0.0f;
+                    if (zr > 0x1p-10f * dist) {
+                        Xa = xa / za;
+                        Ya = ya / za;
+                        const float Xb = xb / zb, Yb = yb / zb;
+                        const float m2 = fmaxf(1.0f + Xa * Xa + Ya * Ya, 1.0f + Xb * Xb + Yb * Yb);
+                        const float rho = rr * sqrtf(m2) / zr;
+                        const float rs = rho * (1.0f + 0x1p-12f) +
+                                         0x1p-18f * (1.0f + fmaxf(fabsf(Xa), fabsf(Xb)) + fmaxf(fabsf(Ya), fabsf(Yb)));
+                        rho2 = rs * rs;
+                        dX = Xb - Xa;
+                        dY = Yb - Ya;
+                    }
+                    const float sd = fminf(fmaxf(-(ox * u0 + oy * u1 + oz * u2), -ha), ha);
+                    const float wx = fmaf(sd, u0, ox), wy = fmaf(sd, u1, oy), wz = fmaf(sd, u2, oz);
+                    const float dmin = sqrtf(wx * wx + wy * wy + wz * wz);
+                    const float tmin = (dmin - rr) * (1.0f - 0x1p-20f) - slack;
+                    const float tmax = (dist + fmaxf(q3, q5) + eye.E) * (1.0f + 0x1p-20f) + slack;
+                    L.fr.scr[slot] = make_float4(Xa, Ya, rho2, tmin);
+                    L.fr.seg[slot] = make_float4(dX, dY, tmax, __uint_as_float(id));
+                    L.fr.geo[slot] = make_float4(q0, q1, q2, q3);
+                    L.fr.ax[slot] = make_float4(ua.x, ua.y, ua.z, q5);
+                    L.fr.alpha[slot] = q4;
+                }
+                top += (uint32_t)__popcll(mi);
+                n_chunk += (uint32_t)__popcll(ml);
+                if (top > kStackS) {
+                    fb = true;
+                    break;
+                }
+                if (n_chunk > kChunk - (uint32_t)kWave) {
+                    chunk_pass(n_chunk);
+                    n_chunk = 0;
+                }
+            }
+            if (!fb && n_chunk > 0u) chunk_pass(n_chunk);
+          }
+        };
+        if constexpr (FRUSTUM && SPH) {
+            bool partial = false;
+            if (!fb) {
+                frustum_dfs();
+                partial = fb;
+            }
+            if (fb) {
+                // a walk cut short has filed hits that the per-lane walk finds again
+                redo = partial;
+                lane_walk(SignTag<kMixedSigns>{});
+                redo = partial || overflow;
+            }
+        } else if constexpr (FRUSTUM) {
             if (!fb) {
                 cand_pass(L.fr);
             } else {
