@@ -308,7 +308,24 @@ k_sort_scatter(const uint32_t *__restrict__ keys_in, const uint32_t *__restrict_
 
 // ---------------------------------------------------------------- hierarchy
 
-__device__ inline int common_prefix(const uint32_t *__restrict__ keys, int n, int i, int j)
+// The keys around a block's nodes, staged in LDS: most nodes are low in the
+// tree, and their searches stay within a few hundred positions.
+constexpr int kKarrasBlock = 256;
+constexpr int kKarrasHalo = 256;
+constexpr int kKarrasSpan = kKarrasBlock + 2 * kKarrasHalo;
+
+struct StagedKeys {
+    const uint32_t *keys;  // all sorted keys
+    const uint32_t *lds;   // keys [first, first + kKarrasSpan), where they exist
+    int first;
+    __device__ uint32_t operator[](int j) const
+    {
+        const int k = j - first;
+        return (k >= 0 && k < kKarrasSpan) ? lds[k] : keys[j];
+    }
+};
+
+__device__ inline int common_prefix(const StagedKeys &keys, int n, int i, int j)
 {
     if (j < 0 || j >= n) return -1;
     const uint32_t a = keys[i], b = keys[j];
@@ -321,15 +338,23 @@ __device__ inline void set_ref(Node *nodes, uint32_t node, int side, uint32_t re
     nodes[node].f[12 + side] = __uint_as_float(ref);
 }
 
-__global__ void __launch_bounds__(256)
-k_karras(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ vals, const uint32_t *__restrict__ count,
+__global__ void __launch_bounds__(kKarrasBlock)
+k_karras(const uint32_t *__restrict__ sorted_keys, const uint32_t *__restrict__ vals, const uint32_t *__restrict__ count,
          uint32_t cap,
          Node *__restrict__ nodes, uint32_t *__restrict__ leaf_parent, uint32_t *__restrict__ node_parent,
          uint32_t *__restrict__ leaf_ids, uint32_t *__restrict__ flags, uint2 *__restrict__ ranges,
          uint32_t *__restrict__ entries, BvhHeader *__restrict__ hdr)
 {
+    __shared__ uint32_t skeys[kKarrasSpan];
     const int n = (int)min(*count, cap);
-    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int first = (int)blockIdx.x * kKarrasBlock - kKarrasHalo;
+    for (int k = threadIdx.x; k < kKarrasSpan; k += kKarrasBlock) {
+        const int j = first + k;
+        skeys[k] = (j >= 0 && j < n) ? sorted_keys[j] : 0u;
+    }
+    __syncthreads();
+    const StagedKeys keys{sorted_keys, skeys, first};
+    const int i = blockIdx.x * kKarrasBlock + threadIdx.x;
     if (i < n) leaf_ids[i] = vals[i];
     if (n == 1 && i == 0) {
         // a single sphere: a root with one leaf and one empty child
@@ -690,7 +715,7 @@ hipError_t launch_build(const splat_spheres &sph, const splat_bvh &bvh, bool ref
             uint32_t *t = ka; ka = kb; kb = t;
             t = va; va = vb; vb = t;
         }
-        hipLaunchKernelGGL(k_karras, dim3(blocks), dim3(256), 0, s, ka, va, sph.count, cap, nodes, leaf_parent,
+        hipLaunchKernelGGL(k_karras, dim3(blocks), dim3(kKarrasBlock), 0, s, ka, va, sph.count, cap, nodes, leaf_parent,
                            node_parent, leaf_ids, flags, ranges, entries, hdr);
     } else {
         hipLaunchKernelGGL(k_header_count, dim3(1), dim3(64), 0, s, sph.count, cap, hdr);
