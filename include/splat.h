@@ -111,6 +111,34 @@ typedef struct splat_bvh {
 } splat_bvh;
 
 /*
+ * Device status word of a BVH: a uint32 at byte SPLAT_BVH_STATUS_OFFSET of
+ * bvh->mem.  splat_build_bvh (also a refit) clears it; the build and every
+ * trace through the BVH OR into it states that no build produces, so a
+ * non-zero word after a run means a corrupt or mismatched hierarchy (the
+ * kernels still end: their walks are bounded and their indices clamped).
+ *   SPLAT_STATUS_CORRUPT  a trace was handed a sphere set smaller than the
+ *                         one the BVH was built over (its references beyond
+ *                         the set are skipped), a tile's breadth-first walk
+ *                         went deeper than any built hierarchy, or the refit
+ *                         met a node range or arrival count that a build
+ *                         never writes
+ *   SPLAT_STATUS_STACK    reserved: a traversal stack that dropped nodes
+ *                         (no walk sets it: their stacks cannot overflow on
+ *                         a built hierarchy, and the per-lane walk's
+ *                         overflow is caught up by the packet walk)
+ * Read it after the stream's work, e.g. with hipMemcpy from
+ * splat_bvh_status_word(bvh).  splat_trace_batched, whose jobs hold their
+ * hierarchies read-only, leaves it alone.
+ */
+#define SPLAT_BVH_STATUS_OFFSET 56
+#define SPLAT_STATUS_CORRUPT 1u
+#define SPLAT_STATUS_STACK 2u
+
+/* Device address of the BVH's status word (host arithmetic only, no GPU
+ * call); NULL for a NULL bvh or mem. */
+uint32_t *splat_bvh_status_word(const splat_bvh *bvh);
+
+/*
  * Trace options.
  *   alpha_stop  stop a ray once its accumulated alpha reaches this value
  *               (0.99 by default; 0 = the paper's first-hit query; > 1 never)
@@ -445,7 +473,8 @@ int splat_trace_batched(const splat_batch_job *jobs, const uint32_t *tile_offset
 /* Thread-local text for the last non-zero status. */
 const char *splat_last_error(void);
 
-/* ABI version (major * 100 + minor): 106 added splat_spheres.axis. */
+/* ABI version (major * 100 + minor): 106 added splat_spheres.axis, 107 the
+ * BVH status word. */
 int splat_version(void);
 
 #ifdef __cplusplus

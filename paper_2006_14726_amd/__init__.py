@@ -8,7 +8,8 @@ front-to-back compositing.  Every step runs in the HIP kernels of
 """
 from . import _lib
 from ._lib import (SPLAT_ALPHA_CONSTANT, SPLAT_ALPHA_SOFT, SPLAT_F16, SPLAT_F32, SPLAT_RADIUS_FOOTPRINT,
-                   SPLAT_RADIUS_INTERVAL, SPLAT_RADIUS_OPACITY, SPLAT_RADIUS_SPHEROID, SplatError)
+                   SPLAT_RADIUS_INTERVAL, SPLAT_RADIUS_OPACITY, SPLAT_RADIUS_SPHEROID, SPLAT_STATUS_CORRUPT,
+                   SPLAT_STATUS_STACK, SplatError)
 from .render import (BVH, Spheres, TraceOptions, accumulate, alloc_bvh, alloc_grads, alloc_spheres, build_bvh,
                      decode_samples, zero_grads,
                      encode_samples, raymarch, render, spheres_from_tensors, trace, trace_backward, trace_noalloc, unproject,
@@ -17,7 +18,7 @@ from .render import (BVH, Spheres, TraceOptions, accumulate, alloc_bvh, alloc_gr
 __all__ = ["BVH", "Spheres", "TraceOptions", "SplatError", "alloc_bvh", "alloc_spheres", "build_bvh", "raymarch", "render",
            "spheres_from_tensors", "trace", "trace_backward", "trace_noalloc", "unproject", "encode_samples", "decode_samples", "accumulate", "unproject_policy", "alloc_grads", "zero_grads", "SPLAT_ALPHA_CONSTANT",
            "SPLAT_RADIUS_FOOTPRINT", "SPLAT_RADIUS_OPACITY", "SPLAT_RADIUS_INTERVAL", "SPLAT_RADIUS_SPHEROID",
-           "SPLAT_ALPHA_SOFT", "SPLAT_F16", "SPLAT_F32", "load_library"]
+           "SPLAT_ALPHA_SOFT", "SPLAT_F16", "SPLAT_F32", "SPLAT_STATUS_CORRUPT", "SPLAT_STATUS_STACK", "load_library"]
 
 
 def load_library():

@@ -12,13 +12,15 @@ SPLAT_F32, SPLAT_F16 = 0, 1
 SPLAT_ALPHA_CONSTANT, SPLAT_ALPHA_SOFT = 0, 1
 SPLAT_WALK_LANE, SPLAT_WALK_PACKET = 0, 1
 SPLAT_RADIUS_FOOTPRINT, SPLAT_RADIUS_OPACITY, SPLAT_RADIUS_INTERVAL, SPLAT_RADIUS_SPHEROID = 0, 1, 2, 3
+SPLAT_STATUS_CORRUPT, SPLAT_STATUS_STACK = 1, 2
+SPLAT_BVH_STATUS_OFFSET = 56
 SPLAT_OP_UNPROJECT, SPLAT_OP_BUILD, SPLAT_OP_TRACE, SPLAT_OP_BACKWARD, SPLAT_OP_BATCHED, SPLAT_OP_ACCUMULATE = range(6)
 
 # every symbol include/splat.h declares
 EXPORTS = ["splat_workspace_bytes", "splat_bvh_bytes", "splat_raymarch", "splat_encode_samples",
            "splat_decode_samples", "splat_accumulate", "splat_unproject", "splat_unproject_policy", "splat_build_bvh", "splat_trace", "splat_trace_backward",
            "splat_trace_batched", "splat_last_error", "splat_version", "splat_trace_noalloc",
-           "splat_trace_noalloc_max_bytes"]
+           "splat_trace_noalloc_max_bytes", "splat_bvh_status_word"]
 
 _P = ctypes.c_void_p
 
@@ -117,6 +119,8 @@ def load() -> ctypes.CDLL:
         lib.splat_last_error.restype = ctypes.c_char_p
         lib.splat_version.argtypes = []
         lib.splat_version.restype = ctypes.c_int
+        lib.splat_bvh_status_word.argtypes = [ctypes.POINTER(splat_bvh)]
+        lib.splat_bvh_status_word.restype = ctypes.c_void_p
         lib.splat_raymarch.argtypes = [ctypes.POINTER(splat_volume), ctypes.POINTER(splat_camera),
                                        ctypes.POINTER(splat_march_opts), _P, _P, _P, _P]
         lib.splat_unproject_policy.argtypes = [ctypes.POINTER(splat_camera), _P, _P, _P,

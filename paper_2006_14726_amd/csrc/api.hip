@@ -118,7 +118,13 @@ int hip_status(hipError_t e, const char *what)
 
 extern "C" {
 
-int splat_version(void) { return 106; }
+int splat_version(void) { return 107; }
+
+uint32_t *splat_bvh_status_word(const splat_bvh *bvh)
+{
+    if (!bvh || !bvh->mem) return nullptr;
+    return reinterpret_cast<uint32_t *>(static_cast<char *>(bvh->mem) + SPLAT_BVH_STATUS_OFFSET);
+}
 
 const char *splat_last_error(void) { return g_err; }
 
@@ -357,6 +363,7 @@ static int trace_common(const splat_bvh *bvh, const splat_spheres *sph, const sp
         return fail(SPLAT_EUNSUPPORTED, "spheroid sets are traced with constant alpha only");
     std::memset(&a, 0, sizeof a);
     a.bvh_mem = bvh->mem;
+    a.status = reinterpret_cast<uint32_t *>(static_cast<char *>(bvh->mem) + SPLAT_BVH_STATUS_OFFSET);
     a.bvh_capacity = bvh->capacity < sph->capacity ? bvh->capacity : sph->capacity;
     a.layout_cap = bvh->capacity;
     a.centre_radius = reinterpret_cast<const float4 *>(sph->centre_radius);

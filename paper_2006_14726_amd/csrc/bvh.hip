@@ -45,6 +45,7 @@ k_bounds_partial(const float4 *__restrict__ cr, const uint32_t *__restrict__ cou
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         hdr->n = n;
         hdr->n_entry = 0u;
+        hdr->status = 0u;
     }
     float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
@@ -517,7 +518,10 @@ k_refit_local(const float4 *__restrict__ cr, const float4 *__restrict__ axis, co
         if ((r & kLeafBit) || r >= n_nodes) continue;  // a leaf entry of the top tree
         const uint2 rng = ranges[r];
         const uint32_t lo = rng.x, hi = min(rng.y, n - 1);
-        if (lo > hi || hi - lo + 1 > (uint32_t)kTreelet) continue;  // only a corrupt hierarchy
+        if (lo > hi || hi - lo + 1 > (uint32_t)kTreelet) {  // only a corrupt hierarchy
+            if (threadIdx.x == 0) flag_status(&hdr->status, SPLAT_STATUS_CORRUPT);
+            continue;
+        }
         __syncthreads();  // the previous treelet's LDS is no longer read
         for (uint32_t k = threadIdx.x; k <= hi - lo; k += kRefitThreads) {
             const uint32_t i = lo + k;
@@ -549,7 +553,10 @@ k_refit_local(const float4 *__restrict__ cr, const float4 *__restrict__ axis, co
             leaf_box(c.x, c.y, c.z, c.w, h, axis, id, bl, bh);
             // (bl, bh) is the box of the child in slot (pp & 1) of node p
             for (;;) {
-                if (p < lo || p > hi) break;  // only a corrupt hierarchy leaves the treelet
+                if (p < lo || p > hi) {  // only a corrupt hierarchy leaves the treelet
+                    flag_status(&hdr->status, SPLAT_STATUS_CORRUPT);
+                    break;
+                }
                 const uint32_t lp = p - lo, side = pp & 1u;
                 for (int k = 0; k < 3; ++k) {
                     lbox[lp][side][k] = bl[k];
@@ -559,7 +566,10 @@ k_refit_local(const float4 *__restrict__ cr, const float4 *__restrict__ axis, co
                                                             __HIP_MEMORY_SCOPE_WORKGROUP);
                 // first arrival: the sibling subtree is not finished and its thread
                 // continues; a count above 1 only occurs in a corrupt hierarchy
-                if (old != 1u) break;
+                if (old != 1u) {
+                    if (old > 1u) flag_status(&hdr->status, SPLAT_STATUS_CORRUPT);
+                    break;
+                }
                 for (int k = 0; k < 3; ++k) {
                     bl[k] = fminf(bl[k], lbox[lp][side ^ 1u][k]);
                     bh[k] = fmaxf(bh[k], lbox[lp][side ^ 1u][3 + k]);
@@ -618,7 +628,10 @@ k_refit_top(const float4 *__restrict__ cr, const float4 *__restrict__ axis, cons
         uint32_t p = pp >> 1;
         while (p < n_nodes) {
             const uint32_t old = __hip_atomic_fetch_add(&flags[p], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
-            if (old != 1u) break;
+            if (old != 1u) {
+                if (old > 1u) flag_status(&hdr->status, SPLAT_STATUS_CORRUPT);  // only a corrupt hierarchy
+                break;
+            }
             const uint32_t up = lift_box(nodes, p, node_parent, axis, hdr);
             if (up == kEmpty) break;
             p = up >> 1;
@@ -668,11 +681,15 @@ k_gather_wide(const uint32_t *__restrict__ count, uint32_t cap, const Node *__re
     for (int k = 0; k < 8; ++k) dst[k] = make_float4(w[4 * k], w[4 * k + 1], w[4 * k + 2], w[4 * k + 3]);
 }
 
-// Header count of a refit (an empty sphere set traces as background); the
-// refit entries of the hierarchy stay.  A build sets it in k_bounds_partial.
+// Header count of a refit (an empty sphere set traces as background) and a
+// clear status word; the refit entries of the hierarchy stay.  A build sets
+// both in k_bounds_partial.
 __global__ void k_header_count(const uint32_t *__restrict__ count, uint32_t cap, BvhHeader *__restrict__ hdr)
 {
-    if (threadIdx.x == 0) hdr->n = min(*count, cap);
+    if (threadIdx.x == 0) {
+        hdr->n = min(*count, cap);
+        hdr->status = 0u;
+    }
 }
 
 hipError_t launch_build(const splat_spheres &sph, const splat_bvh &bvh, bool refit_only, void *ws, hipStream_t s)

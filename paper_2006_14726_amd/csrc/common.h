@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 #include "splat.h"
@@ -133,9 +134,17 @@ struct __align__(256) BvhHeader {
     float scene_hi[3];
     float cen_lo[3];       // bounds of the centres (Morton quantisation)
     float cen_hi[3];
-    uint32_t pad[50];
+    uint32_t status;       // SPLAT_STATUS_* bits: cleared by a build or refit, set by kernels
+    uint32_t pad[49];
 };
 static_assert(sizeof(BvhHeader) == 256, "header size");
+static_assert(offsetof(BvhHeader, status) == SPLAT_BVH_STATUS_OFFSET, "status word offset");
+
+// Marks an impossible device state in the BVH's status word (rare paths only).
+__device__ inline void flag_status(uint32_t *status, uint32_t bits)
+{
+    if (status) atomicOr(status, bits);
+}
 
 __host__ __device__ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 

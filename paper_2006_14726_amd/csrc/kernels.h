@@ -28,6 +28,7 @@ struct TraceArgs {
     const float4 *grad;         // dL/d out
     float *d_rgb, *d_alpha, *d_radius, *d_centre;
     const float4 *axis;         // spheroid sets: (u, h) per sample; NULL for spheres
+    uint32_t *status;           // the BVH's status word (SPLAT_STATUS_* bits)
 };
 
 hipError_t launch_raymarch(const float *vol, int32_t n, double lo, double size, const Cam &cam,

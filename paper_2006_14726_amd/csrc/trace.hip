@@ -189,6 +189,9 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
     // never built cannot send the walk outside it
     const uint32_t n_spheres = min(ufirst(hdr->n), a.bvh_capacity);
     const uint32_t n_nodes = n_spheres > 1 ? n_spheres - 1 : 1;
+    // a hierarchy over more samples than the set holds references samples
+    // beyond it (skipped, and clamped to the nodes of the smaller count)
+
     const int half = a.half;
     const float stop = a.alpha_stop;
     const int soft = a.mode == SPLAT_ALPHA_SOFT;
@@ -328,6 +331,7 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
         for (uint32_t level = 0; n_front > 0; ++level) {
             __builtin_amdgcn_wave_barrier();
             if (level > 40) {
+                if (lane == 0) flag_status(a.status, SPLAT_STATUS_CORRUPT);
                 fb = true;
                 break;
             }
@@ -905,7 +909,8 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
                 const float q0 = q[0], q1 = q[1], q2 = q[2], q3 = q[3], q4 = q[4], q5 = q[5];
                 const uint32_t ref = __float_as_uint(f[24 + sl]);
                 const uint32_t id = ref & ~kLeafBit;
-                // an id beyond the set is never tested (the exact test skips it)
+                // an id beyond the set is never tested (only a corrupt or
+                // mismatched hierarchy has one)
                 bool pass = is_int || (is_leaf && id < n_spheres);
 #pragma unroll
                 for (int pl = 0; pl < 4; ++pl) {
@@ -1210,6 +1215,9 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
         a.out[(size_t)py * a.cam.w + px] = make_float4(C[0], C[1], C[2], A);
         if (a.hits) a.hits[(size_t)py * a.cam.w + px] = n_hit;
     }
+    // a hierarchy over more samples than the set holds references samples
+    // beyond it (skipped, and clamped to the nodes of the smaller count)
+    if (lane == 0 && ufirst(hdr->n) > a.bvh_capacity) flag_status(a.status, SPLAT_STATUS_CORRUPT);
 }
 
 // ---------------------------------------------------------------- kernels
@@ -1303,6 +1311,7 @@ k_trace_batched(const splat_batch_job *__restrict__ jobs, const uint32_t *__rest
         const splat_batch_job &j = jobs[lo];
         TraceArgs a;
         a.bvh_mem = j.bvh_mem;
+        a.status = nullptr;  // a job's hierarchy is read-only here
         a.bvh_capacity = j.bvh_capacity;
         a.layout_cap = j.bvh_capacity;
         const BvhLayout L(a.layout_cap);

@@ -289,6 +289,13 @@ class BVH:
         b.capacity = self.capacity
         return b
 
+    def status(self) -> int:
+        """The BVH's device status word (SPLAT_STATUS_* bits) after the current stream's work."""
+        b = self.struct()
+        addr = _lib.load().splat_bvh_status_word(ctypes.byref(b))
+        off = int(addr) - self.mem.data_ptr()
+        return int(self.mem[off:off + 4].view(torch.int32).item())
+
 
 def alloc_bvh(capacity: int, device) -> BVH:
     nbytes = _lib.load().splat_bvh_bytes(int(capacity))

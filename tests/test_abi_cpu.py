@@ -27,7 +27,23 @@ def test_library_exports_every_declared_symbol():
     lib = _lib.load()
     for name in declared_functions():
         assert hasattr(lib, name), name
-    assert lib.splat_version() == 106
+    assert lib.splat_version() == 107
+
+
+def test_status_word_address_is_host_arithmetic():
+    """The status word lies at a fixed offset of the BVH allocation; its address needs no device."""
+    import ctypes
+    lib = _lib.load()
+    assert lib.splat_bvh_status_word(None) is None
+    b = _lib.splat_bvh()
+    b.mem, b.capacity = 0, 16
+    assert lib.splat_bvh_status_word(ctypes.byref(b)) is None
+    b.mem = 0x10000
+    assert lib.splat_bvh_status_word(ctypes.byref(b)) == 0x10000 + _lib.SPLAT_BVH_STATUS_OFFSET
+    text = open(os.path.join(os.path.dirname(__file__), "..", "include", "splat.h")).read()
+    assert f"#define SPLAT_BVH_STATUS_OFFSET {_lib.SPLAT_BVH_STATUS_OFFSET}" in text
+    assert f"#define SPLAT_STATUS_CORRUPT {_lib.SPLAT_STATUS_CORRUPT}u" in text
+    assert f"#define SPLAT_STATUS_STACK {_lib.SPLAT_STATUS_STACK}u" in text
 
 
 def test_sizes_are_pure_host_functions():
