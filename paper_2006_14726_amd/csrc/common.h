@@ -200,8 +200,9 @@ constexpr int kOrderBuckets = 64;
 constexpr int kOrderMinTiles = 8192;  // fewer tiles: the order is skipped (schedule 0)
 
 // With the frustum walk, the heaviest tiles of the order are traced as four
-// quadrant items each: the first order_split(tiles) tiles, at most 1024.
-__host__ __device__ inline uint32_t order_split(uint32_t tiles) { return tiles / 64 < 1024 ? tiles / 64 : 1024; }
+// quadrant items each: the first order_split(tiles) tiles (1/32 of them, at
+// most 1024).
+__host__ __device__ inline uint32_t order_split(uint32_t tiles) { return tiles / 32 < 1024 ? tiles / 32 : 1024; }
 
 struct TileOrderLayout {
     size_t counts, bucket, order, hist, total;
