@@ -681,6 +681,51 @@ k_gather_wide(const uint32_t *__restrict__ count, uint32_t cap, const Node *__re
     for (int k = 0; k < 8; ++k) dst[k] = make_float4(w[4 * k], w[4 * k + 1], w[4 * k + 2], w[4 * k + 3]);
 }
 
+// The top cut (CutEntry), by one wave once the wide nodes are written: three
+// levels of expansion from the root, sixteen nodes at a time with one slot
+// per lane; sphere slots and the slots of the third level are emitted in
+// lane order.
+__global__ void __launch_bounds__(64)
+k_cut(const uint32_t *__restrict__ count, uint32_t cap, const WideNode *__restrict__ wide, CutEntry *__restrict__ cut,
+      BvhHeader *__restrict__ hdr)
+{
+    __shared__ uint32_t level[2][16];
+    const uint32_t n = min(*count, cap);
+    const uint32_t n_nodes = n > 1 ? n - 1 : 1;
+    const int lane = threadIdx.x;
+    uint32_t n_level = n > 0 ? 1u : 0u, n_out = 0;
+    if (lane == 0) level[0][0] = 0u;  // the root
+    __syncthreads();
+    for (int d = 0; d < 3; ++d) {
+        const uint32_t i = (uint32_t)lane / 4u, sl = (uint32_t)lane & 3u;
+        const bool valid = i < n_level;
+        const uint32_t x = valid ? min(level[d & 1][i], n_nodes - 1) : 0u;
+        const float *f = wide[x].f;
+        const uint32_t kinds = valid ? __float_as_uint(f[31]) : 0u;
+        const bool is_leaf = (kinds >> sl) & 1u, is_int = (kinds >> (4u + sl)) & 1u;
+        const bool expand = is_int && d < 2, emit = is_leaf || (is_int && d == 2);
+        const uint32_t ref = __float_as_uint(f[24 + sl]);
+        const uint64_t me = __ballot(expand), mo = __ballot(emit);
+        const uint64_t below = (1ull << lane) - 1ull;
+        __syncthreads();  // this level's list is read
+        if (expand) level[(d + 1) & 1][__popcll(me & below)] = ref;
+        // at most 64 entries from a built hierarchy; the bound only matters
+        // for a corrupt one
+        const uint32_t at = n_out + (uint32_t)__popcll(mo & below);
+        if (emit && at < kCut) {
+            CutEntry e;
+            for (int k = 0; k < 6; ++k) e.f[k] = f[6 * sl + k];
+            e.f[6] = __uint_as_float(ref);
+            e.f[7] = __uint_as_float((x << 2) | sl);
+            cut[at] = e;
+        }
+        n_out = min(n_out + (uint32_t)__popcll(mo), kCut);
+        n_level = (uint32_t)__popcll(me);
+        __syncthreads();
+    }
+    if (lane == 0) hdr->n_cut = n_out;
+}
+
 // Header count of a refit (an empty sphere set traces as background) and a
 // clear status word; the refit entries of the hierarchy stay.  A build sets
 // both in k_bounds_partial.
@@ -745,6 +790,8 @@ hipError_t launch_build(const splat_spheres &sph, const splat_bvh &bvh, bool ref
                        leaf_parent, node_parent, leaf_ids, flags, entries, hdr);
     hipLaunchKernelGGL(k_gather_wide, dim3(blocks), dim3(256), 0, s, sph.count, cap, nodes,
                        reinterpret_cast<WideNode *>(mem + L.wide));
+    hipLaunchKernelGGL(k_cut, dim3(1), dim3(64), 0, s, sph.count, cap, reinterpret_cast<const WideNode *>(mem + L.wide),
+                       reinterpret_cast<CutEntry *>(mem + L.cut), hdr);
     return hipGetLastError();
 }
 

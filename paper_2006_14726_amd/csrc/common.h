@@ -127,6 +127,19 @@ struct __align__(128) WideNode {
     float f[32];
 };
 
+// Top cut of the hierarchy: the slots met by expanding the root's wide node
+// and the internal slots below it down to three wide levels (the slots of
+// the wide nodes at depth 2, and any sphere slot above them), at most 64.
+// A tile's breadth-first walk starts from the cut with one load instead of
+// three dependent node fetches.
+//   f[0..5]: the slot's words (a box, or a sphere's centre, radius, opacity, h)
+//   f[6]:    its reference (node index, or kLeafBit | sphere id)
+//   f[7]:    its origin, (wide node << 2) | slot (for the exact test)
+constexpr uint32_t kCut = 64;
+struct __align__(32) CutEntry {
+    float f[8];
+};
+
 struct __align__(256) BvhHeader {
     uint32_t n;            // spheres at build time
     uint32_t n_entry;      // refit: entries of the top tree (treelet roots and leaves under top nodes)
@@ -135,7 +148,8 @@ struct __align__(256) BvhHeader {
     float cen_lo[3];       // bounds of the centres (Morton quantisation)
     float cen_hi[3];
     uint32_t status;       // SPLAT_STATUS_* bits: cleared by a build or refit, set by kernels
-    uint32_t pad[49];
+    uint32_t n_cut;        // entries of the top cut (CutEntry)
+    uint32_t pad[48];
 };
 static_assert(sizeof(BvhHeader) == 256, "header size");
 static_assert(offsetof(BvhHeader, status) == SPLAT_BVH_STATUS_OFFSET, "status word offset");
@@ -150,7 +164,7 @@ __host__ __device__ inline size_t align256(size_t x) { return (x + 255) & ~(size
 
 // Offsets inside splat_bvh.mem.
 struct BvhLayout {
-    size_t header, nodes, leaf_parent, node_parent, leaf_ids, flags, ranges, entries, wide, total;
+    size_t header, nodes, leaf_parent, node_parent, leaf_ids, flags, ranges, entries, wide, cut, total;
     __host__ __device__ explicit BvhLayout(uint32_t cap)
     {
         const size_t c = cap < 1 ? 1 : cap;
@@ -163,7 +177,8 @@ struct BvhLayout {
         ranges = align256(flags + c * 4);       // first/last sorted leaf of each internal node
         entries = align256(ranges + c * 8);     // refit entries of the top tree (at most 2 per top node)
         wide = align256(entries + c * 8);       // WideNode per internal node (what the trace reads)
-        total = align256(wide + c * sizeof(WideNode));
+        cut = align256(wide + c * sizeof(WideNode));
+        total = align256(cut + kCut * sizeof(CutEntry));
     }
 };
 

@@ -326,6 +326,57 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
         uint32_t cur = 0, n_front = any ? 1u : 0u;
         if (lane == 0) L.fr.front[0][0] = 0u;  // the root
         fb = false;
+        // the top cut, one entry per lane, in place of the first three levels
+        const uint32_t n_cut = any ? min(ufirst(hdr->n_cut), kCut) : 0u;
+        if (n_cut > 0) {
+            const CutEntry *cut = reinterpret_cast<const CutEntry *>(reinterpret_cast<const char *>(a.bvh_mem) +
+                                                                     BvhLayout(a.layout_cap).cut);
+            const bool valid = (uint32_t)lane < n_cut;
+            const float4 e0 = valid ? reinterpret_cast<const float4 *>(cut + lane)[0] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            const float4 e1 = valid ? reinterpret_cast<const float4 *>(cut + lane)[1] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            const float q0 = e0.x, q1 = e0.y, q2 = e0.z, q3 = e0.w, q4 = e1.x, q5 = e1.y;
+            const uint32_t ref = __float_as_uint(e1.z), origin = __float_as_uint(e1.w);
+            const bool is_leaf = valid && (ref & kLeafBit) != 0u, is_int = valid && (ref & kLeafBit) == 0u;
+            bool pass = is_leaf || is_int;
+#pragma unroll
+            for (int pl = 0; pl < 4; ++pl) {
+                // box: its corner farthest along the normal; sphere: its centre, moved r along it
+                const float bx = fmaf(pp[pl][0], q3, fmaf(pn[pl][0], q0, pc[pl]));
+                const float vb = fmaf(pp[pl][2], q5, fmaf(pn[pl][2], q2, fmaf(pp[pl][1], q4, fmaf(pn[pl][1], q1, bx))));
+                const float vs = fmaf(pp[pl][0] + pn[pl][0], q0, fmaf(pp[pl][1] + pn[pl][1], q1,
+                                 fmaf(pp[pl][2] + pn[pl][2], q2, pc[pl]))) + q3;
+                pass = pass && (is_leaf ? vs : vb) >= -slack;
+            }
+            const uint64_t mi = __ballot(pass && is_int), ml = __ballot(pass && is_leaf);
+            const uint32_t below_i = (uint32_t)__popcll(mi & ((1ull << lane) - 1ull));
+            const uint32_t below_l = (uint32_t)__popcll(ml & ((1ull << lane) - 1ull));
+            if (pass && is_int && below_i < kFront) L.fr.front[0][below_i] = ref;
+            if (pass && is_leaf && below_l < kTileCand) {
+                // the candidate's screen disc and depth range, in float with
+                // outward slack (relative 2^-12 on rho, 2^-18 absolute in tangent
+                // units, 2^-20 relative on depths plus the margin)
+                const float ox = q0 - eye.of[0], oy = q1 - eye.of[1], oz = q2 - eye.of[2];
+                const float x = ox * bR[0] + oy * bR[1] + oz * bR[2];
+                const float y = ox * bU[0] + oy * bU[1] + oz * bU[2];
+                const float z = ox * bF[0] + oy * bF[1] + oz * bF[2];
+                const float dist = sqrtf(ox * ox + oy * oy + oz * oz);
+                const float zr = z - q3;
+                float X = 0.0f, Y = 0.0f, rho2 = INFINITY;
+                if (zr > 0x1p-10f * dist) {
+                    X = x / z;
+                    Y = y / z;
+                    const float rho = q3 * sqrtf(1.0f + X * X + Y * Y) / zr;
+                    const float rs = rho * (1.0f + 0x1p-12f) + 0x1p-18f * (1.0f + fabsf(X) + fabsf(Y));
+                    rho2 = rs * rs;
+                }
+                const float tmin = (dist - q3) * (1.0f - 0x1p-20f) - slack;
+                const float tmax = dist * (1.0f + 0x1p-20f) + slack;
+                L.fr.disc[below_l] = make_float4(X, Y, rho2, tmin);
+                L.fr.far_ref[below_l] = make_float2(tmax, __uint_as_float(origin));
+            }
+            n_front = (uint32_t)__popcll(mi);
+            n_cand = (uint32_t)__popcll(ml);
+        }
         // a hierarchy over 62-bit (code, position) keys is at most 64 binary
         // levels deep; more levels only occur in a corrupt one
         for (uint32_t level = 0; n_front > 0; ++level) {
