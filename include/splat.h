@@ -458,14 +458,18 @@ int splat_trace_backward(const splat_bvh *bvh, const splat_spheres *sph, const s
 
 /*
  * Batched trace: every job of `jobs` (device array of n_jobs splat_batch_job)
- * in ONE persistent launch; waves take tiles from an atomic work counter.
- * Each job's output equals splat_trace's bit for bit.
+ * in ONE launch: either persistent waves that take tiles from an atomic work
+ * counter, or (max_waves = SPLAT_BATCH_GRID) one workgroup per (job, tile),
+ * the job found by a binary search of the tile offsets.  Each job's output
+ * equals splat_trace's bit for bit.
  *   ws          device, >= splat_workspace_bytes(SPLAT_OP_BATCHED, n_jobs, 0, 0)
  *   total_tiles sum over jobs of ceil(w / tile_w) * ceil(h / tile_h)
- *   max_waves   resident waves to launch (0 = one per SIMD slot of the device)
+ *   max_waves   resident waves to launch (0 = one per SIMD slot of the
+ *               device), or SPLAT_BATCH_GRID
  * The host passes per-job tile offsets through `tile_offsets` (device
  * uint32[n_jobs + 1], exclusive prefix of tiles per job).
  */
+#define SPLAT_BATCH_GRID (-1)
 int splat_trace_batched(const splat_batch_job *jobs, const uint32_t *tile_offsets, int32_t n_jobs,
                         uint32_t total_tiles, const splat_trace_opts *opts, int32_t max_waves, void *ws,
                         size_t ws_bytes, void *stream);

@@ -13,6 +13,7 @@ SPLAT_ALPHA_CONSTANT, SPLAT_ALPHA_SOFT = 0, 1
 SPLAT_WALK_LANE, SPLAT_WALK_PACKET = 0, 1
 SPLAT_RADIUS_FOOTPRINT, SPLAT_RADIUS_OPACITY, SPLAT_RADIUS_INTERVAL, SPLAT_RADIUS_SPHEROID = 0, 1, 2, 3
 SPLAT_STATUS_CORRUPT, SPLAT_STATUS_STACK = 1, 2
+SPLAT_BATCH_GRID = -1
 SPLAT_BVH_STATUS_OFFSET = 56
 SPLAT_OP_UNPROJECT, SPLAT_OP_BUILD, SPLAT_OP_TRACE, SPLAT_OP_BACKWARD, SPLAT_OP_BATCHED, SPLAT_OP_ACCUMULATE = range(6)
 

@@ -16,6 +16,7 @@ from dataclasses import replace
 
 import torch
 
+from . import _lib
 from .render import BVH, Spheres, TraceOptions, trace
 
 TRACE_CANDIDATES = [(k, tile, sched, walk) for k in (6, 8) for tile in ((8, 8), (16, 4)) for sched in (0, 2)
@@ -92,7 +93,7 @@ def tune_trace(bvh: BVH, sph: Spheres, cam, base: TraceOptions | None = None, re
 
 
 def tune_batched(renderer, reps: int = 3, use_cache: bool = True) -> dict:
-    """Fastest (kbuf, tile, walk, resident waves) for a batched renderer; applies it to the renderer."""
+    """Fastest (kbuf, tile, walk, resident waves or one grid) for a batched renderer; applies it to the renderer."""
     dev = renderer.device
     cus = torch.cuda.get_device_properties(dev).multi_processor_count
     key = f"{_arch(dev)}|batched|jobs{_bucket(renderer.n_jobs)}|rays{_bucket(renderer.rays)}"
@@ -105,9 +106,11 @@ def tune_batched(renderer, reps: int = 3, use_cache: bool = True) -> dict:
     timings = {}
     for k in (6, 8):
         for tile in ((8, 8), (16, 4)):
-            for walk in (0, 1):
-                for wpc in WAVES_PER_CU:
-                    rec = {"kbuf": k, "tile": list(tile), "walk": walk, "waves": wpc * cus}
+            for walk in (0, 1, 2):
+                # persistent waves per CU, or one workgroup per (job, tile)
+                for wpc in WAVES_PER_CU + (None,):
+                    waves = wpc * cus if wpc else _lib.SPLAT_BATCH_GRID
+                    rec = {"kbuf": k, "tile": list(tile), "walk": walk, "waves": waves}
                     _apply(renderer, rec)
                     timings[json.dumps(rec)] = _time(renderer.trace_batched, reps)
     best = min(timings, key=timings.get)

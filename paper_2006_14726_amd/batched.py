@@ -1,8 +1,9 @@
-"""Many client frames, each with several target views, in one persistent trace.
+"""Many client frames, each with several target views, in one trace launch.
 
 Every frame is unprojected and its LBVH built with the plain entry points;
-then every (frame, view) job is traced by ONE splat_trace_batched launch,
-whose waves pull tiles from an atomic counter until the batch is drained.
+then every (frame, view) job is traced by ONE splat_trace_batched launch:
+persistent waves that pull tiles from an atomic counter until the batch is
+drained, or (waves = GRID) one workgroup per (job, tile).
 The whole sequence can be captured once in a HIP graph and replayed.
 Outputs equal the per-job splat_trace outputs bit for bit.
 """
@@ -15,6 +16,7 @@ import numpy as np
 import torch
 
 from . import _lib
+from ._lib import SPLAT_BATCH_GRID as GRID
 from .render import (BVH, Spheres, TraceOptions, _ptr, _stream, alloc_bvh, alloc_spheres, build_bvh, trace,
                      unproject)
 

@@ -492,7 +492,10 @@ int splat_trace_batched(const splat_batch_job *jobs, const uint32_t *tile_offset
     splat_trace_opts o;
     if ((rc = resolve_opts(opts, &o))) return rc;
     if (!ws || ws_bytes < 256) return fail(SPLAT_ENOSPC, "batched workspace needs 256 bytes");
-    if (max_waves < 0) return fail(SPLAT_EINVAL, "max_waves must be >= 0");
+    if (max_waves < 0 && max_waves != SPLAT_BATCH_GRID)
+        return fail(SPLAT_EINVAL, "max_waves must be >= 0 or SPLAT_BATCH_GRID");
+    if (max_waves == SPLAT_BATCH_GRID && total_tiles > 0x7fffffffu)
+        return fail(SPLAT_EINVAL, "a grid launch holds at most 2^31 - 1 tiles");
     if ((rc = check_device())) return rc;
     int waves = max_waves;
     if (waves == 0) {

@@ -1336,6 +1336,46 @@ __global__ void __launch_bounds__(64) k_trace(TraceArgs a, int tiles_x, int tile
     trace_tile<K, BWD, WALK, SPH>(a, nodes, hdr, tx, ty, lds, rg);
 }
 
+// Trace arguments of one job of a batch.
+template <int K, int WALK>
+__device__ inline TraceArgs batch_args(const splat_batch_job &j, float alpha_stop, int mode, double t_max, int tile_w,
+                                       int tile_h)
+{
+    TraceArgs a;
+    a.bvh_mem = j.bvh_mem;
+    a.status = nullptr;  // a job's hierarchy is read-only here
+    a.bvh_capacity = j.bvh_capacity;
+    a.layout_cap = j.bvh_capacity;
+    a.centre_radius = reinterpret_cast<const float4 *>(j.centre_radius);
+    a.axis = nullptr;
+    a.rgba = j.rgba;
+    a.half = j.rgba_dtype == SPLAT_F16;
+    for (int k = 0; k < 3; ++k) {
+        a.cam.eye[k] = j.camera.eye[k];
+        a.cam.fwd[k] = j.camera.forward[k];
+        a.cam.right[k] = j.camera.right[k];
+        a.cam.up[k] = j.camera.up[k];
+    }
+    a.cam.tan_half = j.camera.tan_half_fov_y;
+    a.cam.w = j.camera.width;
+    a.cam.h = j.camera.height;
+    a.alpha_stop = alpha_stop;
+    a.mode = mode;
+    a.t_max = t_max;
+    a.kbuf = K;
+    a.tile_w = tile_w;
+    a.tile_h = tile_h;
+    a.schedule = 0;
+    a.walk = WALK;
+    a.order = nullptr;
+    a.order_items = 0;
+    a.out = reinterpret_cast<float4 *>(j.out_rgba);
+    a.hits = j.out_hits;
+    a.grad = nullptr;
+    a.d_rgb = a.d_alpha = a.d_radius = a.d_centre = nullptr;
+    return a;
+}
+
 // Persistent batched trace: waves pull tiles from one atomic counter until
 // the batch is drained.  A wave claims its next tile before it traces the
 // current one, so the atomic's round trip overlaps the tile's first node
@@ -1402,6 +1442,34 @@ k_trace_batched(const splat_batch_job *__restrict__ jobs, const uint32_t *__rest
                              t % tiles_x, t / tiles_x, lds, whole);
         item = ufirst(claim);
     }
+}
+
+// Batched trace as one grid: workgroup b traces item b, the tile b minus the
+// offset of its job (the last offset <= b, by binary search).  No loop and no
+// counter: the kernel is compiled like the plain one.
+template <int K, int WALK>
+__global__ void __launch_bounds__(64)
+k_trace_grid(const splat_batch_job *__restrict__ jobs, const uint32_t *__restrict__ tile_offsets, int n_jobs,
+             uint32_t total_tiles, float alpha_stop, int mode, double t_max, int tile_w, int tile_h)
+{
+    __shared__ WaveLds<WALK == SPLAT_WALK_FRUSTUM> lds;
+    const uint32_t item = blockIdx.x;
+    if (item >= total_tiles) return;
+    int lo = 0, hi = n_jobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (tile_offsets[mid] <= item) lo = mid;
+        else hi = mid - 1;
+    }
+    const splat_batch_job &j = jobs[lo];
+    const TraceArgs a = batch_args<K, WALK>(j, alpha_stop, mode, t_max, tile_w, tile_h);
+    const BvhLayout L(a.layout_cap);
+    const int tiles_x = (a.cam.w + tile_w - 1) / tile_w;
+    const int t = (int)(item - min(tile_offsets[lo], item));
+    const char *mem = static_cast<const char *>(j.bvh_mem);
+    const TileRegion whole = {0, tile_w, 0, tile_h};
+    trace_tile<K, false, WALK>(a, reinterpret_cast<const WideNode *>(mem + L.wide), reinterpret_cast<const BvhHeader *>(mem),
+                               t % tiles_x, t / tiles_x, lds, whole);
 }
 
 __global__ void k_zero_counter(uint32_t *c)
@@ -1472,6 +1540,32 @@ hipError_t launch_trace_batched(const splat_batch_job *jobs, const uint32_t *til
                                 uint32_t total_tiles, const splat_trace_opts &o, int32_t waves, void *ws,
                                 hipStream_t s)
 {
+    if (waves < 0) {
+        // one workgroup per (job, tile)
+        if (total_tiles == 0) return hipSuccess;
+        const dim3 grid(total_tiles), block(64);
+#define SPLAT_GRID(KK)                                                                                           \
+    if (o.walk == SPLAT_WALK_PACKET)                                                                             \
+        hipLaunchKernelGGL((k_trace_grid<KK, SPLAT_WALK_PACKET>), grid, block, 0, s, jobs, tile_offsets, n_jobs,   \
+                           total_tiles, o.alpha_stop, o.mode, o.t_max, o.tile_w, o.tile_h);                      \
+    else if (o.walk == SPLAT_WALK_FRUSTUM)                                                                       \
+        hipLaunchKernelGGL((k_trace_grid<KK, SPLAT_WALK_FRUSTUM>), grid, block, 0, s, jobs, tile_offsets, n_jobs,  \
+                           total_tiles, o.alpha_stop, o.mode, o.t_max, o.tile_w, o.tile_h);                      \
+    else                                                                                                         \
+        hipLaunchKernelGGL((k_trace_grid<KK, SPLAT_WALK_LANE>), grid, block, 0, s, jobs, tile_offsets, n_jobs,     \
+                           total_tiles, o.alpha_stop, o.mode, o.t_max, o.tile_w, o.tile_h);
+        switch (o.kbuf) {
+        case 1: SPLAT_GRID(1) break;
+        case 2: SPLAT_GRID(2) break;
+        case 4: SPLAT_GRID(4) break;
+        case 6: SPLAT_GRID(6) break;
+        case 8: SPLAT_GRID(8) break;
+        case 16: SPLAT_GRID(16) break;
+        default: return hipErrorInvalidValue;
+        }
+#undef SPLAT_GRID
+        return hipGetLastError();
+    }
     uint32_t *counter = static_cast<uint32_t *>(ws);
     hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, s, counter);
     const dim3 grid(waves), block(64);

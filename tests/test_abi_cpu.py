@@ -44,6 +44,7 @@ def test_status_word_address_is_host_arithmetic():
     assert f"#define SPLAT_BVH_STATUS_OFFSET {_lib.SPLAT_BVH_STATUS_OFFSET}" in text
     assert f"#define SPLAT_STATUS_CORRUPT {_lib.SPLAT_STATUS_CORRUPT}u" in text
     assert f"#define SPLAT_STATUS_STACK {_lib.SPLAT_STATUS_STACK}u" in text
+    assert f"#define SPLAT_BATCH_GRID ({_lib.SPLAT_BATCH_GRID})" in text
 
 
 def test_sizes_are_pure_host_functions():

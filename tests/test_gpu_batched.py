@@ -50,8 +50,12 @@ def assert_same(a, b):
             assert torch.equal(oa, ob) and torch.equal(ha, hb)
 
 
+GRID = -1  # one workgroup per (job, tile)
+
+
 @pytest.mark.parametrize("kbuf,tile,waves,walk", [(6, (8, 8), 0, 0), (8, (8, 8), 0, 1), (4, (16, 4), 97, 0),
-                                                  (1, (32, 2), 3, 1), (6, (8, 8), 0, 2), (2, (16, 4), 97, 2)])
+                                                  (1, (32, 2), 3, 1), (6, (8, 8), 0, 2), (2, (16, 4), 97, 2),
+                                                  (6, (8, 8), GRID, 2), (8, (8, 8), GRID, 0), (1, (32, 2), GRID, 1)])
 def test_batched_equals_sequential(sp, small_batch, kbuf, tile, waves, walk):
     r = make_renderer(sp, small_batch, half=True, opts=sp.TraceOptions(kbuf=kbuf, tile=tile, walk=walk), waves=waves)
     assert r.n_jobs >= 7
@@ -125,7 +129,7 @@ def test_autotuner_picks_a_valid_schedule(sp, small_batch, tmp_path, monkeypatch
     r.run_sequential()
     ref_out = snapshot(r)
     best = autotune.tune_batched(r)
-    assert best["waves"] > 0
+    assert best["waves"] > 0 or best["waves"] == GRID
     r.run()
     torch.cuda.synchronize()
     assert_same(snapshot(r), ref_out)
