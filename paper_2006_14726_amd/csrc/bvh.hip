@@ -597,18 +597,37 @@ k_refit_local(const float4 *__restrict__ cr, const float4 *__restrict__ axis, co
 // 1 are visible across the kernel boundary.
 constexpr int kTopThreads = 1024;
 
+// A top tree of at most 3/4 of kTopHash nodes climbs in LDS: a hash table
+// keyed by node index holds each node's arrival count and the box of its
+// first arrival, so the handshake needs no global round trip; each thread
+// loads the next parent before its handshake.  Larger top trees climb through
+// the global arrival counters.
+constexpr uint32_t kTopHash = 2048;
+
 __global__ void __launch_bounds__(kTopThreads)
 k_refit_top(const float4 *__restrict__ cr, const float4 *__restrict__ axis, const void *__restrict__ rgba, int half,
             const uint32_t *__restrict__ count, uint32_t cap, Node *nodes, const uint32_t *__restrict__ leaf_parent,
             const uint32_t *__restrict__ node_parent, const uint32_t *__restrict__ leaf_ids, uint32_t *flags,
             const uint32_t *__restrict__ entries, BvhHeader *hdr)
 {
+    __shared__ uint32_t hkey[kTopHash], hcnt[kTopHash];
+    __shared__ float hbox[kTopHash][2][6];
     const uint32_t n = min(*count, cap);
     const uint32_t n_nodes = n > 1 ? n - 1 : 1;
     const uint32_t m = min(hdr->n_entry, 2 * cap);
+    // m entries hang from m - 1 top nodes
+    const bool in_lds = m <= kTopHash / 4 * 3;
+    if (in_lds) {
+        for (uint32_t i = threadIdx.x; i < kTopHash; i += kTopThreads) {
+            hkey[i] = kEmpty;
+            hcnt[i] = 0u;
+        }
+        __syncthreads();
+    }
     for (uint32_t e_i = threadIdx.x; e_i < m; e_i += kTopThreads) {
         const uint32_t e = entries[e_i];
         uint32_t pp;
+        float bl[3], bh[3];
         if (e & kLeafBit) {
             const uint32_t j = e & ~kLeafBit;
             if (j >= n) continue;
@@ -618,22 +637,72 @@ k_refit_top(const float4 *__restrict__ cr, const float4 *__restrict__ axis, cons
             pp = leaf_parent[j];
             if ((pp >> 1) >= n_nodes) continue;
             float *sl = nodes[pp >> 1].f + 6 * (pp & 1u);
+            const float h = axis ? axis[id].w : 0.0f;
             sl[0] = c.x; sl[1] = c.y; sl[2] = c.z; sl[3] = c.w; sl[4] = sphere_alpha_a(rgba, half, id);
-            sl[5] = axis ? axis[id].w : 0.0f;
+            sl[5] = h;
+            if (in_lds) leaf_box(c.x, c.y, c.z, c.w, h, axis, id, bl, bh);
         } else {
             if (e >= n_nodes) continue;
             pp = node_parent[e];
             if (pp == kEmpty) continue;  // the root treelet: phase 1 wrote the header
+            if (in_lds) {
+                // the treelet root's box, written into its parent's slot by phase 1
+                const float *sl = nodes[pp >> 1].f + 6 * (pp & 1u);
+                for (int k = 0; k < 3; ++k) { bl[k] = sl[k]; bh[k] = sl[3 + k]; }
+            }
         }
         uint32_t p = pp >> 1;
+        if (!in_lds) {
+            while (p < n_nodes) {
+                const uint32_t old = __hip_atomic_fetch_add(&flags[p], 1u, __ATOMIC_ACQ_REL,
+                                                            __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (old != 1u) {
+                    if (old > 1u) flag_status(&hdr->status, SPLAT_STATUS_CORRUPT);  // only a corrupt hierarchy
+                    break;
+                }
+                const uint32_t up = lift_box(nodes, p, node_parent, axis, hdr);
+                if (up == kEmpty) break;
+                p = up >> 1;
+            }
+            continue;
+        }
         while (p < n_nodes) {
-            const uint32_t old = __hip_atomic_fetch_add(&flags[p], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
+            const uint32_t up = node_parent[p];
+            uint32_t h = (p * 2654435761u) >> 21, key = kEmpty;
+            for (uint32_t probe = 0; probe < kTopHash; ++probe) {
+                key = atomicCAS(&hkey[h], kEmpty, p);
+                if (key == kEmpty || key == p) break;
+                h = (h + 1u) & (kTopHash - 1u);
+            }
+            if (key != kEmpty && key != p) {  // a full table: only a corrupt hierarchy
+                flag_status(&hdr->status, SPLAT_STATUS_CORRUPT);
+                break;
+            }
+            const uint32_t side = pp & 1u;
+            for (int k = 0; k < 3; ++k) {
+                hbox[h][side][k] = bl[k];
+                hbox[h][side][3 + k] = bh[k];
+            }
+            // the handshake orders the LDS boxes; the global slots written
+            // below are read by later kernels only
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+            const uint32_t old = __hip_atomic_fetch_add(&hcnt[h], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             if (old != 1u) {
                 if (old > 1u) flag_status(&hdr->status, SPLAT_STATUS_CORRUPT);  // only a corrupt hierarchy
                 break;
             }
-            const uint32_t up = lift_box(nodes, p, node_parent, axis, hdr);
-            if (up == kEmpty) break;
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+            for (int k = 0; k < 3; ++k) {
+                bl[k] = fminf(bl[k], hbox[h][side ^ 1u][k]);
+                bh[k] = fmaxf(bh[k], hbox[h][side ^ 1u][3 + k]);
+            }
+            if (up == kEmpty) {
+                for (int k = 0; k < 3; ++k) { hdr->scene_lo[k] = bl[k]; hdr->scene_hi[k] = bh[k]; }
+                break;
+            }
+            float *sl = nodes[up >> 1].f + 6 * (up & 1u);
+            sl[0] = bl[0]; sl[1] = bl[1]; sl[2] = bl[2]; sl[3] = bh[0]; sl[4] = bh[1]; sl[5] = bh[2];
+            pp = up;
             p = up >> 1;
         }
     }

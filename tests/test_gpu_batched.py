@@ -133,3 +133,35 @@ def test_autotuner_picks_a_valid_schedule(sp, small_batch, tmp_path, monkeypatch
     r.run()
     torch.cuda.synchronize()
     assert_same(snapshot(r), ref_out)
+
+
+def test_full_size_job_against_oracle(sp):
+    """A batch job at the batched workload's largest size, a 2048^2 source of the client volume
+    traced into 1920x1080, in the grid launch with the frustum walk: one pixel per 32x32 tile
+    against the oracle's trace of its own unprojection of the same image."""
+    from paper_2006_14726_amd.batched import GRID
+    w = synth.Workload("client-2048sq", 256, 64, 2, 2048, 2048, 1920, 1080, 10.0, 3.0)
+    rgba, depth, src, dst = synth.source_image(w)
+    print("full-size batched job", flush=True)
+    r = make_renderer(sp, [(rgba, depth, src, [dst])], half=True, opts=sp.TraceOptions(walk=2), waves=GRID)
+    r.run()
+    torch.cuda.synchronize()
+    ocr, ocol, _ = oracle.unproject(src, rgba, depth, 1.0, True)
+    s = r.spheres[0]
+    n = s.n()
+    assert n == ocr.shape[0] > 2_000_000
+    assert np.array_equal(ocol.view(np.uint16), s.rgba[:n].cpu().numpy().view(np.uint16))
+    assert np.abs(ocr.view(np.int32).astype(np.int64) - s.centre_radius[:n].cpu().numpy().view(np.int32)).max() <= 1
+    img, hits = r.outputs[0][0]
+    rng = np.random.default_rng(8)
+    ty, tx = np.meshgrid(np.arange(0, dst.height, 32), np.arange(0, dst.width, 32), indexing="ij")
+    px = np.minimum(tx + rng.integers(0, 32, tx.shape), dst.width - 1)
+    py = np.minimum(ty + rng.integers(0, 32, ty.shape), dst.height - 1)
+    pix = np.unique((py * dst.width + px).ravel())
+    g = img.cpu().numpy().reshape(-1, 4)[pix]
+    h = hits.cpu().numpy().reshape(-1)[pix]
+    # the oracle traces its own unprojection (equal to the GPU's to 1 ulp in the radius)
+    st = compare(g, h, oracle.render(ocr, ocol, dst, pixels=pix))
+    print(f"  {st['pixels']} pixels: max err {st['max_err']:.2e}, exempt {st['exempt']}", flush=True)
+    assert_parity(st, exempt_frac=1e-4, context="2048^2 batched job")
+    assert st["hits_checked"] > 500
