@@ -354,18 +354,21 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
             if (pass && is_leaf && below_l < kTileCand) {
                 // the candidate's screen disc and depth range, in float with
                 // outward slack (relative 2^-12 on rho, 2^-18 absolute in tangent
-                // units, 2^-20 relative on depths plus the margin)
+                // units, 2^-20 relative on depths plus the margin); the hardware
+                // reciprocal and square root, within a few ulps on normal
+                // operands, stay far inside it
                 const float ox = q0 - eye.of[0], oy = q1 - eye.of[1], oz = q2 - eye.of[2];
                 const float x = ox * bR[0] + oy * bR[1] + oz * bR[2];
                 const float y = ox * bU[0] + oy * bU[1] + oz * bU[2];
                 const float z = ox * bF[0] + oy * bF[1] + oz * bF[2];
-                const float dist = sqrtf(ox * ox + oy * oy + oz * oz);
+                const float dist = __builtin_amdgcn_sqrtf(ox * ox + oy * oy + oz * oz);
                 const float zr = z - q3;
                 float X = 0.0f, Y = 0.0f, rho2 = INFINITY;
-                if (zr > 0x1p-10f * dist) {
-                    X = x / z;
-                    Y = y / z;
-                    const float rho = q3 * sqrtf(1.0f + X * X + Y * Y) / zr;
+                if (zr > 0x1p-10f * dist && zr > 0x1p-100f) {
+                    const float iz = __builtin_amdgcn_rcpf(z);
+                    X = x * iz;
+                    Y = y * iz;
+                    const float rho = q3 * __builtin_amdgcn_sqrtf(1.0f + X * X + Y * Y) * __builtin_amdgcn_rcpf(zr);
                     const float rs = rho * (1.0f + 0x1p-12f) + 0x1p-18f * (1.0f + fabsf(X) + fabsf(Y));
                     rho2 = rs * rs;
                 }
@@ -414,18 +417,21 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
                 if (pass && is_leaf && n_cand + below_l < kTileCand) {
                     // the candidate's screen disc and depth range, in float with
                     // outward slack (relative 2^-12 on rho, 2^-18 absolute in tangent
-                    // units, 2^-20 relative on depths plus the margin)
+                    // units, 2^-20 relative on depths plus the margin); the hardware
+                    // reciprocal and square root, within a few ulps on normal
+                    // operands, stay far inside it
                     const float ox = q0 - eye.of[0], oy = q1 - eye.of[1], oz = q2 - eye.of[2];
                     const float x = ox * bR[0] + oy * bR[1] + oz * bR[2];
                     const float y = ox * bU[0] + oy * bU[1] + oz * bU[2];
                     const float z = ox * bF[0] + oy * bF[1] + oz * bF[2];
-                    const float dist = sqrtf(ox * ox + oy * oy + oz * oz);
+                    const float dist = __builtin_amdgcn_sqrtf(ox * ox + oy * oy + oz * oz);
                     const float zr = z - q3;
                     float X = 0.0f, Y = 0.0f, rho2 = INFINITY;
-                    if (zr > 0x1p-10f * dist) {
-                        X = x / z;
-                        Y = y / z;
-                        const float rho = q3 * sqrtf(1.0f + X * X + Y * Y) / zr;
+                    if (zr > 0x1p-10f * dist && zr > 0x1p-100f) {
+                        const float iz = __builtin_amdgcn_rcpf(z);
+                        X = x * iz;
+                        Y = y * iz;
+                        const float rho = q3 * __builtin_amdgcn_sqrtf(1.0f + X * X + Y * Y) * __builtin_amdgcn_rcpf(zr);
                         const float rs = rho * (1.0f + 0x1p-12f) + 0x1p-18f * (1.0f + fabsf(X) + fabsf(Y));
                         rho2 = rs * rs;
                     }
