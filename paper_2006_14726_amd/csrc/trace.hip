@@ -1044,12 +1044,15 @@ __device__ void trace_tile(const TraceArgs &a, const WideNode *__restrict__ node
                     const float xb = fmaf(ha, ux, x), yb = fmaf(ha, uy, y), zb = fmaf(ha, uz, z);
                     const float zr = fminf(za, zb) - rr;
                     float Xa = 0.0f, Ya = 0.0f, rho2 = INFINITY, dX = 0.0f, dY = 0.0f;
-                    if (zr > 0x1p-10f * dist) {
-                        Xa = xa / za;
-                        Ya = ya / za;
-                        const float Xb = xb / zb, Yb = yb / zb;
+                    if (zr > 0x1p-10f * dist && zr > 0x1p-100f) {
+                        // the hardware reciprocal and square root (a few ulps on
+                        // normal operands) stay far inside the slack below
+                        const float ia = __builtin_amdgcn_rcpf(za), ib = __builtin_amdgcn_rcpf(zb);
+                        Xa = xa * ia;
+                        Ya = ya * ia;
+                        const float Xb = xb * ib, Yb = yb * ib;
                         const float m2 = fmaxf(1.0f + Xa * Xa + Ya * Ya, 1.0f + Xb * Xb + Yb * Yb);
-                        const float rho = rr * sqrtf(m2) / zr;
+                        const float rho = rr * __builtin_amdgcn_sqrtf(m2) * __builtin_amdgcn_rcpf(zr);
                         const float rs = rho * (1.0f + 0x1p-12f) +
                                          0x1p-18f * (1.0f + fmaxf(fabsf(Xa), fabsf(Xb)) + fmaxf(fabsf(Ya), fabsf(Yb)));
                         rho2 = rs * rs;
