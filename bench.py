@@ -584,10 +584,21 @@ def codec(sp, torch, synth, sph, bvh, src, dst, opts, reps):
                                   lambda: sp.decode_samples(pos, col, sph.count, synth.BOX_LO, synth.BOX_SIZE, ru,
                                                             half=True, out=dec)]) for _ in range(reps)])
     img, _ = sp.trace(bvh, sph, dst, opts)
-    dimg, _ = sp.trace(sp.build_bvh(dec), dec, dst, opts)
+    dbvh = sp.build_bvh(dec)
+    dimg, _ = sp.trace(dbvh, dec, dst, opts)
     diff = (img - dimg).abs()
     n = sph.n()
+    # decode then build, against the build that decodes the samples in its first kernel
+    fused, fbvh = sp.build_bvh_from_samples(pos, col, sph.count, synth.BOX_LO, synth.BOX_SIZE, ru, half=True)
+    tb = np.array([_events(torch, [lambda: sp.decode_samples(pos, col, sph.count, synth.BOX_LO, synth.BOX_SIZE, ru,
+                                                              half=True, out=dec),
+                                   lambda: sp.build_bvh(dec, dbvh),
+                                   lambda: sp.build_bvh_from_samples(pos, col, sph.count, synth.BOX_LO,
+                                                                     synth.BOX_SIZE, ru, half=True, out=fused,
+                                                                     bvh=fbvh)]) for _ in range(reps)])
     return {"spheres": n, "bytes_per_sample": 12, "bytes_per_sample_unpacked": 24,
+            "decode_then_build_ms": round(float(np.median(tb[:, 0] + tb[:, 1])), 4),
+            "build_from_samples_ms": round(float(np.median(tb[:, 2])), 4),
             "encode_ms": round(float(np.median(t[:, 0])), 4), "decode_ms": round(float(np.median(t[:, 1])), 4),
             "image_mean_abs_change": round(float(diff.mean()), 6), "image_max_abs_change": round(float(diff.max()), 4)}
 

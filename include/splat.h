@@ -402,6 +402,23 @@ int splat_unproject_policy(const splat_camera *src, const float *rgba_premul, co
  *   ws  device, >= splat_workspace_bytes(SPLAT_OP_BUILD, bvh->capacity, 0, 0)
  *   sph->capacity <= bvh->capacity (SPLAT_ENOSPC otherwise)
  */
+/*
+ * The build over received wire samples (Sec. 4.1: the client builds its LBVH
+ * over the samples the server sent): decodes min(*count, out->capacity)
+ * samples into the sphere set `out` inside the build's first kernel, which
+ * reads the centres for the scene bounds anyway, then builds as
+ * splat_build_bvh.  The path thus reads the 12-byte samples once instead of
+ * a decode pass writing 24-byte spheres that the build then reads again.
+ * Equal, bit for bit (spheres, count and BVH), to splat_decode_samples
+ * followed by splat_build_bvh.
+ *   pos, rgba, count, codec  as for splat_decode_samples
+ *   out   a sphere set without axis; out->capacity <= bvh->capacity
+ *   ws    device, >= splat_workspace_bytes(SPLAT_OP_BUILD, out->capacity, 0, 0)
+ */
+int splat_build_bvh_from_samples(const uint64_t *pos, const uint32_t *rgba, const uint32_t *count,
+                                 const splat_codec *codec, const splat_spheres *out, const splat_bvh *bvh, void *ws,
+                                 size_t ws_bytes, void *stream);
+
 int splat_build_bvh(const splat_spheres *sph, const splat_bvh *bvh, int32_t refit_only, void *ws, size_t ws_bytes,
                     void *stream);
 

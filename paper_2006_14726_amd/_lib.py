@@ -21,7 +21,7 @@ SPLAT_OP_UNPROJECT, SPLAT_OP_BUILD, SPLAT_OP_TRACE, SPLAT_OP_BACKWARD, SPLAT_OP_
 EXPORTS = ["splat_workspace_bytes", "splat_bvh_bytes", "splat_raymarch", "splat_encode_samples",
            "splat_decode_samples", "splat_accumulate", "splat_unproject", "splat_unproject_policy", "splat_build_bvh", "splat_trace", "splat_trace_backward",
            "splat_trace_batched", "splat_last_error", "splat_version", "splat_trace_noalloc",
-           "splat_trace_noalloc_max_bytes", "splat_bvh_status_word"]
+           "splat_trace_noalloc_max_bytes", "splat_bvh_status_word", "splat_build_bvh_from_samples"]
 
 _P = ctypes.c_void_p
 
@@ -130,6 +130,9 @@ def load() -> ctypes.CDLL:
         lib.splat_encode_samples.argtypes = [ctypes.POINTER(splat_spheres), ctypes.POINTER(splat_codec), _P, _P, _P]
         lib.splat_decode_samples.argtypes = [_P, _P, _P, ctypes.POINTER(splat_codec), ctypes.POINTER(splat_spheres),
                                              _P]
+        lib.splat_build_bvh_from_samples.argtypes = [_P, _P, _P, ctypes.POINTER(splat_codec),
+                                                     ctypes.POINTER(splat_spheres), ctypes.POINTER(splat_bvh), _P,
+                                                     ctypes.c_size_t, _P]
         lib.splat_accumulate.argtypes = [ctypes.POINTER(splat_spheres), ctypes.POINTER(splat_spheres), _P,
                                          ctypes.POINTER(splat_accum_opts), ctypes.POINTER(splat_spheres), _P, _P,
                                          ctypes.c_size_t, _P]

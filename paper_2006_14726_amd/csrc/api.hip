@@ -350,6 +350,26 @@ int splat_build_bvh(const splat_spheres *sph, const splat_bvh *bvh, int32_t refi
                       "build launch");
 }
 
+int splat_build_bvh_from_samples(const uint64_t *pos, const uint32_t *rgba, const uint32_t *count,
+                                 const splat_codec *codec, const splat_spheres *out, const splat_bvh *bvh, void *ws,
+                                 size_t ws_bytes, void *stream)
+{
+    int rc;
+    if (!pos || !rgba || !count) return fail(SPLAT_EINVAL, "pos/rgba/count is NULL");
+    if ((rc = check_spheres(out, true))) return rc;
+    if (out->axis) return fail(SPLAT_EUNSUPPORTED, "the sample codec takes sphere sets (no axis)");
+    if ((rc = check_codec(codec))) return rc;
+    if ((rc = check_bvh(bvh))) return rc;
+    if (out->capacity > bvh->capacity)
+        return fail(SPLAT_ENOSPC, "sphere capacity %u exceeds bvh capacity %u", out->capacity, bvh->capacity);
+    const size_t need = BuildLayout(out->capacity).total;
+    if (!ws || ws_bytes < need) return fail(SPLAT_ENOSPC, "build workspace needs %zu bytes", need);
+    if ((rc = check_device())) return rc;
+    const SampleSource src = {pos, rgba, count, *codec};
+    return hip_status(launch_build(*out, *bvh, false, ws, static_cast<hipStream_t>(stream), &src),
+                      "build launch");
+}
+
 static int trace_common(const splat_bvh *bvh, const splat_spheres *sph, const splat_camera *cam,
                         const splat_trace_opts *opts, TraceArgs &a)
 {

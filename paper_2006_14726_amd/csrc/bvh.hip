@@ -17,12 +17,13 @@
 //
 // All sizes are read from device memory (the sphere count), so the sequence
 // can be captured in a HIP graph.
+#include "codec.h"
 #include "common.h"
 #include "kernels.h"
 
 namespace splat {
 
-constexpr int kBoundsBlocks = 256;
+constexpr int kBoundsBlocks = 1024;
 
 __device__ inline float wave_min(float v)
 {
@@ -37,19 +38,32 @@ __device__ inline float wave_max(float v)
 
 // Block partials of the centre box.  The first thread also sets the header's
 // sphere count and empties the list of refit entries of the new hierarchy.
+// DECODE: the spheres come from wire samples, decoded here into the set (as
+// splat_decode_samples does) while their centres are read for the bounds.
+template <bool DECODE>
 __global__ void __launch_bounds__(256)
 k_bounds_partial(const float4 *__restrict__ cr, const uint32_t *__restrict__ count, uint32_t cap,
-                 float *__restrict__ partial, BvhHeader *__restrict__ hdr)
+                 float *__restrict__ partial, BvhHeader *__restrict__ hdr, SampleSource src, float4 *__restrict__ out_cr,
+                 void *__restrict__ out_rgba, int half, uint32_t *__restrict__ out_count)
 {
-    const uint32_t n = min(*count, cap);
+    const uint32_t n = min(*(DECODE ? src.count : count), cap);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         hdr->n = n;
         hdr->n_entry = 0u;
         hdr->status = 0u;
+        if (DECODE) *out_count = n;
     }
     float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
-        const float4 c = cr[i];
+        float4 c;
+        if constexpr (DECODE) {
+            c = decode_position(src.pos[i], src.codec.box_lo[0], src.codec.box_lo[1], src.codec.box_lo[2],
+                                src.codec.box_size, src.codec.r_unit);
+            out_cr[i] = c;
+            decode_colour(src.col[i], out_rgba, half, i);
+        } else {
+            c = cr[i];
+        }
         lo[0] = fminf(lo[0], c.x); lo[1] = fminf(lo[1], c.y); lo[2] = fminf(lo[2], c.z);
         hi[0] = fmaxf(hi[0], c.x); hi[1] = fmaxf(hi[1], c.y); hi[2] = fmaxf(hi[2], c.z);
     }
@@ -806,7 +820,8 @@ __global__ void k_header_count(const uint32_t *__restrict__ count, uint32_t cap,
     }
 }
 
-hipError_t launch_build(const splat_spheres &sph, const splat_bvh &bvh, bool refit_only, void *ws, hipStream_t s)
+hipError_t launch_build(const splat_spheres &sph, const splat_bvh &bvh, bool refit_only, void *ws, hipStream_t s,
+                        const SampleSource *samples)
 {
     const uint32_t cap = sph.capacity;
     const BvhLayout L(bvh.capacity);
@@ -833,7 +848,12 @@ hipError_t launch_build(const splat_spheres &sph, const splat_bvh &bvh, bool ref
         uint32_t *hist = reinterpret_cast<uint32_t *>(w + B.hist);
         uint32_t *totals = reinterpret_cast<uint32_t *>(w + B.totals);
         float *partial = reinterpret_cast<float *>(w + B.partial);
-        hipLaunchKernelGGL(k_bounds_partial, dim3(kBoundsBlocks), dim3(256), 0, s, cr, sph.count, cap, partial, hdr);
+        if (samples)
+            hipLaunchKernelGGL(k_bounds_partial<true>, dim3(kBoundsBlocks), dim3(256), 0, s, cr, sph.count, cap, partial,
+                               hdr, *samples, const_cast<float4 *>(cr), sph.rgba, half, sph.count);
+        else
+            hipLaunchKernelGGL(k_bounds_partial<false>, dim3(kBoundsBlocks), dim3(256), 0, s, cr, sph.count, cap,
+                               partial, hdr, SampleSource{}, nullptr, nullptr, half, nullptr);
         hipLaunchKernelGGL(k_morton, dim3(B.tiles), dim3(kSortBlock), 0, s, cr, sph.count, cap, partial, hdr, ka, va,
                            hist, B.tiles);
         for (int shift = 0; shift < kMortonBits; shift += kSortBits) {

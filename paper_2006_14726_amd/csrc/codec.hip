@@ -12,6 +12,7 @@
 // One thread per sample; all arithmetic in double, rounded once to float on
 // decode.  12 bytes per sample on the wire instead of 24 (float centre and
 // radius + half colour).
+#include "codec.h"
 #include "common.h"
 #include "kernels.h"
 
@@ -67,22 +68,8 @@ k_decode(const uint64_t *__restrict__ pos, const uint32_t *__restrict__ col, con
     const uint32_t i = blockIdx.x * kCodecBlock + threadIdx.x;
     if (i == 0) *out_count = n;
     if (i >= n) return;
-    const uint64_t w = pos[i];
-    const double step = size / 262144.0;
-    const double x = lo0 + ((double)(w & 0x3ffffu) + 0.5) * step;
-    const double y = lo1 + ((double)((w >> 18) & 0x3ffffu) + 0.5) * step;
-    const double z = lo2 + ((double)((w >> 36) & 0x3ffffu) + 0.5) * step;
-    const double r = r_unit * exp2(((double)(w >> 54) - 512.0) / 64.0);
-    cr[i] = make_float4((float)x, (float)y, (float)z, (float)r);
-    const uint32_t c = col[i];
-    const double k[4] = {(double)(c & 0xffu) / 255.0, (double)((c >> 8) & 0xffu) / 255.0,
-                         (double)((c >> 16) & 0xffu) / 255.0, (double)(c >> 24) / 255.0};
-    if (half) {
-        reinterpret_cast<ushort4 *>(rgba)[i] =
-            make_ushort4(half_bits_rne(k[0]), half_bits_rne(k[1]), half_bits_rne(k[2]), half_bits_rne(k[3]));
-    } else {
-        reinterpret_cast<float4 *>(rgba)[i] = make_float4((float)k[0], (float)k[1], (float)k[2], (float)k[3]);
-    }
+    cr[i] = decode_position(pos[i], lo0, lo1, lo2, size, r_unit);
+    decode_colour(col[i], rgba, half, i);
 }
 
 hipError_t launch_encode(const splat_spheres &sph, const splat_codec &c, uint64_t *pos, uint32_t *col,

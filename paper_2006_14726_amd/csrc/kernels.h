@@ -51,8 +51,16 @@ hipError_t launch_accumulate(const splat_spheres &frame, const splat_spheres *hi
 hipError_t launch_unproject(const Cam &cam, const float *rgba, const float *depth, const float *interval,
                             const splat_radius_policy &policy, const splat_spheres &out, void *ws, hipStream_t s);
 
+// Wire samples that a build decodes into its sphere set as it reads them.
+struct SampleSource {
+    const uint64_t *pos;
+    const uint32_t *col;
+    const uint32_t *count;
+    splat_codec codec;
+};
+
 hipError_t launch_build(const splat_spheres &sph, const splat_bvh &bvh, bool refit_only, void *ws,
-                        hipStream_t s);
+                        hipStream_t s, const SampleSource *samples = nullptr);
 
 hipError_t launch_trace(const TraceArgs &a, bool backward, void *ws, hipStream_t s, hipEvent_t ev_begin,
                         hipEvent_t ev_end);

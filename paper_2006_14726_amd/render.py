@@ -195,6 +195,27 @@ def decode_samples(pos: torch.Tensor, col: torch.Tensor, count: torch.Tensor, bo
     return out
 
 
+def build_bvh_from_samples(pos: torch.Tensor, col: torch.Tensor, count: torch.Tensor, box_lo, box_size: float,
+                           r_unit: float, half: bool = True, out: Spheres | None = None, bvh: BVH | None = None,
+                           ws: torch.Tensor | None = None):
+    """Decode wire samples into a sphere set and build its LBVH in one call (splat_build_bvh_from_samples):
+    the same spheres and BVH as decode_samples followed by build_bvh.  Returns (Spheres, BVH)."""
+    _require_cuda(pos, "pos", torch.int64)
+    _require_cuda(col, "col", torch.int32)
+    _require_cuda(count, "count", torch.int32)
+    if out is None:
+        out = alloc_spheres(int(pos.numel()), pos.device, half)
+    if bvh is None:
+        bvh = alloc_bvh(out.capacity, pos.device)
+    lib = _lib.load()
+    need = lib.splat_workspace_bytes(_lib.SPLAT_OP_BUILD, out.capacity, 0, 0)
+    ws = _own_ws(ws, need, pos.device, "build")
+    c, s, b = _codec(box_lo, box_size, r_unit), out.struct(), bvh.struct()
+    _lib.check(lib.splat_build_bvh_from_samples(_ptr(pos), _ptr(col), _ptr(count), ctypes.byref(c), ctypes.byref(s),
+                                                ctypes.byref(b), _ptr(ws), ws.numel(), _stream()))
+    return out, bvh
+
+
 def accumulate(frame: Spheres, history: Spheres | None, history_age: torch.Tensor | None, box_lo, box_size: float,
                grid: int, max_age: int, out: Spheres | None = None, out_age: torch.Tensor | None = None,
                ws: torch.Tensor | None = None):

@@ -7,7 +7,7 @@ import torch
 
 import oracle
 import synth
-from helpers import assert_parity, compare
+from helpers import assert_parity, bvh_core, bvh_layout, compare
 
 pytestmark = pytest.mark.gpu
 LO, SIZE = synth.BOX_LO, synth.BOX_SIZE
@@ -99,3 +99,36 @@ def test_codec_rejects_bad_parameters(sp, client):
         sp.encode_samples(s, LO, 0.0, 1e-3)
     with pytest.raises(sp.SplatError):
         sp.encode_samples(s, LO, SIZE, -1.0)
+
+
+@pytest.mark.parametrize("half_out", [True, False])
+def test_build_from_samples_equals_decode_then_build(sp, client, half_out):
+    """The build that decodes the wire samples in its first kernel: the same
+    spheres, count and BVH bytes as decode followed by build, and the same image."""
+    s, src, dst, cr, k16 = client
+    ru = r_unit_of(src)
+    pos, col = sp.encode_samples(s, LO, SIZE, ru)
+    print(f"build from samples half={half_out}", flush=True)
+    d = sp.decode_samples(pos, col, s.count, LO, SIZE, ru, half=half_out)
+    bvh = sp.build_bvh(d)
+    f, fbvh = sp.build_bvh_from_samples(pos, col, s.count, LO, SIZE, ru, half=half_out)
+    torch.cuda.synchronize()
+    n = d.n()
+    assert f.n() == n == s.n()
+    assert torch.equal(f.centre_radius[:n], d.centre_radius[:n])
+    assert torch.equal(f.rgba[:n].view(torch.int16) if half_out else f.rgba[:n], d.rgba[:n].view(torch.int16)
+                       if half_out else d.rgba[:n])
+    assert torch.equal(bvh_core(fbvh.mem, fbvh.capacity), bvh_core(bvh.mem, bvh.capacity)), "hierarchies differ"
+    w0 = bvh_layout(bvh.capacity)["wide"]
+    w1 = w0 + max(n - 1, 1) * 128
+    assert torch.equal(fbvh.mem[w0:w1], bvh.mem[w0:w1]), "wide nodes differ"
+    a, ha = sp.trace(bvh, d, dst)
+    b, hb = sp.trace(fbvh, f, dst)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b) and torch.equal(ha, hb)
+    # a count below the capacity: only that many samples are decoded
+    few = torch.tensor([1000], dtype=torch.int32, device="cuda:0")
+    g, gbvh = sp.build_bvh_from_samples(pos, col, few, LO, SIZE, ru, half=half_out)
+    torch.cuda.synchronize()
+    assert g.n() == 1000 and torch.equal(g.centre_radius[:1000], d.centre_radius[:1000])
+    assert gbvh.status() == 0
