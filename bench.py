@@ -405,6 +405,7 @@ def batched(sp, torch, synth, dev, n_frames):
             "graph_ms": round(graph * 1e3, 3), "sequential_ms": round(seq * 1e3, 3),
             "graph_mrays_s": round(r.rays / graph / 1e6, 1), "sequential_mrays_s": round(r.rays / seq / 1e6, 1),
             "bit_identical": bool(same), "tuned": {k: tuned[k] for k in ("kbuf", "tile", "walk", "waves")},
+            "build_lanes": len(r.lanes),
             "input_generation_s": round(gen_s, 1)}
 
 

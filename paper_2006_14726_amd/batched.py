@@ -1,7 +1,9 @@
 """Many client frames, each with several target views, in one trace launch.
 
-Every frame is unprojected and its LBVH built with the plain entry points;
-then every (frame, view) job is traced by ONE splat_trace_batched launch:
+Every frame is unprojected and its LBVH built with the plain entry points,
+the frames spread over a few streams (build lanes) so that the small frames'
+builds, each a chain of short dependent kernels, run side by side; then every
+(frame, view) job is traced by ONE splat_trace_batched launch:
 persistent waves that pull tiles from an atomic counter until the batch is
 drained, or (waves = GRID) one workgroup per (job, tile).
 The whole sequence can be captured once in a HIP graph and replayed.
@@ -33,7 +35,7 @@ class BatchedRenderer:
     """Owns the device buffers of a batch; `run()` enqueues the whole batch."""
 
     def __init__(self, frames: list[Frame], radius_scale: float = 1.0, half: bool = True,
-                 opts: TraceOptions | None = None, waves: int = 0):
+                 opts: TraceOptions | None = None, waves: int = 0, build_streams: int = 4):
         self.frames = frames
         self.radius_scale = float(radius_scale)
         self.half = half
@@ -60,11 +62,34 @@ class BatchedRenderer:
                               device=dev)
         # workspaces of its own, sized for the largest frame: a captured graph
         # keeps their addresses, so no other caller may replace or free them
-        self.ws_unproject = torch.empty(max(256, *(lib.splat_workspace_bytes(_lib.SPLAT_OP_UNPROJECT, 0, fr.src_cam.width,
-                                                                      fr.src_cam.height) for fr in frames)),
-                                        dtype=torch.uint8, device=dev)
-        self.ws_build = torch.empty(max(256, *(lib.splat_workspace_bytes(_lib.SPLAT_OP_BUILD, s.capacity, 0, 0)
-                                                 for s in self.spheres)), dtype=torch.uint8, device=dev)
+        # Build lanes: frames assigned largest first to the least loaded lane
+        # (by source pixels); each lane has a stream and unproject and build
+        # workspaces of its own, sized for its largest frame.
+        n_lanes = max(1, min(int(build_streams), len(frames)))
+        self.lanes: list[list[int]] = [[] for _ in range(n_lanes)]
+        load = [0] * n_lanes
+        for fi in sorted(range(len(frames)), key=lambda i: -self.spheres[i].capacity):
+            lane = min(range(n_lanes), key=lambda k: (load[k], k))
+            self.lanes[lane].append(fi)
+            load[lane] += self.spheres[fi].capacity
+        self.streams = [torch.cuda.Stream(device=dev) for _ in range(n_lanes)] if n_lanes > 1 else []
+        self.ws_unproject, self.ws_build = [], []
+        for idxs in self.lanes:
+            self.ws_unproject.append(torch.empty(max(256, *(lib.splat_workspace_bytes(
+                _lib.SPLAT_OP_UNPROJECT, 0, frames[i].src_cam.width, frames[i].src_cam.height) for i in idxs)),
+                dtype=torch.uint8, device=dev))
+            self.ws_build.append(torch.empty(max(256, *(lib.splat_workspace_bytes(
+                _lib.SPLAT_OP_BUILD, self.spheres[i].capacity, 0, 0) for i in idxs)), dtype=torch.uint8, device=dev))
+        # buffers written on a lane stream are not reused by the allocator
+        # before that stream's work at their release has finished
+        for lane, st in enumerate(self.streams):
+            for t in (self.ws_unproject[lane], self.ws_build[lane]):
+                t.record_stream(st)
+            for fi in self.lanes[lane]:
+                s = self.spheres[fi]
+                for t in (s.centre_radius, s.rgba, s.count, s.src_index, s.axis, self.bvhs[fi].mem):
+                    if t is not None:
+                        t.record_stream(st)
         self.ws_trace = torch.empty(max(256, *(lib.splat_workspace_bytes(_lib.SPLAT_OP_TRACE, 0, c.width, c.height)
                                                  for fr in frames for c in fr.dst_cams)), dtype=torch.uint8, device=dev)
         self.graph = None
@@ -103,11 +128,27 @@ class BatchedRenderer:
         self.job_table = torch.from_numpy(raw.copy()).to(dev)
         self.tile_offsets = torch.tensor(np.array(offsets[:-1], dtype=np.uint32).view(np.int32), device=dev)
 
+    def _prepare_lane(self, lane: int) -> None:
+        for fi in self.lanes[lane]:
+            fr, s = self.frames[fi], self.spheres[fi]
+            unproject(fr.src_cam, fr.rgba, fr.depth, self.radius_scale, self.half, out=s, ws=self.ws_unproject[lane])
+            build_bvh(s, self.bvhs[fi], ws=self.ws_build[lane])
+
     def prepare(self):
-        """Unproject and build every frame (plain launches)."""
-        for fr, s, b in zip(self.frames, self.spheres, self.bvhs):
-            unproject(fr.src_cam, fr.rgba, fr.depth, self.radius_scale, self.half, out=s, ws=self.ws_unproject)
-            build_bvh(s, b, ws=self.ws_build)
+        """Unproject and build every frame (plain launches).  With several
+        lanes each lane's stream waits for the work already on the current
+        stream, and the current stream waits for every lane: under capture
+        the lanes become parallel branches of the graph."""
+        if not self.streams:
+            self._prepare_lane(0)
+            return
+        cur = torch.cuda.current_stream(self.device)
+        for lane, st in enumerate(self.streams):
+            st.wait_stream(cur)
+            with torch.cuda.stream(st):
+                self._prepare_lane(lane)
+        for st in self.streams:
+            cur.wait_stream(st)
 
     def trace_batched(self):
         """Every job in one persistent launch (splat_trace_batched)."""

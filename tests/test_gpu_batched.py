@@ -71,6 +71,36 @@ def test_batched_equals_sequential(sp, small_batch, kbuf, tile, waves, walk):
     assert sum(int(h.sum()) for views in ref for _, h in views) > 100
 
 
+def test_build_lanes_match_one_stream(sp, small_batch):
+    """Frames built on several streams (eager and as parallel graph branches)
+    give the same hierarchies and outputs as the builds on one stream."""
+    one = make_renderer(sp, small_batch, half=True, build_streams=1)
+    assert len(one.lanes) == 1 and not one.streams
+    one.run()
+    torch.cuda.synchronize()
+    ref = snapshot(one)
+    four = make_renderer(sp, small_batch, half=True, build_streams=4)
+    assert len(four.lanes) == 4 and sorted(i for lane in four.lanes for i in lane) == list(range(len(small_batch)))
+    four.run()
+    torch.cuda.synchronize()
+    assert_same(snapshot(four), ref)
+    for a, b in zip(one.bvhs, four.bvhs):
+        assert torch.equal(a.mem[:64], b.mem[:64])  # header: root, counts, scene box
+    four.capture()
+    for it in range(3):
+        for views in four.outputs:
+            for o, h in views:
+                o.fill_(float(it + 2))
+                h.fill_(-1)
+        for s in four.spheres:
+            s.centre_radius.fill_(float("nan"))
+        torch.cuda.synchronize()
+        four.replay()
+        torch.cuda.synchronize()
+        assert_same(snapshot(four), ref)
+        _ = torch.ones(1000, device="cuda:0").sum().item()
+
+
 def test_graph_replay_matches_eager(sp, small_batch):
     r = make_renderer(sp, small_batch, half=True)
     r.run()
