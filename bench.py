@@ -597,7 +597,31 @@ def codec(sp, torch, synth, sph, bvh, src, dst, opts, reps):
                                    lambda: sp.build_bvh_from_samples(pos, col, sph.count, synth.BOX_LO,
                                                                      synth.BOX_SIZE, ru, half=True, out=fused,
                                                                      bvh=fbvh)]) for _ in range(reps)])
+    # algorithmic bytes per call: encode reads 16 B of centre and radius and
+    # 8 B of half colour and writes the 12-byte sample; decode the reverse.
+    # An eager call of a few microseconds waits on the host, so the device
+    # time per call comes from replays of a captured graph of 20 calls.
+    nbytes = 36 * n
+
+    def device_ms(fn, per=20):
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            for _ in range(per):
+                fn()
+        g.replay()
+        torch.cuda.synchronize()
+        return float(np.median([_events(torch, [g.replay])[0] / per for _ in range(max(reps // 4, 3))]))
+
+    enc_ms = device_ms(lambda: sp.encode_samples(sph, synth.BOX_LO, synth.BOX_SIZE, ru))
+    dec_ms = device_ms(lambda: sp.decode_samples(pos, col, sph.count, synth.BOX_LO, synth.BOX_SIZE, ru, half=True,
+                                                 out=dec))
     return {"spheres": n, "bytes_per_sample": 12, "bytes_per_sample_unpacked": 24,
+            "algorithmic_bytes_per_call": nbytes,
+            "encode_device_ms": round(enc_ms, 4), "decode_device_ms": round(dec_ms, 4),
+            "encode_gb_s": round(nbytes / enc_ms / 1e6, 1), "decode_gb_s": round(nbytes / dec_ms / 1e6, 1),
+            "encode_frac_of_hbm_peak": round(nbytes / enc_ms / 1e6 / 8000.0, 4),
+            "decode_frac_of_hbm_peak": round(nbytes / dec_ms / 1e6 / 8000.0, 4),
             "decode_then_build_ms": round(float(np.median(tb[:, 0] + tb[:, 1])), 4),
             "build_from_samples_ms": round(float(np.median(tb[:, 2])), 4),
             "encode_ms": round(float(np.median(t[:, 0])), 4), "decode_ms": round(float(np.median(t[:, 1])), 4),
