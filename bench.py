@@ -181,6 +181,28 @@ def main():
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) / args.steps
 
+    # the same step captured once in a HIP graph and replayed (one host
+    # submission per step instead of the three calls' launches); its image
+    # must equal the eager step's bit for bit
+    eager_img, eager_hits = out.clone(), hits.clone()
+    step_graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(step_graph):
+        step()
+    out.fill_(-1.0)
+    hits.fill_(-1)
+    step_graph.replay()
+    torch.cuda.synchronize()
+    graph_same = bool(torch.equal(out, eager_img) and torch.equal(hits, eager_hits))
+    for _ in range(args.warmup):
+        step_graph.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step_graph.replay()
+    torch.cuda.synchronize()
+    graph_wall = (time.perf_counter() - t0) / args.steps
+    del eager_img, eager_hits
+
     # per-stage device time (events on the stream the kernels are launched on)
     stage = np.zeros((args.steps, 3))
     for i in range(args.steps):
@@ -253,6 +275,8 @@ def main():
         "stages_p10_p90_ms": {k: [round(float(np.percentile(stage[:, i], 10)), 4),
                                   round(float(np.percentile(stage[:, i], 90)), 4)]
                               for i, k in enumerate(("unproject", "build", "trace"))},
+        "graph_step": {"ms_per_step": round(graph_wall * 1e3, 4), "mrays_s": round(P / graph_wall / 1e6, 3),
+                       "bit_identical": graph_same},
         "trace_only_mrays_s": round(P / (call_ms * 1e-3) / 1e6, 2),
         "trace_call_ms": round(call_ms, 4),
         "trace_cold_ms": round(float(np.median(cold)), 4),
